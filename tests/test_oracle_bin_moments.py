@@ -1,0 +1,132 @@
+"""Pins of the oracle's binning, stable sort and central moments (CPU)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_15622_amd import inputs as I
+
+
+@pytest.mark.parametrize("geom", ["couette1d", "cavity2d"])
+def test_keys_match_floor_brute_force(geom):
+    w = I.couette(ncell=37) if geom == "couette1d" else I.cavity(ncell=23, precision="f32")
+    s = I.scattered_state(w, 50000, seed=3, face_hits=0.1)
+    k = O.keys(w, s["x"], s["y"])
+    inv = 1.0 / w["dx"]
+    kx = np.clip(np.floor((s["x"] - w["x0"]) * inv), 0, w["nx"] - 1).astype(np.int64)
+    if geom == "cavity2d":
+        ky = np.clip(np.floor((s["y"] - w["y0"]) * (1.0 / w["dy"])), 0, w["ny"] - 1).astype(np.int64)
+    else:
+        ky = 0
+    np.testing.assert_array_equal(k, ky * w["nx"] + kx)
+    # a particle on an interior face belongs to the upper cell; on the far wall to the last
+    xf = np.array([w["x0"] + 3 * w["dx"], w["x0"] + w["lx"]])
+    kf = O.keys(w, xf, np.full(2, w["y0"]))
+    assert kf[0] == 3 and kf[1] == w["nx"] - 1
+
+
+def test_bin_is_stable_counting_sort():
+    rng = np.random.default_rng(0)
+    for ncell, n in [(1, 0), (5, 1), (100, 10000), (4096, 3000)]:
+        key = rng.integers(0, ncell, n).astype(np.int32)
+        perm, off = O.bin_particles(ncell, key)
+        np.testing.assert_array_equal(perm, np.argsort(key, kind="stable"))
+        np.testing.assert_array_equal(off, np.searchsorted(np.sort(key), np.arange(ncell + 1)))
+
+
+def _brute_moments(v):
+    n = v.shape[0]
+    U = v.mean(axis=0)
+    c = v - U
+    c2 = (c**2).sum(axis=1)
+    P = np.einsum("pi,pj->ij", c, c) / n
+    T = np.einsum("pi,pj,pk->ijk", c, c, c) / n
+    R = np.einsum("pi,pj,p->ij", c, c, c2) / n
+    W = np.einsum("pi,p->i", c, c2**2) / n
+    H = (c2**3).mean()
+    return U, P, T, R, W, H
+
+
+def _unpack(m):
+    s2 = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    s3 = [(0, 0, 0), (0, 0, 1), (0, 0, 2), (0, 1, 1), (0, 1, 2), (0, 2, 2), (1, 1, 1), (1, 1, 2),
+          (1, 2, 2), (2, 2, 2)]
+    P = np.zeros((3, 3)); R = np.zeros((3, 3)); T = np.zeros((3, 3, 3))
+    for q, (i, j) in enumerate(s2):
+        P[i, j] = P[j, i] = m[5 + q]
+        R[i, j] = R[j, i] = m[21 + q]
+    import itertools
+    for q, (i, j, k) in enumerate(s3):
+        for a, b, c in set(itertools.permutations((i, j, k))):
+            T[a, b, c] = m[11 + q]
+    return m[1:4], P, T, R, m[27:30], m[30]
+
+
+def test_moments_match_brute_force_fp64():
+    counts = [0, 1, 2, 7, 64, 65, 500]
+    vx, vy, vz, off = I.mixture_cells(counts, seed=4)
+    mom = O.moments(off, vx, vy, vz)
+    v = np.stack([vx, vy, vz], axis=1)
+    for c, n in enumerate(counts):
+        assert mom[c, 0] == n
+        if n == 0:
+            assert np.all(mom[c] == 0)
+            continue
+        U, P, T, R, W, H = _brute_moments(v[off[c]:off[c + 1]])
+        U2, P2, T2, R2, W2, H2 = _unpack(mom[c])
+        sc = np.sqrt(max(np.trace(P) / 3, 1e-300))
+        np.testing.assert_allclose(U2, U, rtol=1e-13, atol=1e-12 * sc)
+        np.testing.assert_allclose(P2, P, rtol=1e-11, atol=1e-12 * sc**2)
+        np.testing.assert_allclose(T2, T, rtol=1e-10, atol=1e-11 * sc**3)
+        np.testing.assert_allclose(R2, R, rtol=1e-10, atol=1e-11 * sc**4)
+        np.testing.assert_allclose(W2, W, rtol=1e-10, atol=1e-11 * sc**5)
+        assert H2 == pytest.approx(H, rel=1e-10, abs=1e-11 * sc**6)
+        assert mom[c, 4] == pytest.approx(np.trace(P) / 3, rel=1e-13, abs=1e-300)
+
+
+def test_moments_exact_rational_tiny_cells():
+    rng = np.random.default_rng(9)
+    for n in (2, 3, 5, 8):
+        v = rng.integers(-4, 5, (n, 3))
+        vf = v.astype(np.float64)
+        off = np.array([0, n], dtype=np.int32)
+        m = O.moments(off, vf[:, 0], vf[:, 1], vf[:, 2])[0]
+        U = [Fraction(int(v[:, i].sum()), n) for i in range(3)]
+        c = [[Fraction(int(v[p, i])) - U[i] for i in range(3)] for p in range(n)]
+        c2 = [sum(ci * ci for ci in cp) for cp in c]
+        ex = {}
+        ex["P01"] = sum(cp[0] * cp[1] for cp in c) / n
+        ex["T012"] = sum(cp[0] * cp[1] * cp[2] for cp in c) / n
+        ex["T111"] = sum(cp[1] ** 3 for cp in c) / n
+        ex["R22"] = sum(cp[2] * cp[2] * c2[p] for p, cp in enumerate(c)) / n
+        ex["W0"] = sum(cp[0] * c2[p] ** 2 for p, cp in enumerate(c)) / n
+        ex["H"] = sum(x**3 for x in c2) / n
+        got = {"P01": m[6], "T012": m[15], "T111": m[17], "R22": m[26], "W0": m[27], "H": m[30]}
+        for k in ex:
+            assert got[k] == pytest.approx(float(ex[k]), rel=1e-12, abs=1e-12), k
+
+
+def test_gauss_hermite_cell_gives_maxwellian_moments():
+    th = 1.7e4
+    vx, vy, vz = I.gauss_hermite3_cell(th, drift=(30.0, -5.0, 2.0))
+    m = O.moments(np.array([0, 216], dtype=np.int32), vx, vy, vz)[0]
+    U, P, T, R, W, H = _unpack(m)
+    np.testing.assert_allclose(U, [30.0, -5.0, 2.0], rtol=1e-14)
+    np.testing.assert_allclose(P, th * np.eye(3), atol=1e-9 * th)
+    np.testing.assert_allclose(T, 0.0, atol=1e-9 * th**1.5)
+    np.testing.assert_allclose(R, 5 * th**2 * np.eye(3), atol=1e-9 * th**2)
+    np.testing.assert_allclose(W, 0.0, atol=1e-9 * th**2.5)
+    assert m[4] == pytest.approx(th, rel=1e-13)
+
+
+def test_sample_sums():
+    vx, vy, vz, off = I.mixture_cells([3, 0, 10], seed=2)
+    s = O.sample(off, vx, vy, vz)
+    s = O.sample(off, vx, vy, vz, s)
+    v = np.stack([vx, vy, vz], 1)
+    seg = v[off[2]:off[3]]
+    assert s[2, 0] == 20 and s[1, 0] == 0 and s[0, 13] == 2
+    np.testing.assert_allclose(s[2, 1:4], 2 * seg.sum(0), rtol=1e-13)
+    np.testing.assert_allclose(s[2, 4], 2 * (seg[:, 0] ** 2).sum(), rtol=1e-13)
+    np.testing.assert_allclose(s[2, 10:13], 2 * (seg * (seg**2).sum(1)[:, None]).sum(0), rtol=1e-12)

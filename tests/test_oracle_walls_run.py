@@ -1,0 +1,89 @@
+"""Pins of the oracle's free flight, diffuse walls and the full loop (CPU)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import oracle as O
+from paper_2606_15622_amd import inputs as I
+
+
+def test_diffuse_reemission_distribution_ks():
+    """Particles leaving through the x = 0 wall of the Couette channel are re-emitted
+    with a Rayleigh normal speed and Gaussian tangential velocities about the wall's."""
+    w = I.couette(ncell=10, precision="f64")
+    n = 40000
+    R = I.KB / I.MASS_AR
+    RT = R * w["T_wall"][0]
+    x = np.full(n, 1e-12)
+    vx = np.full(n, -2000.0)
+    vy = np.full(n, 55.0)
+    vz = np.zeros(n)
+    pid = np.arange(n, dtype=np.uint32)
+    x1, _, ux, uy, uz, key = O.move(w, x, None, vx, vy, vz, pid, step=4)
+    assert np.all(ux > 0)
+    assert stats.kstest(ux, lambda v: 1 - np.exp(-v * v / (2 * RT))).pvalue > 1e-3
+    assert stats.kstest((uy - w["u_wall"][0][1]) / math.sqrt(RT), "norm").pvalue > 1e-3
+    assert stats.kstest(uz / math.sqrt(RT), "norm").pvalue > 1e-3
+    # the remaining flight time is used: x = u_x * (dt - t_hit)
+    t_hit = 1e-12 / 2000.0
+    np.testing.assert_allclose(x1, ux * (w["dt"] - t_hit), rtol=1e-12)
+    np.testing.assert_array_equal(key, np.minimum((x1 / w["dx"]).astype(int), 9))
+
+
+def test_flight_without_walls_and_corner_bounces():
+    w = I.cavity(ncell=10, precision="f64")
+    dt = w["dt"]
+    x = np.array([5e-5, 1e-7, 1e-7])
+    y = np.array([5e-5, 1e-7, w["ly"] - 1e-7])
+    vx = np.array([100.0, -1e4, -1e4])
+    vy = np.array([-50.0, -1e4, 1e4])
+    vz = np.zeros(3)
+    pid = np.arange(3, dtype=np.uint32)
+    x1, y1, ux, uy, uz, key = O.move(w, x, y, vx, vy, vz, pid, step=0)
+    assert x1[0] == x[0] + vx[0] * dt and y1[0] == y[0] + vy[0] * dt
+    assert ux[0] == 100.0 and uy[0] == -50.0
+    assert np.all((x1 >= 0) & (x1 <= w["lx"]) & (y1 >= 0) & (y1 <= w["ly"]))
+    assert ux[1] > 0 and uy[1] > 0          # reflected off both walls of the corner
+    assert ux[2] > 0 and uy[2] < 0
+
+
+def test_closed_box_equilibrium_and_exact_particle_count():
+    w = I.cavity(ncell=12, ppc=60, lid=0.0, precision="f64", seed=5)
+    s = I.maxwellian_state(w)
+    s["key"] = O.keys(w, s["x"], s["y"])
+    out, mom, rec, st, samp = O.run(w, s, 0, 40, n_skip=10)
+    n = s["x"].shape[0]
+    assert samp[:, 0].sum() == n * 30
+    assert np.all(np.isin(st, [O.OR_OK]))
+    assert np.all((out["x"] >= 0) & (out["x"] <= w["lx"]) & (out["y"] >= 0) & (out["y"] <= w["ly"]))
+    np.testing.assert_array_equal(np.sort(out["pid"]), np.arange(n))
+    R = I.KB / I.MASS_AR
+    T = ((out["vx"] ** 2 + out["vy"] ** 2 + out["vz"] ** 2).mean()) / (3 * R)
+    assert T == pytest.approx(273.0, rel=0.02)
+    assert abs(out["vx"].mean()) < 5.0 and abs(out["vy"].mean()) < 5.0
+
+
+def test_couette_short_run_and_bitwise_resume():
+    w = I.couette(ncell=20, ppc=50, precision="f64", seed=2)
+    s = I.maxwellian_state(w)
+    s["key"] = O.keys(w, s["x"])
+    a, mom_a, _, st_a, _ = O.run(w, s, 0, 30)
+    h, _, _, _, _ = O.run(w, s, 0, 15)
+    b, mom_b, _, _, _ = O.run(w, h, 15, 15)
+    for k in ("x", "vx", "vy", "vz", "pid", "key"):
+        np.testing.assert_array_equal(a[k], b[k])
+    np.testing.assert_array_equal(mom_a, mom_b)
+    assert np.all(st_a == O.OR_OK)
+    # shear develops with the sign of the walls: fluid near x = L moves along +y
+    assert mom_a[-3:, 2].mean() > 10.0 and mom_a[:3, 2].mean() < -10.0
+
+
+def test_f32_storage_rounds_stored_values():
+    w = I.cavity(ncell=8, ppc=20, precision="f32", seed=3)
+    s = I.maxwellian_state(w)
+    s["key"] = O.keys(w, s["x"], s["y"])
+    out, _, _, _, _ = O.run(w, s, 0, 3)
+    for k in ("x", "y", "vx", "vy", "vz"):
+        np.testing.assert_array_equal(out[k], out[k].astype(np.float32).astype(np.float64))
