@@ -1,0 +1,193 @@
+"""Benchmark of the cubic-FP particle step on one MI355X.
+
+Workload (default): the 2-D lid-driven cavity, 100 x 100 cells, 100 particles per cell
+(1e6 particles), FP32 particle storage, FP64 closure, exact closure, nominal Kn 1.0,
+lid 50 m/s, diffuse walls at 273 K.  One step = bin -> moments -> sample -> closure ->
+collide + move: the whole hot path.  Inputs are seeded synthetic states already resident
+in HBM when the timed region starts.
+
+Prints one JSON line: particle-steps/s (value), cell-closures/s, per-entry-point times
+from HIP events on the launch stream, the roofline of the dominant single-kernel entry
+point, the same measured on a scaled cavity (448 x 448 cells, 2e7 particles, beyond the
+256 MB last-level cache), and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--kn", type=float, default=1.0)
+    ap.add_argument("--no-scaled", action="store_true", help="skip the 2e7-particle cavity")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--scaled-steps", type=int, default=20)
+    return ap.parse_args()
+
+
+# algorithmic bytes per launch of each entry point (FP32 2-D particles):
+#   step (collide+move): read x y vx vy vz pid, write x y vx vy vz key = 48 B/particle;
+#                        per cell offsets 8 B, rec 128 B, U and T of mom 104 B
+#   moments:             read vx vy vz = 12 B/particle; per cell offsets 8 B + 256 B out
+#   bin:                 key read twice 8 B, gather read 24 B, write 28 B = 60 B/particle
+#   closure:             256 B in + 128 B + 4 B out per cell
+def alg_bytes(kind, n, nc):
+    return {"step": 48 * n + 240 * nc, "moments": 12 * n + 264 * nc,
+            "bin": 60 * n + 24 * nc, "closure": 388 * nc, "sample": 384 * nc}[kind]
+
+
+class Timed:
+    """Wraps the Context calls with HIP events recorded on the launch stream."""
+
+    def __init__(self, torch, ctx):
+        self.torch = torch
+        self.ctx = ctx
+        self.ev = {}
+
+    def call(self, kind, fn, *a):
+        t = self.torch
+        s, e = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        s.record(t.cuda.current_stream())
+        fn(*a)
+        e.record(t.cuda.current_stream())
+        self.ev.setdefault(kind, []).append((s, e))
+
+    def means_ms(self):
+        return {k: float(np.mean([s.elapsed_time(e) for s, e in v])) for k, v in self.ev.items()}
+
+
+def timed_step(T, sim, s, sample):
+    F = sim.F
+    ctx = sim.ctx
+    T.call("bin", ctx.bin, sim.a, sim.b, sim.offsets)
+    sim.a, sim.b = sim.b, sim.a
+    T.call("moments", ctx.moments, sim.a, sim.offsets, sim.mom)
+    if sample:
+        T.call("sample", ctx.sample, sim.mom, sim.samp)
+    T.call("closure", ctx.closure_solve, sim.mom, sim.rec, sim.status)
+    T.call("step", ctx.step, sim.a, sim.offsets, sim.mom, sim.rec, s, F.STEP_COLLIDE | F.STEP_MOVE)
+
+
+def run_workload(torch, F, I, w, steps, warmup):
+    state = I.maxwellian_state(w)
+    sim = F.Simulation(w, state)
+    sim.F = F
+    n, nc = state["x"].shape[0], I.ncells(w)
+    del state
+    s = 0
+    for _ in range(warmup):
+        sim.step(s, sample=True)
+        s += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step(s, sample=True)
+        s += 1
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    # per-entry-point durations over a second, event-instrumented pass
+    T = Timed(torch, sim.ctx)
+    for _ in range(min(steps, 50)):
+        timed_step(T, sim, s, True)
+        s += 1
+    torch.cuda.synchronize()
+    ms = T.means_ms()
+    kern = {}
+    for k, v in ms.items():
+        gbs = alg_bytes(k, n, nc) / (v * 1e-3) / 1e9
+        kern[k] = {"ms": round(v, 5), "alg_GBps": round(gbs, 1), "alg_bytes": alg_bytes(k, n, nc)}
+    st = sim.status.cpu().numpy()
+    return dict(n=n, nc=nc, t=t, steps=steps, kern=kern, ok_cells=int((st == F.CELL_OK).sum()))
+
+
+def roofline_of(res, kind="step"):
+    k = res["kern"][kind]
+    ach = k["alg_GBps"]
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kind,
+            "alg_bytes_per_launch": k["alg_bytes"], "avg_ms": k["ms"]}
+
+
+def cpu_baseline(I, w):
+    from oracle import oracle as O
+    state = I.maxwellian_state(w)
+    state["key"] = O.keys(w, state["x"], state["y"])
+    nsteps = 50
+    t0 = time.perf_counter()
+    O.run(w, state, 0, nsteps, n_skip=0)
+    t = time.perf_counter() - t0
+    n = state["x"].shape[0]
+    return {"value": round(n * nsteps / t, 1), "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{nsteps} full steps of the same workload ({n} particles, single thread, "
+                      f"{platform.processor() or platform.machine()}, {t:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2606_15622_amd import fpgpu as F
+    from paper_2606_15622_amd import inputs as I
+    F.load()
+    torch.cuda.set_device(0)
+
+    w = I.cavity(kn=args.kn, ncell=100, ppc=100, precision="f32", seed=1)
+    res = run_workload(torch, F, I, w, args.steps, args.warmup)
+    n, nc = res["n"], res["nc"]
+    ms_step = res["t"] / res["steps"] * 1e3
+    pps = n * res["steps"] / res["t"]
+    kern = res["kern"]
+    dominant = max((k for k in kern if k in ("step", "moments", "closure")),
+                   key=lambda k: kern[k]["ms"])
+    out = {
+        "metric": "particle-steps/s (cubic-FP step, exact closure)",
+        "value": round(pps, 1),
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 particles, f64 moments/closure",
+        "data": "synthetic (seeded Maxwellian initial state)",
+        "config": {"workload": f"cavity2d 100x100 cells, 100 particles/cell, Kn {args.kn}, "
+                               f"lid 50 m/s, exact closure", "particles": n, "cells": nc,
+                   "parallelism": "single GPU"},
+        "cell_closures_per_s": round(nc * res["steps"] / res["t"], 1),
+        "closure_kernel_cell_closures_per_s": round(nc / (kern["closure"]["ms"] * 1e-3), 1),
+        "kernels": kern,
+        "roofline": roofline_of(res, dominant),
+    }
+    if not args.no_scaled:
+        ws = I.cavity(kn=args.kn, ncell=448, ppc=100, precision="f32", seed=2)
+        rs = run_workload(torch, F, I, ws, args.scaled_steps, 5)
+        out["scaled"] = {
+            "workload": "cavity2d 448x448 cells, 100 particles/cell (2.0e7 particles)",
+            "value": round(rs["n"] * rs["steps"] / rs["t"], 1), "unit": "particle-steps/s",
+            "ms_per_step": round(rs["t"] / rs["steps"] * 1e3, 4), "kernels": rs["kern"],
+            "roofline_step": roofline_of(rs, "step"), "roofline_moments": roofline_of(rs, "moments"),
+        }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(I, w)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

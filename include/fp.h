@@ -1,0 +1,233 @@
+/*
+ * fp.h -- C ABI of libfpgpu.so: the cubic Fokker-Planck particle step on one MI355X.
+ *
+ * The method is the particle cubic-FP model of Gorji et al. as restated in Roohi,
+ * "Accelerating Kinetic Fokker-Planck Simulations via a GPU-Native Deep Neural Network
+ * Surrogate": every step bins the particles into cells, gathers central velocity
+ * moments per cell, solves the 9x9 moment-matching system for the drift coefficients
+ * (C, Gamma), updates velocities with the mixed Ornstein-Uhlenbeck/Euler scheme and
+ * moves the particles (Algorithm "Baseline Physics Simulation Loop").
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers owned by the caller, on the device that was
+ *     current at fp_init.  The library owns only the context and its scratch memory.
+ *   - Every call is asynchronous on the given HIP stream and never synchronises the
+ *     host, except fp_init, fp_destroy and fp_error_count.
+ *   - Return value 0 (FP_OK) or a negative error code.  FP_EDEVICE keeps the HIP error
+ *     text for fp_last_error.  Numerical trouble inside a cell is NOT a call error: it
+ *     is reported through the per-cell status array (FP_CELL_*).
+ *   - Use one context per stream; calls on one context must not overlap.
+ *
+ * Memory layouts (all row-major, one row per cell):
+ *   mom[ncell][32] doubles: [N, U1 U2 U3, theta, P11 P12 P13 P22 P23 P33,
+ *       T111 T112 T113 T122 T123 T133 T222 T223 T233 T333,
+ *       R11 R12 R13 R22 R23 R33, W1 W2 W3, H, 0]
+ *     with c = v - U, P_ij = <c_i c_j>, T_ijk = <c_i c_j c_k>, R_ij = <c_i c_j |c|^2>,
+ *     W_i = <c_i |c|^4>, H = <|c|^6>, theta = tr(P)/3, averages with 1/N.
+ *   rec[ncell][16] doubles: [Ct11 Ct12 Ct13 Ct22 Ct23 Ct33, G1 G2 G3, tau, theta, E,
+ *       eps2, sigma, status, 0] where the drift is A = -c/tau + N with
+ *       N = Ct c + G (|c|^2 - 3 theta) - eps2 (c |c|^2 - S), S_i = T_ikk
+ *       (eqs. cubic_drift and update_N; the paper's c^(1) equals Ct - I/tau),
+ *       E = exp(-dt/tau), sigma = sqrt(theta (1 - exp(-2 dt/tau))).
+ *   samp[ncell][16] doubles: [sum N, sum v_i (3), sum v_i v_j (11 12 13 22 23 33),
+ *       sum v_i |v|^2 (3), number of samples, 0].
+ */
+#ifndef FP_H
+#define FP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define FP_OK 0
+#define FP_EINVAL (-1)     /* bad argument: null pointer, size, configuration */
+#define FP_ENOMEM (-2)     /* device allocation failed */
+#define FP_EDEVICE (-3)    /* a HIP call failed; text in fp_last_error */
+#define FP_ECAPACITY (-4)  /* more particles than the context's capacity */
+
+enum fp_geometry { FP_COUETTE1D = 0, FP_CAVITY2D = 1 };
+enum fp_precision { FP_F32 = 0, FP_F64 = 1 };
+enum fp_conserve { FP_EXACT = 0, FP_PAPER = 1 };
+
+/* per-cell status written by the closure calls */
+enum fp_cell_status {
+    FP_CELL_OK = 0,          /* exact 9x9 solve */
+    FP_CELL_EMPTY = 1,       /* N <= 1 or theta = 0: the update leaves the cell alone */
+    FP_CELL_FEW = 2,         /* N < n_min: Langevin drift (Ct = G = 0, no cubic term) */
+    FP_CELL_SINGULAR = 3,    /* |pivot| < pivot_tol or non-finite solution: Langevin */
+    FP_CELL_NONFINITE = 4,   /* non-finite moments: the update leaves the cell alone */
+    FP_CELL_NN = 5,          /* learned closure accepted */
+    FP_CELL_NN_FALLBACK = 6  /* learned closure rejected, exact solve used */
+};
+
+/* fp_step flags */
+#define FP_STEP_COLLIDE 1u   /* velocity update (eqs. update_vel, update_N) + conservation */
+#define FP_STEP_MOVE 2u      /* free flight (eq. update_pos), diffuse walls, new cell key */
+#define FP_STEP_KEYS 4u      /* only recompute cell keys from the stored positions */
+
+typedef struct fp_config {
+    int32_t geometry;        /* fp_geometry */
+    int32_t precision;       /* fp_precision: storage and update arithmetic of particles */
+    int32_t conserve;        /* fp_conserve */
+    int32_t nx, ny;          /* cells along x, y (ny = 1 for the 1-D channel) */
+    int32_t n_min;           /* cells with fewer particles use the Langevin drift */
+    int32_t max_bounces;     /* wall interactions per particle and step */
+    int32_t reserved0;
+    int64_t capacity;        /* largest particle count any call will see */
+    double x0, y0;           /* domain origin [m] */
+    double lx, ly;           /* domain extent [m] */
+    double dx, dy;           /* cell size [m] */
+    double dt;               /* time step [s] */
+    double kB, mass;         /* Boltzmann constant [J/K], molecular mass [kg] */
+    double mu_ref, T_ref, omega;  /* viscosity law mu = mu_ref (T/T_ref)^omega */
+    double fnum_over_vol;    /* real molecules per particle / cell volume [1/m^3] */
+    double eps_hat;          /* cubic stabiliser: eps^2 = eps_hat / (theta tau) */
+    double pivot_tol;        /* pivot threshold of the normalised 9x9 system */
+    double T_wall[4];        /* wall temperatures: x = x0, x = x0+lx, y = y0, y = y0+ly */
+    double u_wall[4][3];     /* wall velocities, same order */
+    uint64_t seed;           /* Philox4x32-10 key */
+} fp_config;
+
+/* Particle arrays in structure-of-arrays form.  x, y, vx, vy, vz are float
+ * (FP_F32) or double (FP_F64); y may be NULL in 1-D.  pid is a unique particle id
+ * (the Philox counter); key is the cell index (row-major, ky*nx + kx). */
+typedef struct fp_particles {
+    void *x, *y, *vx, *vy, *vz;
+    uint32_t* pid;
+    int32_t* key;
+    int64_t n;               /* number of particles */
+} fp_particles;
+
+typedef struct fp_ctx fp_ctx;
+
+/* Create a context on the current device; allocates scratch for cfg->capacity
+ * particles and nx*ny cells.  Synchronous. */
+int fp_init(const fp_config* cfg, fp_ctx** out);
+/* Free the context and its scratch (synchronises the device). */
+void fp_destroy(fp_ctx* ctx);
+/* Text of the last FP_EDEVICE/FP_EINVAL error of this context ("" if none). */
+const char* fp_last_error(const fp_ctx* ctx);
+/* Number of invalid keys met by fp_bin since fp_init (synchronous read-back). */
+int64_t fp_error_count(fp_ctx* ctx, hipStream_t s);
+
+/* Stable counting sort by cell key (the sort of "sort_and_calc_moments" in Algorithm
+ * "Baseline Physics Simulation Loop"): dst receives the particles of src ordered by
+ * key, particles of one cell in their order in src.  offsets[ncell+1] receives the
+ * cell start indices.  perm (optional, may be NULL) receives for every slot of dst
+ * the index in src it came from.  src and dst must not alias.  Keys outside
+ * [0, ncell) are counted by fp_error_count and such particles are dropped. */
+int fp_bin(fp_ctx* ctx, const fp_particles* src, fp_particles* dst, int32_t* offsets,
+           int32_t* perm, hipStream_t s);
+
+/* Central moments of every cell of particles sorted by cell (moments u^(p) entering
+ * eq. system9x9 and Table matrix_system; layout mom above). */
+int fp_moments(fp_ctx* ctx, const fp_particles* p, const int32_t* offsets, double* mom,
+               hipStream_t s);
+
+/* Exact closure of every cell: the 9x9 moment-matching system (eq. system9x9, Table
+ * matrix_system) in theta-normalised form, solved by LU with partial pivoting in FP64;
+ * tau = 2 mu / p (eq. tau).  Writes rec and status[ncell]. */
+int fp_closure_solve(fp_ctx* ctx, const double* mom, double* rec, int32_t* status,
+                     hipStream_t s);
+
+/* Per-particle step on particles sorted by cell, as selected by flags:
+ *   FP_STEP_COLLIDE  eq. update_vel with N of eq. update_N, Philox normals with counter
+ *                    (pid, step, 3, 0); then every cell is recentred on U and its energy
+ *                    restored exactly (FP_EXACT) or by alpha of eq. update_alpha
+ *                    (FP_PAPER).  Cells with status EMPTY or NONFINITE are untouched.
+ *   FP_STEP_MOVE     x += v dt (eq. update_pos) in FP64 with diffuse isothermal walls
+ *                    (re-emission draws from counter (pid, step, 4, bounce)), then key.
+ *   FP_STEP_KEYS     key from the stored position only.
+ * mom/rec may be NULL when COLLIDE is not set; offsets may be NULL for MOVE/KEYS only. */
+int fp_step(fp_ctx* ctx, fp_particles* p, const int32_t* offsets, const double* mom,
+            const double* rec, uint64_t step, uint32_t flags, hipStream_t s);
+
+/* Time averaging (the "average_results" step): adds the raw sums of every cell,
+ * reconstructed from mom, to samp (layout samp above). */
+int fp_sample(fp_ctx* ctx, const double* mom, double* samp, hipStream_t s);
+
+
+/* ---- learned closure (project extension) -------------------------------------------
+ * The paper replaces the closure build and solve by a dense network evaluated on the GPU
+ * with standardised inputs and outputs (Secs. "Phase 1-2", "Phase 3", Algorithm
+ * "Accelerated ML Simulation Loop").  Here: 27 features of the theta-normalised moments
+ *   [P/th - I (6), T/th^1.5 (10), R/th^2 - 5I (6), W/th^2.5 (3), eps_hat, log10 N]
+ * -> 128 -> 128 -> 128 (SiLU) -> 9 normalised coefficients
+ *   [tau Ct - 5 eps_hat I (6), tau sqrt(theta) Gamma (3)],
+ * zero padded to 32 inputs and 16 outputs, BF16 MFMA with FP32 accumulation.
+ *
+ * Parameter vector: FP_NN_PARAMS floats, device memory, owned by the caller:
+ *   W1[128][32] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] W4[16][128] b4[16]
+ *   x_mean[32] x_std[32] y_mean[16] y_std[16]
+ * (W[out][in] row-major; the first FP_NN_TRAIN floats are trained, the scalers fixed). */
+#define FP_NN_PARAMS 39408
+#define FP_NN_TRAIN 39312
+#define FP_NN_FEATURES 32
+#define FP_NN_OUTPUTS 16
+#define FP_LOSS_MSE 0        /* mean over samples of the squared error of standardised targets */
+#define FP_LOSS_RESIDUAL 1   /* mean over samples of |A y - b|^2 of the normalised 9x9 system */
+
+typedef struct fp_nn fp_nn;
+
+/* Create a network handle on ctx with training scratch for batches up to max_batch
+ * (0: inference only).  Synchronous. */
+int fp_nn_create(fp_ctx* ctx, int64_t max_batch, fp_nn** out);
+void fp_nn_destroy(fp_nn* net);
+/* Convert params (FP_NN_PARAMS floats, device) into the network's BF16 image. */
+int fp_nn_load(fp_ctx* ctx, fp_nn* net, const float* params, hipStream_t s);
+/* Learned closure of every cell: network outputs de-standardised, then checked against
+ * the cell's own normalised 9x9 system; accepted if |A y - b| <= tol_abs + tol_rel |b|
+ * (status FP_CELL_NN), otherwise solved exactly (FP_CELL_NN_FALLBACK).  Cells that are
+ * EMPTY/NONFINITE/FEW are treated as in fp_closure_solve.  Same rec layout. */
+int fp_closure_nn(fp_ctx* ctx, const fp_nn* net, const double* mom, double* rec,
+                  int32_t* status, double tol_abs, double tol_rel, hipStream_t s);
+/* Copy the standardised network outputs of the last fp_closure_nn ([ncell][16]). */
+int fp_nn_outputs(fp_ctx* ctx, const fp_nn* net, float* y, hipStream_t s);
+/* Raw (unstandardised) features of n moment records: feats[n][32] floats. */
+int fp_nn_features(fp_ctx* ctx, const double* mom, int64_t n, float* feats, hipStream_t s);
+/* Normalised 9x9 systems of n moment records: sys[n][90] doubles, A row-major then b. */
+int fp_closure_build(fp_ctx* ctx, const double* mom, int64_t n, double* sys, hipStream_t s);
+/* Gradient of the loss w.r.t. the trainable parameters for a batch of B samples:
+ * feats[B][32] raw features; targets[B][16] raw normalised targets (FP_LOSS_MSE) or
+ * sys[B][90] (FP_LOSS_RESIDUAL).  Writes grad[FP_NN_PARAMS] (only the trainable prefix)
+ * and *loss (device float).  Fixed-order reductions: bitwise reproducible. */
+int fp_nn_grad(fp_ctx* ctx, fp_nn* net, const float* params, const float* feats,
+               const float* targets, const double* sys, int64_t B, int32_t loss_kind,
+               float* grad, float* loss, hipStream_t s);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8) step t >= 1 on the trainable prefix. */
+int fp_nn_adam(fp_ctx* ctx, float* params, const float* grad, float* m, float* v, int64_t t,
+               float lr, hipStream_t s);
+/* fp_nn_grad followed by fp_nn_adam. */
+int fp_nn_train_step(fp_ctx* ctx, fp_nn* net, float* params, float* m, float* v, int64_t t,
+                     float lr, const float* feats, const float* targets, const double* sys,
+                     int64_t B, int32_t loss_kind, float* loss, hipStream_t s);
+
+/* ---- differentiation (project extension) -------------------------------------------
+ * Reverse mode through fp_moments and fp_closure_solve for the map
+ *   particle velocities -> cell coefficients (Ct, Gamma) of rec entries 0..8,
+ * including the dependence of tau (eq. tau) and of the normalisation on theta. */
+
+/* ybar[ncell][16]: gradient w.r.t. rec entries 0..8 (others ignored).  Writes
+ * mombar[ncell][32], the gradient w.r.t. the moment record (theta folded into the
+ * diagonal of P; zero rows for cells whose status is not FP_CELL_OK). */
+int fp_closure_solve_backward(fp_ctx* ctx, const double* mom, const double* rec,
+                              const double* ybar, double* mombar, hipStream_t s);
+/* Gradient w.r.t. every particle velocity of a scalar whose gradient w.r.t. the moment
+ * records is mombar (entries U, theta, P, T, R, W, H are honoured), recomputed from the
+ * velocities: vbar_p = (1/N) (G(c_p) - <G>) + Ubar / N with G = sum_k mbar_k grad f_k.
+ * vbar_* are double arrays in the order of p. */
+int fp_moments_backward(fp_ctx* ctx, const fp_particles* p, const int32_t* offsets,
+                        const double* mom, const double* mombar, double* vbar_x,
+                        double* vbar_y, double* vbar_z, hipStream_t s);
+/* Normalised training targets [tau Ct - 5 eps_hat I, tau sqrt(theta) Gamma] of n update
+ * records: targets[n][16] floats (entries 9..15 zero). */
+int fp_nn_targets(fp_ctx* ctx, const double* rec, int64_t n, float* targets, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FP_H */

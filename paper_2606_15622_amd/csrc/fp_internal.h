@@ -1,0 +1,143 @@
+// fp_internal.h -- context, layout constants and device helpers of libfpgpu (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/fp.h"
+
+namespace fpg {
+
+// ---- record layouts (see include/fp.h) -------------------------------------------------
+constexpr int MOM = 32, REC = 16, SAMP = 16;
+enum { M_N = 0, M_U = 1, M_TH = 4, M_P = 5, M_T = 11, M_R = 21, M_W = 27, M_H = 30 };
+enum { R_C = 0, R_G = 6, R_TAU = 9, R_TH = 10, R_E = 11, R_EPS2 = 12, R_SIG = 13, R_ST = 14 };
+enum { PURPOSE_COLLISION = 3, PURPOSE_WALL = 4 };
+
+constexpr double TWO_PI = 6.283185307179586;
+
+}  // namespace fpg
+
+struct fp_ctx {
+    fp_config cfg;
+    int device = 0;
+    int32_t ncell = 0;
+    // binning scratch
+    int32_t* cnt = nullptr;      // [ncell+1] particles per destination cell
+    int32_t* ccnt = nullptr;     // [ncell+1] contribution records per destination cell
+    int32_t* coff = nullptr;     // [ncell+1] contribution offsets
+    int32_t* ccur = nullptr;     // [ncell+1] contribution cursors
+    int32_t* cwave = nullptr;    // [capacity] contribution: source wave index
+    uint64_t* cmask = nullptr;   // [capacity] contribution: lane mask
+    int32_t* gidx = nullptr;     // [capacity] slot list for cells too large for LDS
+    int32_t* blocksum = nullptr; // scan partials
+    unsigned long long* errcount = nullptr;  // invalid keys
+    std::string err;
+};
+
+namespace fpg {
+
+// ---- error helpers ----------------------------------------------------------------------
+int set_err(fp_ctx* c, int code, const std::string& msg);
+int check_launch(fp_ctx* c, const char* what);
+
+// ---- Philox4x32-10 (Salmon et al., SC'11) -------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k.x += 0x9E3779B9u;
+            k.y += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.x, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k.y, (uint32_t)p0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint4 draw(uint64_t seed, uint32_t pid, uint32_t step,
+                                      uint32_t purpose, uint32_t sub) {
+    return philox4x32_10(make_uint4(pid, step, purpose, sub),
+                         make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+}
+
+// uniform on (0,1): (k + 1/2) 2^-32, exact in double
+__device__ __forceinline__ double u01d(uint32_t k) { return ((double)k + 0.5) * 0x1p-32; }
+// float version: k rounded to 24 bits, stays in (0, 1]
+__device__ __forceinline__ float u01f(uint32_t k) {
+    return __builtin_fmaf((float)k, 0x1p-32f, 0x1p-33f);
+}
+
+// three standard normals, Box-Muller on (u0,u1) and (u2,u3), double precision
+__device__ __forceinline__ void normals3d(uint4 r, double& z0, double& z1, double& z2) {
+    const double u0 = u01d(r.x), u1 = u01d(r.y), u2 = u01d(r.z), u3 = u01d(r.w);
+    const double r0 = sqrt(-2.0 * log(u0));
+    const double r1 = sqrt(-2.0 * log(u2));
+    z0 = r0 * cos(TWO_PI * u1);
+    z1 = r0 * sin(TWO_PI * u1);
+    z2 = r1 * cos(TWO_PI * u3);
+}
+
+// single precision: hardware log2 and sin/cos of revolutions (v_sin/v_cos take x in
+// units of 2 pi, so sin(2 pi u) is one instruction for u in (0, 1])
+__device__ __forceinline__ void normals3f(uint4 r, float& z0, float& z1, float& z2) {
+    const float u0 = u01f(r.x), u1 = u01f(r.y), u2 = u01f(r.z), u3 = u01f(r.w);
+    constexpr float M2LN2 = -1.3862943611198906f;  // -2 ln 2
+    const float r0 = __builtin_sqrtf(M2LN2 * __builtin_amdgcn_logf(u0));
+    const float r1 = __builtin_sqrtf(M2LN2 * __builtin_amdgcn_logf(u2));
+    z0 = r0 * __builtin_amdgcn_cosf(u1);
+    z1 = r0 * __builtin_amdgcn_sinf(u1);
+    z2 = r1 * __builtin_amdgcn_cosf(u3);
+}
+
+// ---- cell key from a stored position (double, no contraction) --------------------------
+__device__ __forceinline__ int32_t axis_cell(double pos, double origin, double inv_h,
+                                             int32_t n) {
+    const double f = floor(__dmul_rn(__dsub_rn(pos, origin), inv_h));
+    if (!(f >= 0.0)) return 0;
+    if (f > (double)(n - 1)) return n - 1;
+    return (int32_t)f;
+}
+
+// ---- cross-lane sums inside aligned groups of G lanes (result in every lane) -----------
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "G");
+    if constexpr (G >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+    if constexpr (G >= 4) v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+    if constexpr (G >= 8) v += dpp_d<0x141>(v);  // row_half_mirror: other quad of 8
+    if constexpr (G >= 16) v += dpp_d<0x140>(v); // row_mirror: other half of 16
+    if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// ---- host-side launch shape of the per-cell kernels -------------------------------------
+// lanes per cell from the mean occupancy: about 16 particles per lane, 4..64 lanes
+inline int lanes_per_cell(int64_t n, int32_t ncell) {
+    const double avg = ncell > 0 ? (double)n / (double)ncell : 0.0;
+    int g = 4;
+    while (g < 64 && (double)g * 16.0 < avg * 1.25) g *= 2;
+    return g;
+}
+
+// ---- launchers implemented in the kernel files -------------------------------------------
+int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* offsets,
+               int32_t* perm, hipStream_t s);
+int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,
+                   hipStream_t s);
+int launch_closure(fp_ctx* c, const double* mom, double* rec, int32_t* status, hipStream_t s);
+int launch_step(fp_ctx* c, fp_particles* p, const int32_t* offsets, const double* mom,
+                const double* rec, uint64_t step, uint32_t flags, hipStream_t s);
+int launch_sample(fp_ctx* c, const double* mom, double* samp, hipStream_t s);
+
+}  // namespace fpg

@@ -1,0 +1,404 @@
+// fp_step.hip -- velocity update with per-cell conservation, free flight, diffuse walls.
+//
+// Collision (G lanes per cell): for every particle, c = v - U,
+//   N  = Ct c + G (|c|^2 - 3 theta) - eps2 (c |c|^2 - S)            (eq. update_N)
+//   c* = c E + (1 - E) tau N + sigma xi,  xi ~ N(0, I) from Philox    (eq. update_vel)
+// then the cell is recentred on U and its energy restored, exactly (EXACT) or with the
+// factor alpha of eq. update_alpha (PAPER).  c* of up to K particles per lane stays in
+// registers between the sum pass and the write pass; beyond that it is recomputed from
+// the same Philox counter (identical bits).  Per-particle arithmetic is in the storage
+// precision; the cell sums and the rescale factor are FP64.
+// Flight (eq. update_pos) and the wall interactions are FP64 without contraction, so a
+// stored position and the wall decisions are the same numbers on any IEEE machine.
+#include "fp_internal.h"
+
+namespace fpg {
+
+constexpr int ST_BLOCK = 256;
+constexpr int ST_K = 16;
+
+struct Walls {
+    double lo[2], hi[2];
+    double RT[4];   // R T_w per wall
+    double sRT[4];  // sqrt(R T_w)
+};
+
+__device__ __forceinline__ double st_round(double v, bool f32) {
+    return f32 ? (double)__double2float_rn(v) : v;
+}
+
+// diffuse re-emission from wall w (0: x lo, 1: x hi, 2: y lo, 3: y hi): inward normal
+// speed with density ~ v exp(-v^2/(2 R T_w)), Gaussian tangential velocity about u_w
+__device__ __forceinline__ void wall_emit(const fp_config& g, const Walls& W, int w,
+                                          uint32_t pid, uint32_t step, uint32_t bounce,
+                                          double v[3]) {
+    const uint4 r = draw(g.seed, pid, step, PURPOSE_WALL, bounce);
+    const double u0 = u01d(r.x), u1 = u01d(r.y), u2 = u01d(r.z);
+    const double RT = W.RT[w];
+    const double vn = sqrt(-2.0 * RT * log(u0));
+    const double rr = sqrt(-2.0 * log(u1));
+    const double za = rr * cos(TWO_PI * u2);
+    const double zb = rr * sin(TWO_PI * u2);
+    const double s = W.sRT[w];
+    if (w < 2) {
+        v[0] = (w == 0) ? vn : -vn;
+        v[1] = g.u_wall[w][1] + s * za;
+        v[2] = g.u_wall[w][2] + s * zb;
+    } else {
+        v[1] = (w == 2) ? vn : -vn;
+        v[0] = g.u_wall[w][0] + s * za;
+        v[2] = g.u_wall[w][2] + s * zb;
+    }
+}
+
+// free flight over dt with wall interactions; pos/v updated in place (FP64)
+template <bool TWO_D>
+__device__ __forceinline__ void fly(const fp_config& g, const Walls& W, double pos[2],
+                                    double v[3], uint32_t pid, uint32_t step, bool f32) {
+    double trem = g.dt;
+    for (int bounce = 0;; ++bounce) {
+        const double ex = __dadd_rn(pos[0], __dmul_rn(v[0], trem));
+        const double ey = TWO_D ? __dadd_rn(pos[1], __dmul_rn(v[1], trem)) : 0.0;
+        int wall = -1;
+        double th = 0.0;
+        if (ex < W.lo[0] && v[0] < 0.0) {
+            double t = __ddiv_rn(__dsub_rn(W.lo[0], pos[0]), v[0]);
+            t = t < 0.0 ? 0.0 : t;
+            wall = 0;
+            th = t;
+        }
+        if (ex > W.hi[0] && v[0] > 0.0) {
+            double t = __ddiv_rn(__dsub_rn(W.hi[0], pos[0]), v[0]);
+            t = t < 0.0 ? 0.0 : t;
+            if (wall < 0 || t < th) { wall = 1; th = t; }
+        }
+        if (TWO_D) {
+            if (ey < W.lo[1] && v[1] < 0.0) {
+                double t = __ddiv_rn(__dsub_rn(W.lo[1], pos[1]), v[1]);
+                t = t < 0.0 ? 0.0 : t;
+                if (wall < 0 || t < th) { wall = 2; th = t; }
+            }
+            if (ey > W.hi[1] && v[1] > 0.0) {
+                double t = __ddiv_rn(__dsub_rn(W.hi[1], pos[1]), v[1]);
+                t = t < 0.0 ? 0.0 : t;
+                if (wall < 0 || t < th) { wall = 3; th = t; }
+            }
+        }
+        if (wall < 0) {
+            pos[0] = ex;
+            if (TWO_D) pos[1] = ey;
+            break;
+        }
+        if (bounce == g.max_bounces) {
+            pos[0] = fmin(fmax(ex, W.lo[0]), W.hi[0]);
+            if (TWO_D) pos[1] = fmin(fmax(ey, W.lo[1]), W.hi[1]);
+            break;
+        }
+        th = th > trem ? trem : th;
+        if (wall < 2) {
+            pos[0] = wall == 0 ? W.lo[0] : W.hi[0];
+            if (TWO_D) pos[1] = __dadd_rn(pos[1], __dmul_rn(v[1], th));
+        } else {
+            pos[0] = __dadd_rn(pos[0], __dmul_rn(v[0], th));
+            pos[1] = wall == 2 ? W.lo[1] : W.hi[1];
+        }
+        wall_emit(g, W, wall, pid, step, (uint32_t)bounce, v);
+        v[0] = st_round(v[0], f32);
+        v[1] = st_round(v[1], f32);
+        v[2] = st_round(v[2], f32);
+        trem = __dsub_rn(trem, th);
+    }
+    pos[0] = st_round(pos[0], f32);
+    if (TWO_D) pos[1] = st_round(pos[1], f32);
+}
+
+template <bool TWO_D>
+__device__ __forceinline__ int32_t cell_key(const fp_config& g, double x, double y, double inv_dx,
+                                            double inv_dy) {
+    const int32_t kx = axis_cell(x, g.x0, inv_dx, g.nx);
+    const int32_t ky = TWO_D ? axis_cell(y, g.y0, inv_dy, g.ny) : 0;
+    return ky * g.nx + kx;
+}
+
+__host__ __device__ inline Walls make_walls(const fp_config& g) {
+    Walls W;
+    W.lo[0] = g.x0;
+    W.lo[1] = g.y0;
+    W.hi[0] = g.x0 + g.lx;
+    W.hi[1] = g.y0 + g.ly;
+    for (int w = 0; w < 4; ++w) {
+        W.RT[w] = g.kB / g.mass * g.T_wall[w];
+        W.sRT[w] = sqrt(W.RT[w]);
+    }
+    return W;
+}
+
+// ---- per-particle collision arithmetic in the storage precision -----------------------
+template <typename T>
+struct CellCoef {
+    T U[3], C[6], G[3], S[3], th3, E, k1, sig, eps2;
+};
+
+template <typename T>
+__device__ __forceinline__ void collide_one(const CellCoef<T>& q, T v0, T v1, T v2, uint4 r,
+                                            T cs[3], T& nn, T& cn);
+
+template <>
+__device__ __forceinline__ void collide_one<float>(const CellCoef<float>& q, float v0, float v1,
+                                                   float v2, uint4 r, float cs[3], float& nn,
+                                                   float& cn) {
+    const float c0 = v0 - q.U[0], c1 = v1 - q.U[1], c2 = v2 - q.U[2];
+    const float cc = __builtin_fmaf(c0, c0, __builtin_fmaf(c1, c1, c2 * c2));
+    const float a = cc - q.th3;
+    const float N0 = __builtin_fmaf(q.C[0], c0, __builtin_fmaf(q.C[1], c1, __builtin_fmaf(q.C[2], c2,
+                     __builtin_fmaf(q.G[0], a, -q.eps2 * __builtin_fmaf(c0, cc, -q.S[0])))));
+    const float N1 = __builtin_fmaf(q.C[1], c0, __builtin_fmaf(q.C[3], c1, __builtin_fmaf(q.C[4], c2,
+                     __builtin_fmaf(q.G[1], a, -q.eps2 * __builtin_fmaf(c1, cc, -q.S[1])))));
+    const float N2 = __builtin_fmaf(q.C[2], c0, __builtin_fmaf(q.C[4], c1, __builtin_fmaf(q.C[5], c2,
+                     __builtin_fmaf(q.G[2], a, -q.eps2 * __builtin_fmaf(c2, cc, -q.S[2])))));
+    float z0, z1, z2;
+    normals3f(r, z0, z1, z2);
+    cs[0] = __builtin_fmaf(c0, q.E, __builtin_fmaf(q.k1, N0, q.sig * z0));
+    cs[1] = __builtin_fmaf(c1, q.E, __builtin_fmaf(q.k1, N1, q.sig * z1));
+    cs[2] = __builtin_fmaf(c2, q.E, __builtin_fmaf(q.k1, N2, q.sig * z2));
+    nn = __builtin_fmaf(N0, N0, __builtin_fmaf(N1, N1, N2 * N2));
+    cn = __builtin_fmaf(c0, N0, __builtin_fmaf(c1, N1, c2 * N2));
+}
+
+template <>
+__device__ __forceinline__ void collide_one<double>(const CellCoef<double>& q, double v0,
+                                                    double v1, double v2, uint4 r, double cs[3],
+                                                    double& nn, double& cn) {
+    const double c0 = v0 - q.U[0], c1 = v1 - q.U[1], c2 = v2 - q.U[2];
+    const double cc = fma(c0, c0, fma(c1, c1, c2 * c2));
+    const double a = cc - q.th3;
+    const double N0 = fma(q.C[0], c0, fma(q.C[1], c1, fma(q.C[2], c2,
+                      fma(q.G[0], a, -q.eps2 * fma(c0, cc, -q.S[0])))));
+    const double N1 = fma(q.C[1], c0, fma(q.C[3], c1, fma(q.C[4], c2,
+                      fma(q.G[1], a, -q.eps2 * fma(c1, cc, -q.S[1])))));
+    const double N2 = fma(q.C[2], c0, fma(q.C[4], c1, fma(q.C[5], c2,
+                      fma(q.G[2], a, -q.eps2 * fma(c2, cc, -q.S[2])))));
+    double z0, z1, z2;
+    normals3d(r, z0, z1, z2);
+    cs[0] = fma(c0, q.E, fma(q.k1, N0, q.sig * z0));
+    cs[1] = fma(c1, q.E, fma(q.k1, N1, q.sig * z1));
+    cs[2] = fma(c2, q.E, fma(q.k1, N2, q.sig * z2));
+    nn = fma(N0, N0, fma(N1, N1, N2 * N2));
+    cn = fma(c0, N0, fma(c1, N1, c2 * N2));
+}
+
+template <typename T, int G, int K, bool TWO_D>
+__global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
+    fp_config g, int32_t ncell, const int32_t* __restrict__ offsets,
+    const double* __restrict__ mom, const double* __restrict__ rec, T* __restrict__ px,
+    T* __restrict__ py, T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
+    const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step, int move) {
+    const int64_t gt = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
+    const int32_t cell = (int32_t)(gt / G);
+    const int lg = (int)(gt % G);
+    const bool in = cell < ncell;
+    const bool f32 = sizeof(T) == 4;
+    int32_t b = 0, n = 0;
+    bool active = false;
+    CellCoef<T> q;
+    double Ud[3] = {0, 0, 0}, theta = 0, tau = 0, E = 1;
+    if (in) {
+        b = offsets[cell];
+        n = offsets[cell + 1] - b;
+        const double* r = rec + (int64_t)cell * REC;
+        const int st = (int)r[R_ST];
+        active = n > 0 && st != FP_CELL_EMPTY && st != FP_CELL_NONFINITE;
+        if (active) {
+            const double* m = mom + (int64_t)cell * MOM;
+            Ud[0] = m[M_U]; Ud[1] = m[M_U + 1]; Ud[2] = m[M_U + 2];
+            tau = r[R_TAU]; theta = r[R_TH]; E = r[R_E];
+            for (int i = 0; i < 3; ++i) q.U[i] = (T)Ud[i];
+            for (int i = 0; i < 6; ++i) q.C[i] = (T)r[R_C + i];
+            for (int i = 0; i < 3; ++i) q.G[i] = (T)r[R_G + i];
+            q.S[0] = (T)(m[M_T + 0] + m[M_T + 3] + m[M_T + 5]);
+            q.S[1] = (T)(m[M_T + 1] + m[M_T + 6] + m[M_T + 8]);
+            q.S[2] = (T)(m[M_T + 2] + m[M_T + 7] + m[M_T + 9]);
+            q.th3 = (T)(3.0 * theta);
+            q.E = (T)E;
+            q.k1 = (T)((1.0 - E) * tau);
+            q.sig = (T)r[R_SIG];
+            q.eps2 = (T)r[R_EPS2];
+        }
+    }
+    const int32_t na = active ? n : 0;
+
+    // pass A: c* and cell sums
+    T cs0[K], cs1[K], cs2[K];
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+    const bool exact = g.conserve == FP_EXACT;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int32_t j = lg + k * G;
+        if (j < na) {
+            const int32_t p = b + j;
+            T cs[3], nn, cn;
+            collide_one<T>(q, pvx[p], pvy[p], pvz[p], draw(g.seed, ppid[p], step, PURPOSE_COLLISION, 0),
+                           cs, nn, cn);
+            cs0[k] = cs[0]; cs1[k] = cs[1]; cs2[k] = cs[2];
+            const double d0 = cs[0], d1 = cs[1], d2 = cs[2];
+            s0 += d0; s1 += d1; s2 += d2;
+            if (exact) s3 = fma(d0, d0, fma(d1, d1, fma(d2, d2, s3)));
+            else { s3 += (double)nn; s4 += (double)cn; }
+        }
+    }
+    for (int32_t j = lg + K * G; j < na; j += G) {
+        const int32_t p = b + j;
+        T cs[3], nn, cn;
+        collide_one<T>(q, pvx[p], pvy[p], pvz[p], draw(g.seed, ppid[p], step, PURPOSE_COLLISION, 0),
+                       cs, nn, cn);
+        const double d0 = cs[0], d1 = cs[1], d2 = cs[2];
+        s0 += d0; s1 += d1; s2 += d2;
+        if (exact) s3 = fma(d0, d0, fma(d1, d1, fma(d2, d2, s3)));
+        else { s3 += (double)nn; s4 += (double)cn; }
+    }
+    s0 = group_sum<G>(s0);
+    s1 = group_sum<G>(s1);
+    s2 = group_sum<G>(s2);
+    s3 = group_sum<G>(s3);
+    s4 = group_sum<G>(s4);
+
+    T cb[3] = {0, 0, 0}, sc = 1;
+    if (active) {
+        const double in_ = 1.0 / (double)n;
+        const double c0 = s0 * in_, c1 = s1 * in_, c2 = s2 * in_;
+        double scale;
+        if (exact) {
+            const double e2 = s3 * in_ - (c0 * c0 + c1 * c1 + c2 * c2);
+            scale = sqrt(3.0 * theta / e2);
+        } else {
+            const double a2 = 1.0 + tau / (3.0 * theta) *
+                                        (tau * (1.0 - E) * (1.0 - E) * (s3 * in_) +
+                                         2.0 * (E - E * E) * (s4 * in_));
+            scale = 1.0 / sqrt(a2);
+        }
+        if (!isfinite(scale) || !(scale > 0.0)) scale = 1.0;
+        cb[0] = (T)c0; cb[1] = (T)c1; cb[2] = (T)c2;
+        sc = (T)scale;
+    }
+
+    // pass B: final velocity, then flight and key
+    const Walls W = make_walls(g);
+    const double inv_dx = 1.0 / g.dx, inv_dy = 1.0 / g.dy;
+    auto finish = [&](int32_t p, T v0, T v1, T v2) {
+        if (!move) {
+            pvx[p] = v0; pvy[p] = v1; pvz[p] = v2;
+            return;
+        }
+        double pos[2] = {(double)px[p], TWO_D ? (double)py[p] : 0.0};
+        double v[3] = {(double)v0, (double)v1, (double)v2};
+        fly<TWO_D>(g, W, pos, v, ppid[p], step, f32);
+        px[p] = (T)pos[0];
+        if (TWO_D) py[p] = (T)pos[1];
+        pvx[p] = (T)v[0]; pvy[p] = (T)v[1]; pvz[p] = (T)v[2];
+        pkey[p] = cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy);
+    };
+    auto newv = [&](T c, int i) -> T {
+        return __builtin_fma(c - cb[i], sc, q.U[i]);
+    };
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int32_t j = lg + k * G;
+        if (j < n) {
+            const int32_t p = b + j;
+            if (active)
+                finish(p, newv(cs0[k], 0), newv(cs1[k], 1), newv(cs2[k], 2));
+            else
+                finish(p, pvx[p], pvy[p], pvz[p]);
+        }
+    }
+    for (int32_t j = lg + K * G; j < n; j += G) {
+        const int32_t p = b + j;
+        if (active) {
+            T cs[3], nn, cn;
+            collide_one<T>(q, pvx[p], pvy[p], pvz[p],
+                           draw(g.seed, ppid[p], step, PURPOSE_COLLISION, 0), cs, nn, cn);
+            finish(p, newv(cs[0], 0), newv(cs[1], 1), newv(cs[2], 2));
+        } else {
+            finish(p, pvx[p], pvy[p], pvz[p]);
+        }
+    }
+}
+
+// flight (or key recomputation) without a collision: one thread per particle
+template <typename T, bool TWO_D>
+__global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, T* __restrict__ px,
+                                                         T* __restrict__ py, T* __restrict__ pvx,
+                                                         T* __restrict__ pvy, T* __restrict__ pvz,
+                                                         const uint32_t* __restrict__ ppid,
+                                                         int32_t* __restrict__ pkey, uint32_t step,
+                                                         int keys_only) {
+    const int64_t p = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
+    if (p >= n) return;
+    const double inv_dx = 1.0 / g.dx, inv_dy = 1.0 / g.dy;
+    double pos[2] = {(double)px[p], TWO_D ? (double)py[p] : 0.0};
+    if (!keys_only) {
+        const Walls W = make_walls(g);
+        double v[3] = {(double)pvx[p], (double)pvy[p], (double)pvz[p]};
+        fly<TWO_D>(g, W, pos, v, ppid[p], step, sizeof(T) == 4);
+        px[p] = (T)pos[0];
+        if (TWO_D) py[p] = (T)pos[1];
+        pvx[p] = (T)v[0]; pvy[p] = (T)v[1]; pvz[p] = (T)v[2];
+    }
+    pkey[p] = cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy);
+}
+
+template <typename T, int G, bool TWO_D>
+static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
+                           const double* rec, uint32_t step, int move, hipStream_t s) {
+    const int64_t threads = (int64_t)c->ncell * G;
+    const unsigned grid = (unsigned)((threads + ST_BLOCK - 1) / ST_BLOCK);
+    hipLaunchKernelGGL((collide_kernel<T, G, ST_K, TWO_D>), dim3(grid), dim3(ST_BLOCK), 0, s,
+                       c->cfg, c->ncell, off, mom, rec, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy,
+                       (T*)p->vz, p->pid, p->key, step, move);
+}
+
+template <typename T, bool TWO_D>
+static void collide_dispatch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
+                             const double* rec, uint32_t step, int move, hipStream_t s) {
+    switch (lanes_per_cell(p->n, c->ncell)) {
+        case 4: collide_launch<T, 4, TWO_D>(c, p, off, mom, rec, step, move, s); break;
+        case 8: collide_launch<T, 8, TWO_D>(c, p, off, mom, rec, step, move, s); break;
+        case 16: collide_launch<T, 16, TWO_D>(c, p, off, mom, rec, step, move, s); break;
+        case 32: collide_launch<T, 32, TWO_D>(c, p, off, mom, rec, step, move, s); break;
+        default: collide_launch<T, 64, TWO_D>(c, p, off, mom, rec, step, move, s); break;
+    }
+}
+
+template <typename T>
+static void step_typed(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
+                       const double* rec, uint32_t step, uint32_t flags, hipStream_t s) {
+    const bool two_d = c->cfg.geometry == FP_CAVITY2D;
+    const int move = (flags & FP_STEP_MOVE) ? 1 : 0;
+    if (flags & FP_STEP_COLLIDE) {
+        if (two_d) collide_dispatch<T, true>(c, p, off, mom, rec, step, move, s);
+        else collide_dispatch<T, false>(c, p, off, mom, rec, step, move, s);
+        return;
+    }
+    if (p->n == 0) return;
+    const unsigned grid = (unsigned)((p->n + ST_BLOCK - 1) / ST_BLOCK);
+    const int keys_only = (flags & FP_STEP_KEYS) ? 1 : 0;
+    if (two_d)
+        hipLaunchKernelGGL((move_kernel<T, true>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg, p->n,
+                           (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
+                           step, keys_only);
+    else
+        hipLaunchKernelGGL((move_kernel<T, false>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg, p->n,
+                           (T*)p->x, (T*)nullptr, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid,
+                           p->key, step, keys_only);
+}
+
+int launch_step(fp_ctx* c, fp_particles* p, const int32_t* offsets, const double* mom,
+                const double* rec, uint64_t step, uint32_t flags, hipStream_t s) {
+    if (c->cfg.precision == FP_F32)
+        step_typed<float>(c, p, offsets, mom, rec, (uint32_t)step, flags, s);
+    else
+        step_typed<double>(c, p, offsets, mom, rec, (uint32_t)step, flags, s);
+    return check_launch(c, "fp_step");
+}
+
+}  // namespace fpg

@@ -1,0 +1,347 @@
+"""ctypes binding of ``libfpgpu.so`` (include/fp.h).
+
+Argument marshalling only: torch tensors provide device memory and the stream, and
+every step of the path runs in the library's HIP kernels.  ``load()`` raises if the
+library has not been built; there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfpgpu.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "fp.h")
+
+FP_OK, FP_EINVAL, FP_ENOMEM, FP_EDEVICE, FP_ECAPACITY = 0, -1, -2, -3, -4
+FP_COUETTE1D, FP_CAVITY2D = 0, 1
+FP_F32, FP_F64 = 0, 1
+FP_EXACT, FP_PAPER = 0, 1
+(CELL_OK, CELL_EMPTY, CELL_FEW, CELL_SINGULAR, CELL_NONFINITE, CELL_NN,
+ CELL_NN_FALLBACK) = range(7)
+STEP_COLLIDE, STEP_MOVE, STEP_KEYS = 1, 2, 4
+MOM_STRIDE, REC_STRIDE, SAMP_STRIDE = 32, 16, 16
+NN_PARAMS, NN_TRAIN, NN_FEATURES, NN_OUTPUTS = 39408, 39312, 32, 16
+LOSS_MSE, LOSS_RESIDUAL = 0, 1
+
+
+class FPConfig(C.Structure):
+    _fields_ = [
+        ("geometry", C.c_int32), ("precision", C.c_int32), ("conserve", C.c_int32),
+        ("nx", C.c_int32), ("ny", C.c_int32), ("n_min", C.c_int32), ("max_bounces", C.c_int32),
+        ("reserved0", C.c_int32), ("capacity", C.c_int64),
+        ("x0", C.c_double), ("y0", C.c_double), ("lx", C.c_double), ("ly", C.c_double),
+        ("dx", C.c_double), ("dy", C.c_double), ("dt", C.c_double),
+        ("kB", C.c_double), ("mass", C.c_double),
+        ("mu_ref", C.c_double), ("T_ref", C.c_double), ("omega", C.c_double),
+        ("fnum_over_vol", C.c_double), ("eps_hat", C.c_double), ("pivot_tol", C.c_double),
+        ("T_wall", C.c_double * 4), ("u_wall", (C.c_double * 3) * 4),
+        ("seed", C.c_uint64),
+    ]
+
+
+class FPParticles(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("vx", C.c_void_p), ("vy", C.c_void_p),
+                ("vz", C.c_void_p), ("pid", C.c_void_p), ("key", C.c_void_p), ("n", C.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Load libfpgpu.so (built by ``paper_2606_15622_amd.build``); raises if missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2606_15622_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, vp, i32, i64, u32, u64 = C.POINTER, C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
+        L.fp_init.argtypes = [P(FPConfig), P(vp)]
+        L.fp_init.restype = C.c_int
+        L.fp_destroy.argtypes = [vp]
+        L.fp_last_error.argtypes = [vp]
+        L.fp_last_error.restype = C.c_char_p
+        L.fp_error_count.argtypes = [vp, vp]
+        L.fp_error_count.restype = i64
+        L.fp_bin.argtypes = [vp, P(FPParticles), P(FPParticles), vp, vp, vp]
+        L.fp_moments.argtypes = [vp, P(FPParticles), vp, vp, vp]
+        L.fp_closure_solve.argtypes = [vp, vp, vp, vp, vp]
+        L.fp_step.argtypes = [vp, P(FPParticles), vp, vp, vp, u64, u32, vp]
+        L.fp_sample.argtypes = [vp, vp, vp, vp]
+        L.fp_nn_create.argtypes = [vp, i64, P(vp)]
+        L.fp_nn_destroy.argtypes = [vp]
+        L.fp_nn_load.argtypes = [vp, vp, vp, vp]
+        L.fp_closure_nn.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, vp]
+        L.fp_nn_outputs.argtypes = [vp, vp, vp, vp]
+        L.fp_nn_features.argtypes = [vp, vp, i64, vp, vp]
+        L.fp_closure_build.argtypes = [vp, vp, i64, vp, vp]
+        L.fp_nn_grad.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp, vp, vp]
+        L.fp_nn_adam.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float, vp]
+        L.fp_nn_train_step.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float, vp, vp, vp, i64, i32,
+                                       vp, vp]
+        L.fp_nn_targets.argtypes = [vp, vp, i64, vp, vp]
+        L.fp_closure_solve_backward.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fp_moments_backward.argtypes = [vp, P(FPParticles), vp, vp, vp, vp, vp, vp, vp]
+        for f in ("fp_bin", "fp_moments", "fp_closure_solve", "fp_step", "fp_sample", "fp_nn_create",
+                  "fp_nn_load", "fp_closure_nn", "fp_nn_outputs", "fp_nn_features",
+                  "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
+                  "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/fp.h."""
+    import re
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|int64_t|const char\*)\s+(fp_\w+)\s*\(", txt, re.M)))
+
+
+def make_config(w: dict, capacity: int) -> FPConfig:
+    c = FPConfig()
+    c.geometry = {"couette1d": FP_COUETTE1D, "cavity2d": FP_CAVITY2D}[w["geometry"]]
+    c.precision = {"f32": FP_F32, "f64": FP_F64}[w["precision"]]
+    c.conserve = {"exact": FP_EXACT, "paper": FP_PAPER}[w.get("conserve", "exact")]
+    c.nx, c.ny = int(w["nx"]), int(w["ny"])
+    c.n_min = int(w.get("n_min", 4))
+    c.max_bounces = int(w.get("max_bounces", 8))
+    c.capacity = int(capacity)
+    c.x0, c.y0, c.lx, c.ly = float(w["x0"]), float(w["y0"]), float(w["lx"]), float(w["ly"])
+    c.dx, c.dy, c.dt = float(w["dx"]), float(w["dy"]), float(w["dt"])
+    c.kB, c.mass = float(w["kB"]), float(w["mass"])
+    c.mu_ref, c.T_ref, c.omega = float(w["mu_ref"]), float(w["T_ref"]), float(w["omega"])
+    c.fnum_over_vol, c.eps_hat = float(w["fnum_over_vol"]), float(w["eps_hat"])
+    c.pivot_tol = float(w.get("pivot_tol", 1e-12))
+    for k in range(4):
+        c.T_wall[k] = float(w["T_wall"][k])
+        for j in range(3):
+            c.u_wall[k][j] = float(w["u_wall"][k][j])
+    c.seed = int(w["seed"])
+    return c
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Particles:
+    """Device particle arrays (structure of arrays) of one storage precision."""
+
+    def __init__(self, n, dtype, two_d, device="cuda", capacity=None):
+        cap = int(capacity if capacity is not None else n)
+        self.capacity = cap
+        self.n = int(n)
+        self.dtype = dtype
+        self.two_d = two_d
+        mk = lambda dt: torch.zeros(max(cap, 1), dtype=dt, device=device)
+        self.x = mk(dtype)
+        self.y = mk(dtype) if two_d else None
+        self.vx, self.vy, self.vz = mk(dtype), mk(dtype), mk(dtype)
+        self.pid = mk(torch.int32)
+        self.key = mk(torch.int32)
+
+    @classmethod
+    def from_numpy(cls, w, state, capacity=None, device="cuda"):
+        dt = torch.float32 if w["precision"] == "f32" else torch.float64
+        two_d = w["geometry"] != "couette1d"
+        n = state["x"].shape[0]
+        p = cls(n, dt, two_d, device, capacity)
+        npdt = np.float32 if dt == torch.float32 else np.float64
+        for k in ("x", "vx", "vy", "vz"):
+            getattr(p, k)[:n].copy_(torch.from_numpy(np.ascontiguousarray(state[k], dtype=npdt)))
+        if two_d:
+            p.y[:n].copy_(torch.from_numpy(np.ascontiguousarray(state["y"], dtype=npdt)))
+        p.pid[:n].copy_(torch.from_numpy(np.ascontiguousarray(state["pid"], dtype=np.uint32).view(np.int32)))
+        if "key" in state:
+            p.key[:n].copy_(torch.from_numpy(np.ascontiguousarray(state["key"], dtype=np.int32)))
+        return p
+
+    def struct(self):
+        s = FPParticles()
+        s.x, s.vx, s.vy, s.vz = (t.data_ptr() for t in (self.x, self.vx, self.vy, self.vz))
+        s.y = self.y.data_ptr() if self.y is not None else None
+        s.pid, s.key = self.pid.data_ptr(), self.key.data_ptr()
+        s.n = self.n
+        return s
+
+    def numpy(self):
+        n = self.n
+        out = {k: getattr(self, k)[:n].double().cpu().numpy() for k in ("x", "vx", "vy", "vz")}
+        out["y"] = self.y[:n].double().cpu().numpy() if self.y is not None else np.zeros(n)
+        out["pid"] = self.pid[:n].cpu().numpy().view(np.uint32).copy()
+        out["key"] = self.key[:n].cpu().numpy().copy()
+        return out
+
+
+class Context:
+    """An fp_ctx plus the entry points of include/fp.h."""
+
+    def __init__(self, w: dict, capacity: int):
+        self.lib = load()
+        self.w = w
+        self.cfg = make_config(w, capacity)
+        self.ncell = int(w["nx"]) * int(w["ny"])
+        h = C.c_void_p()
+        rc = self.lib.fp_init(C.byref(self.cfg), C.byref(h))
+        if rc != FP_OK:
+            raise RuntimeError(f"fp_init failed ({rc})")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.fp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != FP_OK:
+            raise RuntimeError(f"{what} failed ({rc}): {self.lib.fp_last_error(self.h).decode()}")
+
+    def error_count(self, stream=None):
+        return self.lib.fp_error_count(self.h, _stream(stream))
+
+    def bin(self, src, dst, offsets, perm=None, stream=None):
+        a, b = src.struct(), dst.struct()
+        self._check(self.lib.fp_bin(self.h, C.byref(a), C.byref(b), _ptr(offsets), _ptr(perm),
+                                    _stream(stream)), "fp_bin")
+
+    def moments(self, p, offsets, mom, stream=None):
+        a = p.struct()
+        self._check(self.lib.fp_moments(self.h, C.byref(a), _ptr(offsets), _ptr(mom),
+                                        _stream(stream)), "fp_moments")
+
+    def closure_solve(self, mom, rec, status, stream=None):
+        self._check(self.lib.fp_closure_solve(self.h, _ptr(mom), _ptr(rec), _ptr(status),
+                                              _stream(stream)), "fp_closure_solve")
+
+    def step(self, p, offsets, mom, rec, step, flags, stream=None):
+        a = p.struct()
+        self._check(self.lib.fp_step(self.h, C.byref(a), _ptr(offsets), _ptr(mom), _ptr(rec),
+                                     int(step), int(flags), _stream(stream)), "fp_step")
+
+    def sample(self, mom, samp, stream=None):
+        self._check(self.lib.fp_sample(self.h, _ptr(mom), _ptr(samp), _stream(stream)), "fp_sample")
+
+    # ---- learned closure -------------------------------------------------------------
+    def closure_build(self, mom, n, sys, stream=None):
+        self._check(self.lib.fp_closure_build(self.h, _ptr(mom), int(n), _ptr(sys), _stream(stream)),
+                    "fp_closure_build")
+
+    def nn_features(self, mom, n, feats, stream=None):
+        self._check(self.lib.fp_nn_features(self.h, _ptr(mom), int(n), _ptr(feats), _stream(stream)),
+                    "fp_nn_features")
+
+    def nn_targets(self, rec, n, targets, stream=None):
+        self._check(self.lib.fp_nn_targets(self.h, _ptr(rec), int(n), _ptr(targets), _stream(stream)),
+                    "fp_nn_targets")
+
+    def closure_solve_backward(self, mom, rec, ybar, mombar, stream=None):
+        self._check(self.lib.fp_closure_solve_backward(self.h, _ptr(mom), _ptr(rec), _ptr(ybar),
+                                                       _ptr(mombar), _stream(stream)),
+                    "fp_closure_solve_backward")
+
+    def moments_backward(self, p, offsets, mom, mombar, gx, gy, gz, stream=None):
+        a = p.struct()
+        self._check(self.lib.fp_moments_backward(self.h, C.byref(a), _ptr(offsets), _ptr(mom),
+                                                 _ptr(mombar), _ptr(gx), _ptr(gy), _ptr(gz),
+                                                 _stream(stream)), "fp_moments_backward")
+
+    def nn_adam(self, params, grad, m, v, t, lr, stream=None):
+        self._check(self.lib.fp_nn_adam(self.h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t),
+                                        float(lr), _stream(stream)), "fp_nn_adam")
+
+
+class Network:
+    """An fp_nn handle: BF16 image for inference plus training scratch."""
+
+    def __init__(self, ctx: Context, max_batch: int = 0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        rc = ctx.lib.fp_nn_create(ctx.h, int(max_batch), C.byref(h))
+        if rc != FP_OK:
+            raise RuntimeError(f"fp_nn_create failed ({rc})")
+        self.h = h
+        self.max_batch = int(max_batch)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.fp_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, params, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_nn_load(c.h, self.h, _ptr(params), _stream(stream)), "fp_nn_load")
+
+    def closure(self, mom, rec, status, tol_abs, tol_rel, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_closure_nn(c.h, self.h, _ptr(mom), _ptr(rec), _ptr(status), float(tol_abs),
+                                     float(tol_rel), _stream(stream)), "fp_closure_nn")
+
+    def outputs(self, y, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_nn_outputs(c.h, self.h, _ptr(y), _stream(stream)), "fp_nn_outputs")
+
+    def grad(self, params, feats, targets, sys, B, loss_kind, grad, loss, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_nn_grad(c.h, self.h, _ptr(params), _ptr(feats), _ptr(targets), _ptr(sys),
+                                  int(B), int(loss_kind), _ptr(grad), _ptr(loss), _stream(stream)),
+                 "fp_nn_grad")
+
+    def train_step(self, params, m, v, t, lr, feats, targets, sys, B, loss_kind, loss, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_nn_train_step(c.h, self.h, _ptr(params), _ptr(m), _ptr(v), int(t),
+                                        float(lr), _ptr(feats), _ptr(targets), _ptr(sys), int(B),
+                                        int(loss_kind), _ptr(loss), _stream(stream)), "fp_nn_train_step")
+
+
+class Simulation:
+    """Host loop of the exact-closure step on one GPU (Algorithm "Baseline Physics
+    Simulation Loop"): bin -> moments -> [sample] -> closure -> collide + move.
+    All buffers stay on the device; nothing crosses to the host inside the loop."""
+
+    def __init__(self, w, state, device="cuda"):
+        self.w = w
+        n = state["x"].shape[0]
+        self.ctx = Context(w, n)
+        self.a = Particles.from_numpy(w, state, device=device)
+        self.b = Particles(n, self.a.dtype, self.a.two_d, device)
+        nc = self.ctx.ncell
+        self.offsets = torch.zeros(nc + 1, dtype=torch.int32, device=device)
+        self.mom = torch.zeros((nc, MOM_STRIDE), dtype=torch.float64, device=device)
+        self.rec = torch.zeros((nc, REC_STRIDE), dtype=torch.float64, device=device)
+        self.status = torch.zeros(nc, dtype=torch.int32, device=device)
+        self.samp = torch.zeros((nc, SAMP_STRIDE), dtype=torch.float64, device=device)
+        if "key" not in state:
+            self.ctx.step(self.a, None, None, None, 0, STEP_KEYS)
+
+    def step(self, s, sample=False):
+        self.ctx.bin(self.a, self.b, self.offsets)
+        self.a, self.b = self.b, self.a
+        self.ctx.moments(self.a, self.offsets, self.mom)
+        if sample:
+            self.ctx.sample(self.mom, self.samp)
+        self.ctx.closure_solve(self.mom, self.rec, self.status)
+        self.ctx.step(self.a, self.offsets, self.mom, self.rec, s, STEP_COLLIDE | STEP_MOVE)
+
+    def run(self, step0, nsteps, n_skip=None):
+        n_skip = self.w.get("n_skip", 0) if n_skip is None else n_skip
+        for s in range(step0, step0 + nsteps):
+            self.step(s, sample=s >= n_skip)

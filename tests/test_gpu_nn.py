@@ -1,0 +1,197 @@
+"""Learned closure on the GPU: BF16-MFMA inference, fallback, gradients and Adam against
+the FP64 MLP oracle (through the C ABI).
+
+The oracle evaluates the network in FP64 with the weights, inputs, hidden activations
+and back-propagated pre-activation gradients rounded to bfloat16 at the points where the
+GPU holds them in that format.  The remaining differences come from FP32 (GPU) versus
+FP64 accumulation of <= 128-term dot products (~1e-6 relative) and the rare bfloat16
+rounding flips they cause (one bfloat16 ulp = 2^-8 relative in one element); the
+tolerances below (relative L2 1e-2 on outputs and gradients) bound that with margin.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as M
+from oracle import oracle as O
+from paper_2606_15622_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def fp():
+    from paper_2606_15622_amd import fpgpu
+    fpgpu.load()
+    return fpgpu
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def random_params(seed=0):
+    rng = np.random.default_rng(seed)
+    d = {}
+    for name, shp in M.SHAPES:
+        if name.startswith("W"):
+            d[name] = rng.standard_normal(shp) / np.sqrt(shp[1]) * 1.5
+        elif name.startswith("b"):
+            d[name] = rng.standard_normal(shp) * 0.1
+        elif name == "x_mean":
+            d[name] = rng.standard_normal(shp) * 0.05
+        elif name == "x_std":
+            d[name] = rng.uniform(0.3, 1.5, shp)
+        elif name == "y_mean":
+            d[name] = rng.standard_normal(shp) * 0.01
+        else:
+            d[name] = rng.uniform(0.01, 0.1, shp)
+    return d
+
+
+def cells(ncell, seed):
+    rng = np.random.default_rng(seed)
+    counts = rng.integers(10, 500, ncell)
+    vx, vy, vz, off = I.mixture_cells(counts, seed=seed)
+    return O.moments(off, vx, vy, vz)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_inference_matches_bf16_oracle():
+    F = fp()
+    nc = 1000 + 17
+    mom = cells(nc, 3)
+    w = I.couette(ncell=nc, eps_hat=0.01)
+    ctx = F.Context(w, 1)
+    net = F.Network(ctx, 0)
+    p = random_params(1)
+    pflat = M.pack(p).astype(np.float32)
+    pd = dev(pflat, torch.float32)
+    net.load(pd)
+    md = dev(mom, torch.float64)
+    rec = torch.zeros((nc, 16), dtype=torch.float64, device="cuda")
+    st = torch.zeros(nc, dtype=torch.int32, device="cuda")
+    net.closure(md, rec, st, 1e30, 0.0)
+    y = torch.zeros((nc, 16), dtype=torch.float32, device="cuda")
+    net.outputs(y)
+    torch.cuda.synchronize()
+    yg = y.double().cpu().numpy()
+    p32 = M.unpack(pflat.astype(np.float64))
+    xs = (M.features(mom, 0.01) - p32["x_mean"]) / p32["x_std"]
+    yo, _ = M.forward(p32, xs, emulate_bf16=True)
+    assert np.all(yg[:, 9:] == 0)
+    assert rel_l2(yg[:, :9], yo[:, :9]) < 1e-2
+    assert np.abs(yg[:, :9] - yo[:, :9]).max() < 0.05 * np.abs(yo[:, :9]).max()
+    stn = st.cpu().numpy()
+    assert np.all(stn == F.CELL_NN)
+    # the record is the de-standardised network output, de-normalised
+    r = rec.cpu().numpy()
+    yn = yg[:, :9] * p32["y_std"][:9] + p32["y_mean"][:9]
+    yn[:, [0, 3, 5]] += 5 * 0.01
+    tau, th = r[:, 9], r[:, 10]
+    np.testing.assert_allclose(r[:, :6] * tau[:, None], yn[:, :6], rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(r[:, 6:9] * (tau * np.sqrt(th))[:, None], yn[:, 6:], rtol=1e-6, atol=1e-9)
+
+
+def test_forced_fallback_is_bitwise_the_exact_closure():
+    F = fp()
+    nc = 777
+    mom = cells(nc, 4)
+    mom[5] = 0
+    mom[5, 0] = 1
+    w = I.couette(ncell=nc, eps_hat=0.01)
+    ctx = F.Context(w, 1)
+    net = F.Network(ctx, 0)
+    net.load(dev(M.pack(random_params(2)).astype(np.float32), torch.float32))
+    md = dev(mom, torch.float64)
+    r1 = torch.zeros((nc, 16), dtype=torch.float64, device="cuda")
+    r2 = torch.zeros_like(r1)
+    s1 = torch.zeros(nc, dtype=torch.int32, device="cuda")
+    s2 = torch.zeros_like(s1)
+    ctx.closure_solve(md, r1, s1)
+    net.closure(md, r2, s2, 0.0, 0.0)
+    torch.cuda.synchronize()
+    a, b = r1.cpu().numpy(), r2.cpu().numpy()
+    sa, sb = s1.cpu().numpy(), s2.cpu().numpy()
+    assert np.all(sb[sa == F.CELL_OK] == F.CELL_NN_FALLBACK)
+    assert np.all(sb[sa != F.CELL_OK] == sa[sa != F.CELL_OK])
+    np.testing.assert_array_equal(a[:, :14], b[:, :14])
+
+
+@pytest.mark.parametrize("loss_kind", [0, 1])
+def test_gradient_matches_bf16_oracle(loss_kind):
+    F = fp()
+    B = 3000 + 5
+    mom = cells(B, 5)
+    eh = 0.01
+    w = I.couette(ncell=1, eps_hat=eh)
+    ctx = F.Context(w, 1)
+    net = F.Network(ctx, B)
+    p = random_params(3)
+    pflat = M.pack(p).astype(np.float32)
+    pd = dev(pflat, torch.float32)
+    md = dev(mom, torch.float64)
+    feats = torch.zeros((B, 32), dtype=torch.float32, device="cuda")
+    ctx.nn_features(md, B, feats)
+    sys = torch.zeros((B, 90), dtype=torch.float64, device="cuda")
+    ctx.closure_build(md, B, sys)
+    wex = I.couette(ncell=B, eps_hat=eh)
+    rec, st = O.closure(wex, mom)
+    tgt = M.targets(rec, eh)
+    td = dev(tgt, torch.float32)
+    grad = torch.zeros(M.N_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    net.grad(pd, feats, td, sys, B, loss_kind, grad, loss)
+    grad2 = torch.zeros_like(grad)
+    net.grad(pd, feats, td, sys, B, loss_kind, grad2, loss)
+    torch.cuda.synchronize()
+    g = grad.double().cpu().numpy()
+    assert torch.equal(grad, grad2)
+    # features and systems against the oracle's own
+    fo = M.features(mom, eh)
+    np.testing.assert_allclose(feats.cpu().numpy(), fo, rtol=2e-6, atol=2e-6)
+    so = np.array([np.concatenate([a.ravel(), b]) for a, b in (O.closure_system(m, eh) for m in mom)])
+    np.testing.assert_allclose(sys.cpu().numpy(), so, rtol=1e-12, atol=1e-12)
+    # oracle gradient
+    p32 = M.unpack(pflat.astype(np.float64))
+    xs = (fo - p32["x_mean"]) / p32["x_std"]
+    y, cache = M.forward(p32, xs, emulate_bf16=True)
+    if loss_kind == 0:
+        ts = (tgt - p32["y_mean"]) / p32["y_std"]
+        mask = np.r_[np.ones(9), np.zeros(7)]
+        lo, dy = M.mse_grad(y, ts, mask)
+    else:
+        yf = y[:, :9] * p32["y_std"][:9] + p32["y_mean"][:9]
+        yf[:, [0, 3, 5]] += 5 * eh
+        A = so[:, :81].reshape(B, 9, 9)
+        r = np.einsum("nik,nk->ni", A, yf) - so[:, 81:]
+        lo = float((r * r).sum() / B)
+        dy = np.zeros((B, 16))
+        dy[:, :9] = 2.0 * np.einsum("nik,ni->nk", A, r) / B * p32["y_std"][:9]
+    go = M.grads_flat(M.backward(p32, cache, dy, emulate_bf16=True))
+    assert float(loss.cpu()) == pytest.approx(lo, rel=2e-2)
+    assert rel_l2(g[:M.N_TRAIN], go[:M.N_TRAIN]) < 1e-2
+    cos = g[:M.N_TRAIN] @ go[:M.N_TRAIN] / np.linalg.norm(g[:M.N_TRAIN]) / np.linalg.norm(go[:M.N_TRAIN])
+    assert cos > 0.9999
+    assert np.all(g[M.N_TRAIN:] == 0)
+
+
+def test_adam_matches_oracle():
+    F = fp()
+    w = I.couette(ncell=1)
+    ctx = F.Context(w, 1)
+    rng = np.random.default_rng(7)
+    p = rng.standard_normal(M.N_PARAMS).astype(np.float32)
+    m = np.zeros(M.N_PARAMS, dtype=np.float32)
+    v = np.zeros(M.N_PARAMS, dtype=np.float32)
+    pd, md, vd = dev(p, torch.float32), dev(m, torch.float32), dev(v, torch.float32)
+    po, mo, vo = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for t in range(1, 4):
+        g = rng.standard_normal(M.N_PARAMS).astype(np.float32)
+        ctx.nn_adam(pd, dev(g, torch.float32), md, vd, t, 1e-3)
+        po, mo, vo = M.adam(po, g.astype(np.float64), mo, vo, t, 1e-3)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(pd.cpu().numpy(), po, rtol=1e-5, atol=1e-6)
+    assert np.all(pd.cpu().numpy()[M.N_TRAIN:] == p[M.N_TRAIN:])

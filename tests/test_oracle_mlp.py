@@ -1,0 +1,96 @@
+"""Pins of the MLP oracle used to check the learned-closure kernels (CPU)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as M
+from oracle import oracle as O
+from paper_2606_15622_amd import inputs as I
+
+
+def random_params(seed=0, scale=1.0):
+    rng = np.random.default_rng(seed)
+    d = {}
+    for name, shp in M.SHAPES:
+        if name.startswith("W"):
+            d[name] = rng.standard_normal(shp) * scale / np.sqrt(shp[1])
+        elif name.startswith("b"):
+            d[name] = rng.standard_normal(shp) * 0.1
+        elif name.endswith("mean"):
+            d[name] = rng.standard_normal(shp) * 0.1
+        else:
+            d[name] = rng.uniform(0.5, 2.0, shp)
+    return d
+
+
+def test_backward_matches_central_differences():
+    p = random_params(1)
+    rng = np.random.default_rng(2)
+    xs = rng.standard_normal((7, 32))
+    t = rng.standard_normal((7, 16))
+    mask = np.r_[np.ones(9), np.zeros(7)]
+
+    def loss(pp):
+        y, _ = M.forward(pp, xs)
+        return M.mse_grad(y, t, mask)[0]
+
+    y, cache = M.forward(p, xs)
+    _, dy = M.mse_grad(y, t, mask)
+    g = M.backward(p, cache, dy)
+    h = 1e-6
+    for name, idx in [("W1", (3, 5)), ("b1", (7,)), ("W2", (10, 100)), ("b3", (50,)), ("W4", (2, 64)),
+                      ("b4", (8,)), ("W3", (127, 0))]:
+        pp, pm = {k: v.copy() for k, v in p.items()}, {k: v.copy() for k, v in p.items()}
+        pp[name][idx] += h
+        pm[name][idx] -= h
+        fd = (loss(pp) - loss(pm)) / (2 * h)
+        assert g[name][idx] == pytest.approx(fd, rel=1e-6, abs=1e-9), name
+    # padded outputs carry no gradient
+    assert np.all(g["W4"][9:] == 0) and np.all(g["b4"][9:] == 0)
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(3)
+    a = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-8, 8, 10000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 65504.0, 3.4e38]])
+    ref = torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(M.bf16(a), ref)
+
+
+def test_adam_matches_torch():
+    rng = np.random.default_rng(4)
+    p = rng.standard_normal(M.N_PARAMS)
+    m = np.zeros(M.N_PARAMS)
+    v = np.zeros(M.N_PARAMS)
+    tp = torch.tensor(p[:M.N_TRAIN].copy(), requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    for t in range(1, 6):
+        g = rng.standard_normal(M.N_PARAMS)
+        p, m, v = M.adam(p, g, m, v, t, 1e-3)
+        opt.zero_grad()
+        tp.grad = torch.tensor(g[:M.N_TRAIN].copy())
+        opt.step()
+    np.testing.assert_allclose(p[:M.N_TRAIN], tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_maxwellian_features_and_targets_vanish():
+    th = I.KB / I.MASS_AR * 273.0
+    vx, vy, vz = I.gauss_hermite3_cell(th, drift=(3.0, 1.0, 0.0))
+    m = O.moments(np.array([0, 216], dtype=np.int32), vx, vy, vz)
+    for eh in (0.0, 0.01):
+        f = M.features(m, eh)
+        np.testing.assert_allclose(f[0, :25], 0.0, atol=1e-12)
+        assert f[0, 25] == eh and f[0, 26] == pytest.approx(np.log10(216))
+        w = I.couette(ncell=1, eps_hat=eh)
+        rec, st = O.closure(w, m)
+        np.testing.assert_allclose(M.targets(rec, eh), 0.0, atol=1e-12)
+
+
+def test_pack_unpack_layout():
+    p = random_params(5)
+    flat = M.pack(p)
+    assert flat.shape == (M.N_PARAMS,)
+    q = M.unpack(flat)
+    for k in p:
+        np.testing.assert_array_equal(p[k], q[k])
+    assert M.N_TRAIN == 39312 and M.N_PARAMS == 39408
