@@ -91,21 +91,23 @@ void or_keys(const or_config* cfg, int64_t n, const double* x, const double* y, 
     for (int64_t p = 0; p < n; ++p) {
         int32_t kx = axis_index(x[p], cfg->x0, inv_dx, cfg->nx);
         int32_t ky = 0;
-        if (cfg->geometry == OR_CAVITY2D) ky = axis_index(y[p], cfg->y0, inv_dy, cfg->ny);
+        if (cfg->geometry != OR_COUETTE1D) ky = axis_index(y[p], cfg->y0, inv_dy, cfg->ny);
         key[p] = ky * cfg->nx + kx;
     }
 }
 
 /* Stable counting sort (sort step of the loop): slot order within a cell is the
- * previous order of the particles. */
+ * previous order of the particles.  Particles with key == ncell are dropped. */
 void or_bin(int32_t ncell, int64_t n, const int32_t* key, int64_t* perm, int32_t* offsets)
 {
     for (int32_t c = 0; c <= ncell; ++c) offsets[c] = 0;
-    for (int64_t p = 0; p < n; ++p) offsets[key[p] + 1] += 1;
+    for (int64_t p = 0; p < n; ++p)
+        if (key[p] < ncell) offsets[key[p] + 1] += 1;     /* key == ncell: deleted */
     for (int32_t c = 0; c < ncell; ++c) offsets[c + 1] += offsets[c];
     int32_t* cursor = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ncell > 0 ? ncell : 1));
     for (int32_t c = 0; c < ncell; ++c) cursor[c] = offsets[c];
-    for (int64_t p = 0; p < n; ++p) perm[cursor[key[p]]++] = p;
+    for (int64_t p = 0; p < n; ++p)
+        if (key[p] < ncell) perm[cursor[key[p]]++] = p;
     free(cursor);
 }
 
@@ -172,11 +174,12 @@ void or_moments(int32_t ncell, const int32_t* offsets, const double* vx, const d
 /* ------------------------------------------------------------------------------------ */
 /* Collision time tau = 2 mu / p (eq. tau) with the VHS law for mu, and the cubic
  * stabiliser eps^2 = eps_hat / (theta tau).                                           */
-void or_cell_params(const or_config* cfg, const double* m, double* tau, double* eps2)
+void or_cell_params(const or_config* cfg, const double* m, double nvol, double* tau,
+                    double* eps2)
 {
     double theta = m[M_TH];
     double T = theta * cfg->mass / cfg->kB;
-    double ndens = m[M_N] * cfg->fnum_over_vol;
+    double ndens = m[M_N] * nvol;
     double p = ndens * cfg->kB * T;
     double mu = cfg->mu_ref * pow(T / cfg->T_ref, cfg->omega);
     *tau = 2.0 * mu / p;
@@ -268,8 +271,8 @@ static int solve9(double* A, double* b, double* y, double tol)
     return 0;
 }
 
-void or_closure(const or_config* cfg, int32_t ncell, const double* mom, double* rec,
-                int32_t* status)
+void or_closure(const or_config* cfg, int32_t ncell, const double* mom, const double* nvol,
+                double* rec, int32_t* status)
 {
     for (int32_t cell = 0; cell < ncell; ++cell) {
         const double* m = mom + (int64_t)cell * OR_MOM_STRIDE;
@@ -290,7 +293,7 @@ void or_closure(const or_config* cfg, int32_t ncell, const double* mom, double* 
             continue;
         }
         double tau, eps2;
-        or_cell_params(cfg, m, &tau, &eps2);
+        or_cell_params(cfg, m, nvol ? nvol[cell] : cfg->fnum_over_vol, &tau, &eps2);
         double E = exp(-cfg->dt / tau);
         double sigma = sqrt(theta * (1.0 - exp(-2.0 * cfg->dt / tau)));
         double y[9] = {0};
@@ -312,6 +315,105 @@ void or_closure(const or_config* cfg, int32_t ncell, const double* mom, double* 
         r[9] = tau; r[10] = theta; r[11] = E; r[13] = sigma; r[14] = (double)st;
         status[cell] = st;
     }
+}
+
+
+/* ------------------------------------------------------------------------------------ */
+/* Gas volume of the cells.  The part of a cell covered by the circle is integrated over
+ * x = cx + R sin(phi) (dx = R cos(phi) dphi, chord half-height R cos(phi)), split at the
+ * angles where the chord ends cross the cell's horizontal edges, with 24-point
+ * Gauss-Legendre on every smooth piece; the nodes are found by Newton iteration on the
+ * Legendre polynomial. */
+static void gauss_legendre(int n, double* xs, double* ws)
+{
+    for (int i = 0; i < n; ++i) {
+        double x = cos(OR_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1; p1 = p2;
+            }
+            double dp = n * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = x;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+            p0 = p1; p1 = p2;
+        }
+        double dp = n * (x * p1 - p0) / (x * x - 1.0);
+        xs[i] = x;
+        ws[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+}
+
+static double chord_in_cell(double phi, double cx, double cy, double R, double ya, double yb)
+{
+    (void)cx;
+    double h = R * cos(phi);
+    double lo = cy - h > ya ? cy - h : ya;
+    double hi = cy + h < yb ? cy + h : yb;
+    return hi > lo ? (hi - lo) * R * cos(phi) : 0.0;
+}
+
+static double covered_area(double cx, double cy, double R, double xa, double xb, double ya,
+                           double yb, const double* gx, const double* gw, int ng)
+{
+    double lo = xa > cx - R ? xa : cx - R;
+    double hi = xb < cx + R ? xb : cx + R;
+    if (!(lo < hi)) return 0.0;
+    double br[6];
+    int nb = 0;
+    br[nb++] = asin((lo - cx) / R);
+    br[nb++] = asin((hi - cx) / R);
+    double ys[2] = {ya, yb};
+    for (int k = 0; k < 2; ++k) {
+        double d = ys[k] - cy;
+        if (fabs(d) < R) {
+            double a = acos(fabs(d) / R);     /* chord end crosses y at x - cx = +-R sin(a) */
+            for (int sg = -1; sg <= 1; sg += 2) {
+                double ph = sg * a;
+                if (ph > br[0] && ph < br[1]) br[nb++] = ph;
+            }
+        }
+    }
+    for (int i = 1; i < nb; ++i)
+        for (int j = i; j > 0 && br[j] < br[j - 1]; --j) { double t = br[j]; br[j] = br[j - 1]; br[j - 1] = t; }
+    double area = 0.0;
+    for (int k = 0; k + 1 < nb; ++k) {
+        double a = br[k], b = br[k + 1];
+        if (!(b > a)) continue;
+        double s = 0.0;
+        for (int i = 0; i < ng; ++i) {
+            double ph = 0.5 * (a + b) + 0.5 * (b - a) * gx[i];
+            s += gw[i] * chord_in_cell(ph, cx, cy, R, ya, yb);
+        }
+        area += 0.5 * (b - a) * s;
+    }
+    return area;
+}
+
+void or_cell_volumes(const or_config* cfg, double* vol)
+{
+    double gx[24], gw[24];
+    gauss_legendre(24, gx, gw);
+    for (int32_t ky = 0; ky < cfg->ny; ++ky)
+        for (int32_t kx = 0; kx < cfg->nx; ++kx) {
+            double xa = cfg->x0 + kx * cfg->dx, xb = xa + cfg->dx;
+            double ya = cfg->y0 + ky * cfg->dy, yb = ya + cfg->dy;
+            double full = cfg->dx * cfg->dy;
+            double v = full;
+            if (cfg->geometry == OR_CYLINDER2D) {
+                v = full - covered_area(cfg->circle[0], cfg->circle[1], cfg->circle[2], xa, xb, ya,
+                                        yb, gx, gw, 24);
+                if (v < 1e-12 * full) v = 0.0;     /* covered cells (up to rounding) */
+                v *= cfg->depth;
+            }
+            vol[ky * cfg->nx + kx] = v;
+        }
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -419,9 +521,96 @@ static void emit(const or_config* cfg, int w, uint32_t pid, uint32_t step, uint3
     v[tb] = cfg->u_wall[w][tb] + s * zb;
 }
 
+/* Diffuse re-emission from the cylinder surface at (px, py): normal n = (p - c)/R points
+ * into the gas; speed along n ~ v exp(-v^2/(2 R T_body)), Gaussian along the in-plane
+ * tangent (-n_y, n_x) and along z; the body is at rest. */
+static void emit_circle(const or_config* cfg, double px, double py, uint32_t pid, uint32_t step,
+                        uint32_t bounce, double v[3])
+{
+    double u[4];
+    or_uniforms(cfg->seed, pid, step, OR_PURPOSE_WALL, bounce, u);
+    double RT = cfg->kB / cfg->mass * cfg->T_body;
+    double vn = sqrt(-2.0 * RT * log(u[0]));
+    double rr = sqrt(-2.0 * log(u[1]));
+    double za = rr * cos(2.0 * OR_PI * u[2]);
+    double zb = rr * sin(2.0 * OR_PI * u[2]);
+    double s = sqrt(RT);
+    double nx = (px - cfg->circle[0]) / cfg->circle[2];
+    double ny = (py - cfg->circle[1]) / cfg->circle[2];
+    double vt = s * za;
+    v[0] = vn * nx - vt * ny;
+    v[1] = vn * ny + vt * nx;
+    v[2] = s * zb;
+}
+
+/* Free flight in the open cylinder domain: straight segments between diffuse hits on
+ * the circle |p - c| = R; a particle whose end point lies outside the box is deleted.
+ * Returns 1 if deleted. */
+static int fly_cylinder(const or_config* cfg, double pos[2], double v[3], uint32_t pid,
+                        uint32_t step)
+{
+    const double cx = cfg->circle[0], cy = cfg->circle[1], R = cfg->circle[2];
+    double trem = cfg->dt;
+    for (int bounce = 0;; ++bounce) {
+        double dxc = pos[0] - cx, dyc = pos[1] - cy;
+        double a = v[0] * v[0] + v[1] * v[1];
+        double b = dxc * v[0] + dyc * v[1];
+        double c = dxc * dxc + dyc * dyc - R * R;
+        int hit = 0;
+        double th = 0.0;
+        if (c < 0.0) {
+            if (b < 0.0) {                    /* inside (rounding) and moving in: hit now */
+                double d = sqrt(dxc * dxc + dyc * dyc);
+                if (d > 0.0) {
+                    pos[0] = cx + R * (dxc / d);
+                    pos[1] = cy + R * (dyc / d);
+                }
+                hit = 1;
+            }
+        } else if (b < 0.0 && a > 0.0) {
+            double disc = b * b - a * c;
+            if (disc >= 0.0) {
+                double q = -b + sqrt(disc);
+                double t = c / q;
+                if (t <= trem) {
+                    hit = 1;
+                    th = t;
+                    pos[0] = pos[0] + v[0] * th;
+                    pos[1] = pos[1] + v[1] * th;
+                }
+            }
+        }
+        if (!hit) {
+            pos[0] = pos[0] + v[0] * trem;
+            pos[1] = pos[1] + v[1] * trem;
+            break;
+        }
+        if (bounce == cfg->max_bounces) return 0;      /* stop on the surface */
+        emit_circle(cfg, pos[0], pos[1], pid, step, (uint32_t)bounce, v);
+        for (int i = 0; i < 3; ++i) v[i] = store(cfg, v[i]);
+        trem = trem - th;
+    }
+    double x1 = cfg->x0 + cfg->lx, y1 = cfg->y0 + cfg->ly;
+    return (pos[0] < cfg->x0 || pos[0] > x1 || pos[1] < cfg->y0 || pos[1] > y1) ? 1 : 0;
+}
+
 void or_move(const or_config* cfg, int64_t n, double* x, double* y, double* vx, double* vy,
              double* vz, const uint32_t* pid, int32_t* key, uint32_t step)
 {
+    if (cfg->geometry == OR_CYLINDER2D) {
+        int32_t ncell = cfg->nx * cfg->ny;
+        for (int64_t p = 0; p < n; ++p) {
+            double pos[2] = {x[p], y[p]};
+            double v[3] = {vx[p], vy[p], vz[p]};
+            int gone = fly_cylinder(cfg, pos, v, pid[p], step);
+            x[p] = store(cfg, pos[0]);
+            y[p] = store(cfg, pos[1]);
+            vx[p] = v[0]; vy[p] = v[1]; vz[p] = v[2];
+            or_keys(cfg, 1, &x[p], &y[p], &key[p]);
+            if (gone) key[p] = ncell;
+        }
+        return;
+    }
     int two_d = (cfg->geometry == OR_CAVITY2D);
     double lo[2] = {cfg->x0, cfg->y0};
     double hi[2] = {cfg->x0 + cfg->lx, cfg->y0 + cfg->ly};
@@ -471,6 +660,59 @@ void or_move(const or_config* cfg, int64_t n, double* x, double* y, double* vx, 
         vx[p] = v[0]; vy[p] = v[1]; vz[p] = v[2];
     }
     or_keys(cfg, n, x, y, key);
+}
+
+
+/* ------------------------------------------------------------------------------------ */
+int64_t or_inject(const or_config* cfg, uint32_t step, uint32_t* pid_next, int64_t room,
+                  double* x, double* y, double* vx, double* vy, double* vz, uint32_t* pid,
+                  int32_t* key)
+{
+    double RT = cfg->kB / cfg->mass * cfg->T_inf;
+    double umag = sqrt(cfg->u_inf[0] * cfg->u_inf[0] + cfg->u_inf[1] * cfg->u_inf[1] +
+                       cfg->u_inf[2] * cfg->u_inf[2]);
+    double w = (umag + 4.0 * sqrt(2.0 * RT)) * cfg->dt;
+    double x0 = cfg->x0, y0 = cfg->y0, x1 = cfg->x0 + cfg->lx, y1 = cfg->y0 + cfg->ly;
+    double reg[4][4] = {{x0 - w, x0, y0 - w, y1 + w}, {x1, x1 + w, y0 - w, y1 + w},
+                        {x0, x1, y0 - w, y0}, {x0, x1, y1, y1 + w}};
+    double s = sqrt(RT);
+    int64_t total = 0, out = 0;
+    for (int r = 0; r < 4; ++r) {
+        double xa = reg[r][0], xb = reg[r][1], ya = reg[r][2], yb = reg[r][3];
+        double lam = cfg->n_inf * ((xb - xa) * (yb - ya)) * cfg->depth / cfg->fnum;
+        double base = floor(lam);
+        double uc[4];
+        or_uniforms(cfg->seed, (uint32_t)r, step, OR_PURPOSE_INJECT, 1, uc);
+        int64_t K = (int64_t)base + (uc[0] < lam - base ? 1 : 0);
+        for (int64_t k = 0; k < K; ++k) {
+            uint32_t id = *pid_next + (uint32_t)(total + k);
+            double d0[4], d1[4];
+            or_uniforms(cfg->seed, id, step, OR_PURPOSE_INJECT, 0, d0);
+            or_uniforms(cfg->seed, id, step, OR_PURPOSE_INJECT, 2, d1);
+            double px = xa + d0[0] * (xb - xa);
+            double py = ya + d0[1] * (yb - ya);
+            double r0 = sqrt(-2.0 * log(d0[2]));
+            double v0 = cfg->u_inf[0] + s * (r0 * cos(2.0 * OR_PI * d0[3]));
+            double v1 = cfg->u_inf[1] + s * (r0 * sin(2.0 * OR_PI * d0[3]));
+            double v2 = cfg->u_inf[2] + s * (sqrt(-2.0 * log(d1[0])) * cos(2.0 * OR_PI * d1[1]));
+            double ex = px + v0 * cfg->dt;
+            double ey = py + v1 * cfg->dt;
+            if (ex >= x0 && ex <= x1 && ey >= y0 && ey <= y1) {
+                if (out >= room) return -1;
+                x[out] = store(cfg, ex);
+                y[out] = store(cfg, ey);
+                vx[out] = store(cfg, v0);
+                vy[out] = store(cfg, v1);
+                vz[out] = store(cfg, v2);
+                pid[out] = id;
+                or_keys(cfg, 1, &x[out], &y[out], &key[out]);
+                ++out;
+            }
+        }
+        total += K;
+    }
+    *pid_next += (uint32_t)total;
+    return out;
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -524,10 +766,57 @@ int or_run(const or_config* cfg, int64_t n, double* x, double* y, double* vx, do
         memcpy(pid, tmpu, sizeof(uint32_t) * (size_t)n);
         or_moments(ncell, offsets, vx, vy, vz, mom);
         if (step >= n_skip && samp) or_sample(ncell, offsets, vx, vy, vz, samp);
-        or_closure(cfg, ncell, mom, rec, status);
+        or_closure(cfg, ncell, mom, NULL, rec, status);
         or_update(cfg, ncell, offsets, vx, vy, vz, pid, mom, rec, step);
         or_move(cfg, n, x, y, vx, vy, vz, pid, key, step);
     }
     free(perm); free(offsets); free(tmp); free(tmpu);
     return 0;
+}
+
+int or_run_open(const or_config* cfg, int64_t capacity, int64_t* n, double* x, double* y,
+                double* vx, double* vy, double* vz, uint32_t* pid, int32_t* key,
+                uint32_t* pid_next, uint32_t step0, int32_t nsteps, uint32_t n_skip,
+                double* mom, double* rec, int32_t* status, double* samp)
+{
+    int32_t ncell = cfg->nx * cfg->ny;
+    size_t cap = (size_t)(capacity > 0 ? capacity : 1);
+    int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * cap);
+    int32_t* offsets = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ncell + 1));
+    double* tmp = (double*)malloc(sizeof(double) * cap);
+    uint32_t* tmpu = (uint32_t*)malloc(sizeof(uint32_t) * cap);
+    double* vol = (double*)malloc(sizeof(double) * (size_t)ncell);
+    double* nvol = (double*)malloc(sizeof(double) * (size_t)ncell);
+    if (!perm || !offsets || !tmp || !tmpu || !vol || !nvol) {
+        free(perm); free(offsets); free(tmp); free(tmpu); free(vol); free(nvol);
+        return -1;
+    }
+    or_cell_volumes(cfg, vol);
+    double full = cfg->dx * cfg->dy * cfg->depth;
+    for (int32_t c = 0; c < ncell; ++c) nvol[c] = cfg->fnum / (vol[c] > 0.0 ? vol[c] : full);
+    int rc = 0;
+    for (int32_t s = 0; s < nsteps && rc == 0; ++s) {
+        uint32_t step = step0 + (uint32_t)s;
+        or_bin(ncell, *n, key, perm, offsets);
+        int64_t live = offsets[ncell];
+        double* arrs[5] = {x, y, vx, vy, vz};
+        for (int a = 0; a < 5; ++a) {
+            for (int64_t j = 0; j < live; ++j) tmp[j] = arrs[a][perm[j]];
+            memcpy(arrs[a], tmp, sizeof(double) * (size_t)live);
+        }
+        for (int64_t j = 0; j < live; ++j) tmpu[j] = pid[perm[j]];
+        memcpy(pid, tmpu, sizeof(uint32_t) * (size_t)live);
+        *n = live;
+        or_moments(ncell, offsets, vx, vy, vz, mom);
+        if (step >= n_skip && samp) or_sample(ncell, offsets, vx, vy, vz, samp);
+        or_closure(cfg, ncell, mom, nvol, rec, status);
+        or_update(cfg, ncell, offsets, vx, vy, vz, pid, mom, rec, step);
+        or_move(cfg, live, x, y, vx, vy, vz, pid, key, step);
+        int64_t add = or_inject(cfg, step, pid_next, capacity - live, x + live, y + live,
+                                vx + live, vy + live, vz + live, pid + live, key + live);
+        if (add < 0) rc = -2;
+        else *n = live + add;
+    }
+    free(perm); free(offsets); free(tmp); free(tmpu); free(vol); free(nvol);
+    return rc;
 }

@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 /* geometry kinds */
-enum { OR_COUETTE1D = 0, OR_CAVITY2D = 1 };
+enum { OR_COUETTE1D = 0, OR_CAVITY2D = 1, OR_CYLINDER2D = 2 };
 /* particle storage precision */
 enum { OR_F32 = 0, OR_F64 = 1 };
 /* conservation mode after the velocity update */
@@ -33,7 +33,7 @@ enum { OR_EXACT = 0, OR_PAPER = 1 };
 enum { OR_OK = 0, OR_EMPTY = 1, OR_FEW = 2, OR_SINGULAR = 3, OR_NONFINITE = 4,
        OR_NN = 5, OR_NN_FALLBACK = 6 };
 /* Philox stream purposes (third counter word) */
-enum { OR_PURPOSE_COLLISION = 3, OR_PURPOSE_WALL = 4 };
+enum { OR_PURPOSE_COLLISION = 3, OR_PURPOSE_WALL = 4, OR_PURPOSE_INJECT = 5 };
 
 /* Cell record layout, 32 doubles per cell:
  * [N, U1..3, theta, P11 P12 P13 P22 P23 P33,
@@ -66,6 +66,14 @@ typedef struct or_config {
     double T_wall[4];       /* wall temperatures: x_lo, x_hi, y_lo, y_hi */
     double u_wall[4][3];    /* wall velocities */
     uint64_t seed;
+    /* cylinder in an open domain (OR_CYLINDER2D) */
+    double circle[3];       /* centre x, centre y, radius */
+    double T_body;          /* cylinder wall temperature */
+    double n_inf;           /* free-stream number density */
+    double u_inf[3];        /* free-stream velocity */
+    double T_inf;           /* free-stream temperature */
+    double fnum;            /* real molecules per simulator particle */
+    double depth;           /* extent along z */
 } or_config;
 
 /* Philox4x32-10 of Salmon et al. (SC'11): one block of four 32-bit outputs. */
@@ -85,20 +93,36 @@ void or_bin(int32_t ncell, int64_t n, const int32_t* key, int64_t* perm, int32_t
 /* central moments of each cell, record layout above */
 void or_moments(int32_t ncell, const int32_t* offsets, const double* vx, const double* vy,
                 const double* vz, double* mom);
-/* cell gas state: tau = 2 mu / p (eq. tau), eps^2, E = exp(-dt/tau), sigma */
-void or_cell_params(const or_config* cfg, const double* mom_cell, double* tau, double* eps2);
+/* cell gas state: tau = 2 mu / p (eq. tau), eps^2; nvol = real molecules per particle
+ * divided by the cell volume (cfg->fnum_over_vol for uniform cells) */
+void or_cell_params(const or_config* cfg, const double* mom_cell, double nvol, double* tau,
+                    double* eps2);
+/* gas volume of every cell (cylinder: the part of the cell outside the circle, times the
+ * depth; box geometries: dx dy times 1) */
+void or_cell_volumes(const or_config* cfg, double* vol);
 /* normalised 9x9 system of one cell: A (row major 81) and b (9) */
 void or_closure_system(const double* mom_cell, double eps_hat, double* A, double* b);
-/* exact closure of every cell: update records and status */
-void or_closure(const or_config* cfg, int32_t ncell, const double* mom, double* rec,
-                int32_t* status);
+/* exact closure of every cell: update records and status; nvol[ncell] (real molecules
+ * per particle / cell volume) or NULL for cfg->fnum_over_vol everywhere */
+void or_closure(const or_config* cfg, int32_t ncell, const double* mom, const double* nvol,
+                double* rec, int32_t* status);
 /* velocity update of eq. update_vel with conservation (in place) */
 void or_update(const or_config* cfg, int32_t ncell, const int32_t* offsets, double* vx,
                double* vy, double* vz, const uint32_t* pid, const double* mom,
                const double* rec, uint32_t step);
-/* free flight of eq. update_pos with diffuse walls, then the new key (in place) */
+/* free flight of eq. update_pos with diffuse walls, then the new key (in place); in the
+ * open cylinder domain a particle leaving the box gets key = ncell (deleted) */
 void or_move(const or_config* cfg, int64_t n, double* x, double* y, double* vx, double* vy,
              double* vz, const uint32_t* pid, int32_t* key, uint32_t step);
+/* Inflow through the open boundaries of the cylinder domain: candidates drawn uniformly
+ * in a buffer frame of width (|u_inf| + 4 sqrt(2 R T_inf)) dt around the domain with a
+ * Maxwellian(u_inf, T_inf) velocity fly for dt; those ending inside the domain are
+ * appended (x, y, v, pid = *pid_next + candidate index, key).  Returns the number
+ * appended, or -1 if more than room would be needed; *pid_next advances by the number
+ * of candidates. */
+int64_t or_inject(const or_config* cfg, uint32_t step, uint32_t* pid_next, int64_t room,
+                  double* x, double* y, double* vx, double* vy, double* vz, uint32_t* pid,
+                  int32_t* key);
 /* add raw particle sums of each cell to samp */
 void or_sample(int32_t ncell, const int32_t* offsets, const double* vx, const double* vy,
                const double* vz, double* samp);
@@ -109,6 +133,13 @@ void or_sample(int32_t ncell, const int32_t* offsets, const double* vx, const do
 int or_run(const or_config* cfg, int64_t n, double* x, double* y, double* vx, double* vy,
            double* vz, uint32_t* pid, int32_t* key, uint32_t step0, int32_t nsteps,
            uint32_t n_skip, double* mom, double* rec, int32_t* status, double* samp);
+/* The same loop for the open cylinder domain: arrays have room for `capacity`
+ * particles, *n is updated (deletions at the boundaries, injection after the move).
+ * Returns 0, -1 on allocation failure, -2 if the capacity is exceeded. */
+int or_run_open(const or_config* cfg, int64_t capacity, int64_t* n, double* x, double* y,
+                double* vx, double* vy, double* vz, uint32_t* pid, int32_t* key,
+                uint32_t* pid_next, uint32_t step0, int32_t nsteps, uint32_t n_skip,
+                double* mom, double* rec, int32_t* status, double* samp);
 
 #ifdef __cplusplus
 }

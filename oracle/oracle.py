@@ -14,7 +14,7 @@ from . import build_oracle
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
-OR_COUETTE1D, OR_CAVITY2D = 0, 1
+OR_COUETTE1D, OR_CAVITY2D, OR_CYLINDER2D = 0, 1, 2
 OR_F32, OR_F64 = 0, 1
 OR_EXACT, OR_PAPER = 0, 1
 OR_OK, OR_EMPTY, OR_FEW, OR_SINGULAR, OR_NONFINITE, OR_NN, OR_NN_FALLBACK = range(7)
@@ -34,6 +34,9 @@ class OrConfig(C.Structure):
         ("fnum_over_vol", C.c_double), ("eps_hat", C.c_double), ("pivot_tol", C.c_double),
         ("T_wall", C.c_double * 4), ("u_wall", (C.c_double * 3) * 4),
         ("seed", C.c_uint64),
+        ("circle", C.c_double * 3), ("T_body", C.c_double), ("n_inf", C.c_double),
+        ("u_inf", C.c_double * 3), ("T_inf", C.c_double), ("fnum", C.c_double),
+        ("depth", C.c_double),
     ]
 
 
@@ -63,9 +66,15 @@ def _declare(L):
     L.or_keys.argtypes = [cfgp, i64, P(d), P(d), P(i32)]
     L.or_bin.argtypes = [i32, i64, P(i32), P(i64), P(i32)]
     L.or_moments.argtypes = [i32, P(i32), P(d), P(d), P(d), P(d)]
-    L.or_cell_params.argtypes = [cfgp, P(d), P(d), P(d)]
+    L.or_cell_params.argtypes = [cfgp, P(d), d, P(d), P(d)]
+    L.or_cell_volumes.argtypes = [cfgp, P(d)]
+    L.or_inject.argtypes = [cfgp, u32, P(u32), i64, P(d), P(d), P(d), P(d), P(d), P(u32), P(i32)]
+    L.or_inject.restype = i64
+    L.or_run_open.argtypes = [cfgp, i64, P(i64), P(d), P(d), P(d), P(d), P(d), P(u32), P(i32),
+                              P(u32), u32, i32, u32, P(d), P(d), P(i32), P(d)]
+    L.or_run_open.restype = C.c_int
     L.or_closure_system.argtypes = [P(d), d, P(d), P(d)]
-    L.or_closure.argtypes = [cfgp, i32, P(d), P(d), P(i32)]
+    L.or_closure.argtypes = [cfgp, i32, P(d), P(d), P(d), P(i32)]
     L.or_update.argtypes = [cfgp, i32, P(i32), P(d), P(d), P(d), P(u32), P(d), P(d), u32]
     L.or_move.argtypes = [cfgp, i64, P(d), P(d), P(d), P(d), P(d), P(u32), P(i32), u32]
     L.or_sample.argtypes = [i32, P(i32), P(d), P(d), P(d), P(d)]
@@ -86,7 +95,8 @@ def _f64(a):
 def make_config(w: dict) -> OrConfig:
     """Oracle configuration from a workload dictionary (see the package's inputs module)."""
     c = OrConfig()
-    c.geometry = {"couette1d": OR_COUETTE1D, "cavity2d": OR_CAVITY2D}[w["geometry"]]
+    c.geometry = {"couette1d": OR_COUETTE1D, "cavity2d": OR_CAVITY2D,
+                  "cylinder2d": OR_CYLINDER2D}[w["geometry"]]
     c.precision = {"f32": OR_F32, "f64": OR_F64}[w["precision"]]
     c.conserve = {"exact": OR_EXACT, "paper": OR_PAPER}[w.get("conserve", "exact")]
     c.nx, c.ny = int(w["nx"]), int(w["ny"])
@@ -106,6 +116,14 @@ def make_config(w: dict) -> OrConfig:
         for j in range(3):
             c.u_wall[k][j] = float(w["u_wall"][k][j])
     c.seed = int(w["seed"])
+    for k in range(3):
+        c.circle[k] = float(w.get("circle", (0.0, 0.0, 0.0))[k])
+        c.u_inf[k] = float(w.get("u_inf", (0.0, 0.0, 0.0))[k])
+    c.T_body = float(w.get("T_body", 0.0))
+    c.n_inf = float(w.get("n_inf", 0.0))
+    c.T_inf = float(w.get("T_inf", 0.0))
+    c.fnum = float(w.get("fnum", 0.0))
+    c.depth = float(w.get("depth", 1.0))
     return c
 
 
@@ -165,13 +183,22 @@ def moments(offsets, vx, vy, vz):
     return mom
 
 
-def cell_params(w, mom_cell):
+def cell_params(w, mom_cell, nvol=None):
     L = lib()
     cfg = make_config(w)
     m = _f64(mom_cell)
     tau, eps2 = C.c_double(), C.c_double()
-    L.or_cell_params(C.byref(cfg), _p(m, C.c_double), C.byref(tau), C.byref(eps2))
+    nv = float(w["fnum_over_vol"] if nvol is None else nvol)
+    L.or_cell_params(C.byref(cfg), _p(m, C.c_double), nv, C.byref(tau), C.byref(eps2))
     return tau.value, eps2.value
+
+
+def cell_volumes(w):
+    L = lib()
+    cfg = make_config(w)
+    vol = np.empty(int(w["nx"]) * int(w["ny"]), dtype=np.float64)
+    L.or_cell_volumes(C.byref(cfg), _p(vol, C.c_double))
+    return vol
 
 
 def closure_system(mom_cell, eps_hat):
@@ -183,14 +210,16 @@ def closure_system(mom_cell, eps_hat):
     return A.reshape(9, 9), b
 
 
-def closure(w, mom):
+def closure(w, mom, nvol=None):
     L = lib()
     cfg = make_config(w)
     mom = _f64(mom)
     ncell = mom.shape[0]
     rec = np.empty((ncell, REC_STRIDE), dtype=np.float64)
     st = np.empty(ncell, dtype=np.int32)
-    L.or_closure(C.byref(cfg), ncell, _p(mom, C.c_double), _p(rec, C.c_double), _p(st, C.c_int32))
+    nv = _p(_f64(nvol), C.c_double) if nvol is not None else None
+    L.or_closure(C.byref(cfg), ncell, _p(mom, C.c_double), nv, _p(rec, C.c_double),
+                 _p(st, C.c_int32))
     return rec, st
 
 
@@ -261,3 +290,53 @@ def run(w, state, step0, nsteps, n_skip=0, samp=None):
     if rc != 0:
         raise MemoryError("oracle run failed to allocate")
     return s, mom, rec, st, samp
+
+
+def inject(w, step, pid_next, room=10_000_000):
+    """Returns (dict of appended arrays, new pid_next)."""
+    L = lib()
+    cfg = make_config(w)
+    a = {k: np.empty(room) for k in ("x", "y", "vx", "vy", "vz")}
+    pid = np.empty(room, dtype=np.uint32)
+    key = np.empty(room, dtype=np.int32)
+    pn = C.c_uint32(int(pid_next))
+    k = L.or_inject(C.byref(cfg), int(step), C.byref(pn), room, *(_p(a[q], C.c_double) for q in
+                    ("x", "y", "vx", "vy", "vz")), _p(pid, C.c_uint32), _p(key, C.c_int32))
+    if k < 0:
+        raise MemoryError("oracle injection room exceeded")
+    out = {q: a[q][:k].copy() for q in a}
+    out["pid"] = pid[:k].copy()
+    out["key"] = key[:k].copy()
+    return out, pn.value
+
+
+def run_open(w, state, pid_next, step0, nsteps, capacity, n_skip=0, samp=None):
+    """Open-domain loop (cylinder).  Returns (state, pid_next, mom, rec, status, samp)."""
+    L = lib()
+    cfg = make_config(w)
+    ncell = int(w["nx"]) * int(w["ny"])
+    n0 = state["x"].shape[0]
+    s = {}
+    for k in ("x", "y", "vx", "vy", "vz"):
+        s[k] = np.zeros(capacity)
+        s[k][:n0] = state[k]
+    s["pid"] = np.zeros(capacity, dtype=np.uint32)
+    s["pid"][:n0] = state["pid"]
+    s["key"] = np.zeros(capacity, dtype=np.int32)
+    s["key"][:n0] = state["key"]
+    n = C.c_int64(n0)
+    pn = C.c_uint32(int(pid_next))
+    mom = np.zeros((ncell, MOM_STRIDE))
+    rec = np.zeros((ncell, REC_STRIDE))
+    st = np.zeros(ncell, dtype=np.int32)
+    if samp is None:
+        samp = np.zeros((ncell, SAMP_STRIDE))
+    rc = L.or_run_open(C.byref(cfg), capacity, C.byref(n), *(_p(s[k], C.c_double) for k in
+                       ("x", "y", "vx", "vy", "vz")), _p(s["pid"], C.c_uint32),
+                       _p(s["key"], C.c_int32), C.byref(pn), int(step0), int(nsteps), int(n_skip),
+                       _p(mom, C.c_double), _p(rec, C.c_double), _p(st, C.c_int32),
+                       _p(samp, C.c_double))
+    if rc != 0:
+        raise RuntimeError(f"oracle open run failed ({rc})")
+    out = {k: v[:n.value].copy() for k, v in s.items()}
+    return out, pn.value, mom, rec, st, samp

@@ -82,6 +82,54 @@ def cavity(kn=1.0, ncell=100, ppc=100, cell=1e-5, lid=50.0, precision="f32", n_s
     return w
 
 
+def cylinder(cell=2e-3, nx=400, ny=300, radius=0.1, mach=10.0, T_inf=200.0, n_inf=1e20,
+             T_body=500.0, fnum=2.5e12, dt=5e-7, precision="f32", n_steps=10000, n_skip=5000,
+             seed=1, **kw):
+    """Hypersonic flow of argon past a circular cylinder (Sec. "hypersonic cylinder"):
+    Mach 10 at 200 K, n = 1e20 m^-3, diffuse isothermal wall at 500 K, radius 0.1 m at
+    the origin in the box [-0.3, 0.5] x [-0.3, 0.3] m (400 x 300 cells of 2 mm), open
+    boundaries with free-stream inflow, 1 m depth.  fnum real molecules per particle
+    gives about 160 particles per free-stream cell."""
+    R = KB / MASS_AR
+    a_inf = math.sqrt(5.0 / 3.0 * R * T_inf)
+    u = mach * a_inf
+    w = _base(name=f"cylinder2d_{nx}x{ny}_M{mach}", geometry="cylinder2d", precision=precision,
+              nx=nx, ny=ny, x0=-0.3, y0=-0.3, lx=nx * cell, ly=ny * cell, dx=cell, dy=cell,
+              dt=dt, circle=(0.0, 0.0, radius), T_body=T_body, n_inf=n_inf, u_inf=(u, 0.0, 0.0),
+              T_inf=T_inf, fnum=fnum, depth=1.0, fnum_over_vol=fnum / (cell * cell),
+              T_wall=[T_inf] * 4, u_wall=[[0.0] * 3] * 4, T_init=T_inf, n_steps=n_steps,
+              n_skip=n_skip, seed=seed, ppc=n_inf * cell * cell / fnum)
+    w.update(kw)
+    return w
+
+
+def freestream_state(w, seed=None):
+    """Uniform free stream in the gas part of the cylinder domain: the expected number
+    n_inf (box area - pi R^2) depth / fnum of particles, uniform positions (those falling
+    inside the circle are redrawn), Maxwellian(u_inf, T_inf) velocities."""
+    seed = int(w["seed"] if seed is None else seed)
+    rng = np.random.default_rng(seed)
+    cx, cy, rad = w["circle"]
+    area = w["lx"] * w["ly"] - math.pi * rad * rad
+    n = int(round(w["n_inf"] * area * w["depth"] / w["fnum"]))
+    x = np.empty(n)
+    y = np.empty(n)
+    filled = 0
+    while filled < n:
+        m = n - filled
+        xs = w["x0"] + rng.random(m) * w["lx"]
+        ys = w["y0"] + rng.random(m) * w["ly"]
+        ok = (xs - cx) ** 2 + (ys - cy) ** 2 > rad * rad
+        k = int(ok.sum())
+        x[filled:filled + k] = xs[ok]
+        y[filled:filled + k] = ys[ok]
+        filled += k
+    s = math.sqrt(KB / MASS_AR * w["T_inf"])
+    v = rng.standard_normal((3, n)) * s + np.asarray(w["u_inf"])[:, None]
+    return dict(x=_round(w, x), y=_round(w, y), vx=_round(w, v[0]), vy=_round(w, v[1]),
+                vz=_round(w, v[2]), pid=np.arange(n, dtype=np.uint32))
+
+
 def ncells(w):
     return int(w["nx"]) * int(w["ny"])
 

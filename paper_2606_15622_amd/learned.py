@@ -1,0 +1,173 @@
+"""Learned closure pipeline on one GPU (the surrogate of Secs. "Phase 0"-"Phase 3").
+
+harvest()      runs the exact-closure loop and keeps the moment records of solved cells
+               (the paper's Phase 0 saves the physics solver's inputs and outputs);
+dataset()      features, targets and normalised systems by the library's kernels;
+fit_scalers()  per-column mean and standard deviation (the paper's StandardScaler);
+train()        Adam on the MSE of standardised targets (or the closure residual) with a
+               random 10 % split used only for early stopping (patience) and keeping the
+               best parameters (the paper's EarlyStopping / ModelCheckpoint);
+LearnedSimulation  the loop of Algorithm "Accelerated ML Simulation Loop": the exact
+               build+solve replaced by fp_closure_nn, with the per-cell residual check
+               falling back to the exact solve on the device.
+Every arithmetic step runs in libfpgpu kernels; torch provides buffers, index
+shuffles and the scaler statistics.
+"""
+import math
+
+import numpy as np
+import torch
+
+from . import fpgpu as F
+
+NF, NO = F.NN_FEATURES, F.NN_OUTPUTS
+
+
+def harvest(w, state, n_transient, n_samples, every=1, seed_offset=0):
+    """Moment records [k][32] (device, FP64) of the cells the exact closure solved."""
+    sim = F.Simulation(w, state)
+    s = 0
+    for _ in range(n_transient):
+        sim.step(s)
+        s += 1
+    keep = []
+    for i in range(n_samples):
+        sim.step(s)
+        s += 1
+        if i % every == 0:
+            ok = sim.status == F.CELL_OK
+            keep.append(sim.mom[ok].clone())
+    return torch.cat(keep, 0)
+
+
+def dataset(w, mom):
+    """(feats [n][32] f32, targets [n][16] f32, sys [n][90] f64) of moment records."""
+    n = mom.shape[0]
+    wd = dict(w)
+    wd.update(geometry="couette1d", nx=n, ny=1, lx=float(w["dx"]) * n, ly=1.0, dy=1.0)
+    ctx = F.Context(wd, 1)
+    rec = torch.zeros((n, F.REC_STRIDE), dtype=torch.float64, device=mom.device)
+    st = torch.zeros(n, dtype=torch.int32, device=mom.device)
+    ctx.closure_solve(mom, rec, st)
+    feats = torch.zeros((n, NF), dtype=torch.float32, device=mom.device)
+    tg = torch.zeros((n, NO), dtype=torch.float32, device=mom.device)
+    sys = torch.zeros((n, 90), dtype=torch.float64, device=mom.device)
+    ctx.nn_features(mom, n, feats)
+    ctx.nn_targets(rec, n, tg)
+    ctx.closure_build(mom, n, sys)
+    ok = st == F.CELL_OK
+    return feats[ok].contiguous(), tg[ok].contiguous(), sys[ok].contiguous()
+
+
+def fit_scalers(feats, tg):
+    xm = feats.double().mean(0)
+    xs = feats.double().std(0)
+    ym = tg.double().mean(0)
+    ys = tg.double().std(0)
+    xs = torch.where(xs > 1e-6, xs, torch.ones_like(xs))
+    ys = torch.where(ys > 1e-9, ys, torch.ones_like(ys))
+    ym[9:] = 0.0
+    ys[9:] = 1.0
+    return xm.float(), xs.float(), ym.float(), ys.float()
+
+
+def init_params(scalers, seed=0, device="cuda"):
+    """Glorot-uniform weights, zero biases, then the scalers (flat layout of fp.h)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((128, 32), (128, 128), (128, 128), (16, 128)):
+        lim = math.sqrt(6.0 / (fan_in + fan_out))
+        Wm = rng.uniform(-lim, lim, (fan_out, fan_in))
+        if fan_in == 32:
+            Wm[:, 27:] = 0.0
+        if fan_out == 16:
+            Wm[9:, :] = 0.0
+        parts += [Wm.ravel(), np.zeros(fan_out)]
+    p = torch.tensor(np.concatenate(parts), dtype=torch.float32, device=device)
+    return torch.cat([p] + [t.to(device) for t in scalers])
+
+
+def train(w, params, feats, tg, sys=None, loss_kind=F.LOSS_MSE, epochs=100, batch=4096,
+          lr=1e-4, patience=10, val_frac=0.1, seed=0, log=None):
+    """Adam training by the library's MFMA kernels; returns (best params, history)."""
+    dev = feats.device
+    n = feats.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    perm = torch.randperm(n, generator=g).to(dev)
+    nval = max(int(n * val_frac), 1)
+    vi, ti = perm[:nval], perm[nval:]
+    ctx = F.Context(dict(w, geometry="couette1d", nx=1, ny=1), 1)
+    net = F.Network(ctx, max(batch, nval))
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    grad = torch.zeros(F.NN_PARAMS, dtype=torch.float32, device=dev)
+    vfe, vtg = feats[vi].contiguous(), tg[vi].contiguous()
+    vsy = sys[vi].contiguous() if sys is not None else None
+    best, best_p, bad, t = float("inf"), params.clone(), 0, 0
+    hist = []
+    for ep in range(epochs):
+        order = ti[torch.randperm(ti.shape[0], generator=g).to(dev)]
+        for b0 in range(0, order.shape[0], batch):
+            idx = order[b0:b0 + batch]
+            t += 1
+            net.train_step(params, m, v, t, lr, feats[idx].contiguous(), tg[idx].contiguous(),
+                           sys[idx].contiguous() if sys is not None else None, idx.shape[0],
+                           loss_kind, loss)
+        net.grad(params, vfe, vtg, vsy, nval, loss_kind, grad, loss)
+        vl = float(loss)
+        hist.append(vl)
+        if log:
+            log(f"epoch {ep} val_loss {vl:.6g}")
+        if vl < best:
+            best, best_p, bad = vl, params.clone(), 0
+        else:
+            bad += 1
+            if bad >= patience:
+                break
+    return best_p, hist
+
+
+class LearnedSimulation(F.Simulation):
+    """The loop with the learned closure (or the Langevin drift when net is None and
+    langevin is set), everything else as in Simulation."""
+
+    def __init__(self, w, state, params=None, tol_abs=0.05, tol_rel=0.05, langevin=False,
+                 device="cuda"):
+        if langevin:
+            w = dict(w, n_min=1 << 30)
+        super().__init__(w, state, device)
+        self.net = None
+        if params is not None:
+            self.net = F.Network(self.ctx, 0)
+            self.net.load(params)
+        self.tol = (tol_abs, tol_rel)
+
+    def step(self, s, sample=False):
+        self.ctx.bin(self.a, self.b, self.offsets)
+        self.a, self.b = self.b, self.a
+        self.ctx.moments(self.a, self.offsets, self.mom)
+        if sample:
+            self.ctx.sample(self.mom, self.samp)
+        if self.net is not None:
+            self.net.closure(self.mom, self.rec, self.status, *self.tol)
+        else:
+            self.ctx.closure_solve(self.mom, self.rec, self.status)
+        self.ctx.step(self.a, self.offsets, self.mom, self.rec, s, F.STEP_COLLIDE | F.STEP_MOVE)
+
+
+def fields(w, samp):
+    """Time-averaged |U|, T, rho/rho0, p/p0 per cell from the sampling sums (host)."""
+    s = samp.double().cpu().numpy()
+    N = np.maximum(s[:, 0], 1.0)
+    U = s[:, 1:4] / N[:, None]
+    R = w["kB"] / w["mass"]
+    T = ((s[:, 4] + s[:, 7] + s[:, 9]) / N - (U * U).sum(1)) / (3.0 * R)
+    nsamp = np.maximum(s[:, 13], 1.0)
+    rho = N / nsamp / float(w["ppc"])
+    p = rho * T / w["T_init"]
+    return {"U": np.linalg.norm(U, axis=1), "T": T, "rho": rho, "p": p}
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
