@@ -49,7 +49,7 @@ extern "C" {
 #define FP_EDEVICE (-3)    /* a HIP call failed; text in fp_last_error */
 #define FP_ECAPACITY (-4)  /* more particles than the context's capacity */
 
-enum fp_geometry { FP_COUETTE1D = 0, FP_CAVITY2D = 1 };
+enum fp_geometry { FP_COUETTE1D = 0, FP_CAVITY2D = 1, FP_CYLINDER2D = 2 };
 enum fp_precision { FP_F32 = 0, FP_F64 = 1 };
 enum fp_conserve { FP_EXACT = 0, FP_PAPER = 1 };
 
@@ -90,6 +90,16 @@ typedef struct fp_config {
     double T_wall[4];        /* wall temperatures: x = x0, x = x0+lx, y = y0, y = y0+ly */
     double u_wall[4][3];     /* wall velocities, same order */
     uint64_t seed;           /* Philox4x32-10 key */
+    /* open domain around a cylinder (FP_CYLINDER2D): the box boundaries are open (a
+     * particle whose flight ends outside is deleted), free stream enters by fp_inject */
+    double circle[3];        /* cylinder centre x, y and radius [m] */
+    double T_body;           /* cylinder wall temperature [K] (diffuse, isothermal) */
+    double n_inf;            /* free-stream number density [1/m^3] */
+    double u_inf[3];         /* free-stream velocity [m/s] */
+    double T_inf;            /* free-stream temperature [K] */
+    double fnum;             /* real molecules per particle (cylinder: density uses the
+                                gas volume of each cut cell; fnum_over_vol is ignored) */
+    double depth;            /* extent along z [m] */
 } fp_config;
 
 /* Particle arrays in structure-of-arrays form.  x, y, vx, vy, vz are float
@@ -117,9 +127,10 @@ int64_t fp_error_count(fp_ctx* ctx, hipStream_t s);
 /* Stable counting sort by cell key (the sort of "sort_and_calc_moments" in Algorithm
  * "Baseline Physics Simulation Loop"): dst receives the particles of src ordered by
  * key, particles of one cell in their order in src.  offsets[ncell+1] receives the
- * cell start indices.  perm (optional, may be NULL) receives for every slot of dst
- * the index in src it came from.  src and dst must not alias.  Keys outside
- * [0, ncell) are counted by fp_error_count and such particles are dropped. */
+ * cell start indices; offsets[ncell] is the number of particles kept.  perm (optional,
+ * may be NULL) receives for every slot of dst the index in src it came from.  src and
+ * dst must not alias.  Particles with key == ncell (deleted) are dropped; keys outside
+ * [0, ncell] are counted by fp_error_count and dropped as well. */
 int fp_bin(fp_ctx* ctx, const fp_particles* src, fp_particles* dst, int32_t* offsets,
            int32_t* perm, hipStream_t s);
 
@@ -134,7 +145,9 @@ int fp_moments(fp_ctx* ctx, const fp_particles* p, const int32_t* offsets, doubl
 int fp_closure_solve(fp_ctx* ctx, const double* mom, double* rec, int32_t* status,
                      hipStream_t s);
 
-/* Per-particle step on particles sorted by cell, as selected by flags:
+/* Per-particle step on particles sorted by cell, as selected by flags (in the open
+ * cylinder domain MOVE also reflects diffusely off the body at T_body and gives a
+ * particle whose flight ends outside the box the key ncell):
  *   FP_STEP_COLLIDE  eq. update_vel with N of eq. update_N, Philox normals with counter
  *                    (pid, step, 3, 0); then every cell is recentred on U and its energy
  *                    restored exactly (FP_EXACT) or by alpha of eq. update_alpha
@@ -145,6 +158,26 @@ int fp_closure_solve(fp_ctx* ctx, const double* mom, double* rec, int32_t* statu
  * mom/rec may be NULL when COLLIDE is not set; offsets may be NULL for MOVE/KEYS only. */
 int fp_step(fp_ctx* ctx, fp_particles* p, const int32_t* offsets, const double* mom,
             const double* rec, uint64_t step, uint32_t flags, hipStream_t s);
+
+/* Free-stream inflow of the open cylinder domain (boundary step of the loop).
+ * Candidates are drawn uniformly in a buffer frame of width
+ * (|u_inf| + 4 sqrt(2 R T_inf)) dt around the box (four rectangles: x-low, x-high, y-low,
+ * y-high) with Maxwellian(u_inf, T_inf) velocities (Philox counter (pid, step, 5, 0|2);
+ * the count of rectangle r is floor(lambda_r) plus a Bernoulli remainder drawn with
+ * counter (r, step, 5, 1), lambda_r = n_inf area_r depth / fnum); they fly for dt and
+ * those ending inside the box are kept.  fp_inject writes fp_inject_slots(ctx) slots at
+ * indices [at, at + slots) of p (capacity must allow it): kept candidates with their
+ * cell key, the rest with key = ncell so that the next fp_bin drops them.  pid_next
+ * (device, one uint32) is the id of the first candidate and advances by the number of
+ * candidates.  Returns FP_EINVAL for other geometries. */
+int fp_inject(fp_ctx* ctx, fp_particles* p, int64_t at, uint32_t* pid_next, uint64_t step,
+              hipStream_t s);
+/* Number of slots fp_inject writes per call (a configuration constant). */
+int64_t fp_inject_slots(const fp_ctx* ctx);
+/* Gas volume of every cell [m^3] into vol[ncell] (device): cylinder cells lose the part
+ * covered by the body (exact disk-rectangle areas, cells covered up to 1e-12 of their
+ * area count as solid, volume 0); box geometries dx dy (1 m depth). */
+int fp_cell_volumes(fp_ctx* ctx, double* vol, hipStream_t s);
 
 /* Time averaging (the "average_results" step): adds the raw sums of every cell,
  * reconstructed from mom, to samp (layout samp above). */

@@ -1,7 +1,9 @@
 // fp_api.hip -- context management and argument checking of the C ABI (include/fp.h).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <new>
+#include <vector>
 
 #include "fp_internal.h"
 
@@ -26,7 +28,8 @@ using namespace fpg;
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 static int validate(const fp_config* g, std::string& why) {
-    if (g->geometry != FP_COUETTE1D && g->geometry != FP_CAVITY2D) return why = "geometry", 0;
+    if (g->geometry != FP_COUETTE1D && g->geometry != FP_CAVITY2D && g->geometry != FP_CYLINDER2D)
+        return why = "geometry", 0;
     if (g->precision != FP_F32 && g->precision != FP_F64) return why = "precision", 0;
     if (g->conserve != FP_EXACT && g->conserve != FP_PAPER) return why = "conserve", 0;
     if (g->nx < 1 || g->ny < 1 || (int64_t)g->nx * g->ny > (1 << 28)) return why = "grid", 0;
@@ -40,7 +43,60 @@ static int validate(const fp_config* g, std::string& why) {
     for (int w = 0; w < 4; ++w)
         if (!finite_pos(g->T_wall[w])) return why = "wall temperature", 0;
     if (!(g->eps_hat >= 0.0) || !(g->pivot_tol >= 0.0)) return why = "eps_hat/pivot_tol", 0;
+    if (g->geometry == FP_CYLINDER2D) {
+        if (!(g->circle[2] >= 0.0) || !finite_pos(g->T_body) || !finite_pos(g->n_inf) ||
+            !finite_pos(g->T_inf) || !finite_pos(g->fnum) || !finite_pos(g->depth))
+            return why = "cylinder parameters", 0;
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(g->u_inf[k]) || !std::isfinite(g->circle[k])) return why = "cylinder", 0;
+    }
     return 1;
+}
+
+// ---- exact gas volume of the cells of the cylinder domain ------------------------------
+// Coordinates relative to the circle centre.  I(x) = int_{-R}^{x} sqrt(R^2 - X^2) dX and
+// G(x, y) = area of the disk part with X <= x and Y <= y; a rectangle's covered area is
+// G(xb,yb) - G(xa,yb) - G(xb,ya) + G(xa,ya).
+static double half_int(double x, double R) {
+    if (x <= -R) return 0.0;
+    if (x >= R) return 0.5 * M_PI * R * R;
+    return 0.5 * (x * std::sqrt(R * R - x * x) + R * R * std::asin(x / R)) + 0.25 * M_PI * R * R;
+}
+
+static double corner_area(double x, double y, double R) {
+    if (x <= -R || y <= -R || R <= 0.0) return 0.0;
+    if (x > R) x = R;
+    if (y >= R) return 2.0 * half_int(x, R);
+    const double a = std::sqrt(R * R - y * y);
+    if (y >= 0.0) {   // chord 2h outside |X| < a, y + h inside
+        double t = 2.0 * half_int(std::min(x, -a), R);
+        if (x > -a) {
+            const double x2 = std::min(x, a);
+            t += y * (x2 + a) + (half_int(x2, R) - half_int(-a, R));
+        }
+        if (x > a) t += 2.0 * (half_int(x, R) - half_int(a, R));
+        return t;
+    }
+    if (x <= -a) return 0.0;   // y < 0: only |X| < a contributes, y + h
+    const double x2 = std::min(x, a);
+    return y * (x2 + a) + (half_int(x2, R) - half_int(-a, R));
+}
+
+static void gas_volumes(const fp_config& g, std::vector<double>& vol) {
+    const double cx = g.circle[0], cy = g.circle[1], R = g.circle[2];
+    const double full = g.dx * g.dy;
+    vol.assign((size_t)g.nx * g.ny, full);
+    if (g.geometry != FP_CYLINDER2D) return;
+    for (int32_t ky = 0; ky < g.ny; ++ky)
+        for (int32_t kx = 0; kx < g.nx; ++kx) {
+            const double xa = g.x0 + kx * g.dx - cx, xb = xa + g.dx;
+            const double ya = g.y0 + ky * g.dy - cy, yb = ya + g.dy;
+            const double cov = corner_area(xb, yb, R) - corner_area(xa, yb, R) -
+                               corner_area(xb, ya, R) + corner_area(xa, ya, R);
+            double v = full - cov;
+            if (v < 1e-12 * full) v = 0.0;
+            vol[(size_t)ky * g.nx + kx] = v * g.depth;
+        }
 }
 
 template <typename T>
@@ -71,6 +127,38 @@ extern "C" int fp_init(const fp_config* cfg, fp_ctx** out) {
               dalloc(&c->gidx, cap) && dalloc(&c->blocksum, 2 * 8192) &&
               dalloc(&c->errcount, 1);
     if (ok) ok = hipMemset(c->errcount, 0, sizeof(unsigned long long)) == hipSuccess;
+    if (ok && cfg->geometry == FP_CYLINDER2D) {
+        std::vector<double> vol, nvol;
+        gas_volumes(*cfg, vol);
+        const double full = cfg->dx * cfg->dy * cfg->depth;
+        nvol.resize(vol.size());
+        for (size_t i = 0; i < vol.size(); ++i) nvol[i] = cfg->fnum / (vol[i] > 0.0 ? vol[i] : full);
+        ok = dalloc(&c->vol, vol.size()) && dalloc(&c->nvol, vol.size()) && dalloc(&c->inj, 16);
+        if (ok) ok = hipMemcpy(c->vol, vol.data(), sizeof(double) * vol.size(), hipMemcpyHostToDevice) == hipSuccess;
+        if (ok) ok = hipMemcpy(c->nvol, nvol.data(), sizeof(double) * vol.size(), hipMemcpyHostToDevice) == hipSuccess;
+        // inflow rectangles: a frame of width (|u_inf| + 4 sqrt(2 R T_inf)) dt around the box
+        const double RT = cfg->kB / cfg->mass * cfg->T_inf;
+        const double um = std::sqrt(cfg->u_inf[0] * cfg->u_inf[0] + cfg->u_inf[1] * cfg->u_inf[1] +
+                                    cfg->u_inf[2] * cfg->u_inf[2]);
+        const double w = (um + 4.0 * std::sqrt(2.0 * RT)) * cfg->dt;
+        const double x0 = cfg->x0, y0 = cfg->y0, x1 = cfg->x0 + cfg->lx, y1 = cfg->y0 + cfg->ly;
+        const double rect[4][4] = {{x0 - w, x0, y0 - w, y1 + w}, {x1, x1 + w, y0 - w, y1 + w},
+                                   {x0, x1, y0 - w, y0}, {x0, x1, y1, y1 + w}};
+        c->inj_slot0[0] = 0;
+        for (int r = 0; r < 4; ++r) {
+            for (int k = 0; k < 4; ++k) c->inj_rect[r][k] = rect[r][k];
+            c->inj_lambda[r] = cfg->n_inf * ((rect[r][1] - rect[r][0]) * (rect[r][3] - rect[r][2])) *
+                               cfg->depth / cfg->fnum;
+            const double slots = std::floor(c->inj_lambda[r]) + 1.0;
+            if (!(slots < 1e8)) ok = false;
+            c->inj_slot0[r + 1] = c->inj_slot0[r] + (ok ? (int32_t)slots : 0);
+        }
+    } else if (ok) {
+        std::vector<double> vol;
+        gas_volumes(*cfg, vol);
+        ok = dalloc(&c->vol, vol.size()) &&
+             hipMemcpy(c->vol, vol.data(), sizeof(double) * vol.size(), hipMemcpyHostToDevice) == hipSuccess;
+    }
     if (ok) ok = hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         fp_destroy(c);
@@ -92,6 +180,9 @@ extern "C" void fp_destroy(fp_ctx* c) {
     (void)hipFree(c->gidx);
     (void)hipFree(c->blocksum);
     (void)hipFree(c->errcount);
+    (void)hipFree(c->vol);
+    (void)hipFree(c->nvol);
+    (void)hipFree(c->inj);
     delete c;
 }
 
@@ -110,7 +201,7 @@ static bool particles_ok(const fp_ctx* c, const fp_particles* p, bool need_pos) 
     if (!p || p->n < 0 || p->n > c->cfg.capacity) return false;
     if (p->n == 0) return true;
     if (!p->vx || !p->vy || !p->vz || !p->pid || !p->key) return false;
-    if (need_pos && (!p->x || (c->cfg.geometry == FP_CAVITY2D && !p->y))) return false;
+    if (need_pos && (!p->x || (c->cfg.geometry != FP_COUETTE1D && !p->y))) return false;
     return true;
 }
 
@@ -119,7 +210,7 @@ extern "C" int fp_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int
     if (!c || !offsets || !particles_ok(c, src, true) || !dst)
         return set_err(c, FP_EINVAL, "fp_bin: bad argument");
     if (src->n > 0 && (!dst->vx || !dst->vy || !dst->vz || !dst->pid || !dst->key || !dst->x ||
-                       (c->cfg.geometry == FP_CAVITY2D && !dst->y)))
+                       (c->cfg.geometry != FP_COUETTE1D && !dst->y)))
         return set_err(c, FP_EINVAL, "fp_bin: bad destination");
     if (src->vx == dst->vx || src->x == dst->x || src->pid == dst->pid)
         return set_err(c, FP_EINVAL, "fp_bin: src and dst alias");
@@ -155,4 +246,29 @@ extern "C" int fp_step(fp_ctx* c, fp_particles* p, const int32_t* offsets, const
 extern "C" int fp_sample(fp_ctx* c, const double* mom, double* samp, hipStream_t s) {
     if (!c || !mom || !samp) return set_err(c, FP_EINVAL, "fp_sample: bad argument");
     return launch_sample(c, mom, samp, s);
+}
+
+extern "C" int64_t fp_inject_slots(const fp_ctx* c) {
+    if (!c || c->cfg.geometry != FP_CYLINDER2D) return 0;
+    return c->inj_slot0[4];
+}
+
+extern "C" int fp_inject(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_next,
+                         uint64_t step, hipStream_t s) {
+    if (!c || !p || !pid_next || c->cfg.geometry != FP_CYLINDER2D)
+        return set_err(c, FP_EINVAL, "fp_inject: bad argument or geometry");
+    if (at < 0 || at + c->inj_slot0[4] > c->cfg.capacity)
+        return set_err(c, FP_ECAPACITY, "fp_inject: capacity exceeded");
+    if (!p->x || !p->y || !p->vx || !p->vy || !p->vz || !p->pid || !p->key)
+        return set_err(c, FP_EINVAL, "fp_inject: bad particles");
+    if (step > 0xFFFFFFFFull) return set_err(c, FP_EINVAL, "fp_inject: step beyond 2^32");
+    return launch_inject(c, p, at, pid_next, (uint32_t)step, s);
+}
+
+extern "C" int fp_cell_volumes(fp_ctx* c, double* vol, hipStream_t s) {
+    if (!c || !vol) return set_err(c, FP_EINVAL, "fp_cell_volumes: bad argument");
+    if (hipMemcpyAsync(vol, c->vol, sizeof(double) * (size_t)c->ncell, hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+        return set_err(c, FP_EDEVICE, "fp_cell_volumes: copy failed");
+    return FP_OK;
 }

@@ -38,10 +38,10 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_wave_kernel(
     int32_t k = -1;
     if (valid) {
         k = key[p];
-        if (k < 0 || k >= ncell) {
+        if (k < 0 || k > ncell) {
             if (!PLACE) atomicAdd(errcount, 1ull);
             k = ncell;  // dropped
-        }
+        }                // k == ncell: deleted particle, dropped
     }
     uint64_t active = __ballot(valid);
     while (active) {

@@ -20,7 +20,8 @@ __global__ __launch_bounds__(CL_BLOCK) void closure_kernel(fp_config g, int32_t 
                                                             int32_t* __restrict__ status,
                                                             const float* __restrict__ ynn,
                                                             const float* __restrict__ ysec,
-                                                            double tol_abs, double tol_rel) {
+                                                            double tol_abs, double tol_rel,
+                                                            const double* __restrict__ nvol) {
     const int32_t cell = blockIdx.x * CL_BLOCK + threadIdx.x;
     if (cell >= ncell) return;
     double m[31];
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(CL_BLOCK) void closure_kernel(fp_config g, int32_t 
         out[R_E] = 1.0;
         out[R_TH] = finite ? theta : 0.0;
     } else {
-        const double tau = cell_tau(g, N, theta);
+        const double tau = cell_tau(g, N * (nvol ? nvol[cell] : g.fnum_over_vol), theta);
         const double eps2 = g.eps_hat / (theta * tau);
         double y[9];
         if (N < (double)g.n_min) {
@@ -109,7 +110,8 @@ __global__ __launch_bounds__(CL_BLOCK) void closure_kernel(fp_config g, int32_t 
 int launch_closure(fp_ctx* c, const double* mom, double* rec, int32_t* status, hipStream_t s) {
     const int grid = (c->ncell + CL_BLOCK - 1) / CL_BLOCK;
     hipLaunchKernelGGL(closure_kernel<false>, dim3(grid), dim3(CL_BLOCK), 0, s, c->cfg, c->ncell,
-                       mom, rec, status, (const float*)nullptr, (const float*)nullptr, 0.0, 0.0);
+                       mom, rec, status, (const float*)nullptr, (const float*)nullptr, 0.0, 0.0,
+                       (const double*)c->nvol);
     return check_launch(c, "fp_closure_solve");
 }
 
@@ -118,7 +120,7 @@ int launch_closure_nn(fp_ctx* c, const float* ynn, const float* ysec, double tol
                       hipStream_t s) {
     const int grid = (c->ncell + CL_BLOCK - 1) / CL_BLOCK;
     hipLaunchKernelGGL(closure_kernel<true>, dim3(grid), dim3(CL_BLOCK), 0, s, c->cfg, c->ncell,
-                       mom, rec, status, ynn, ysec, tol_abs, tol_rel);
+                       mom, rec, status, ynn, ysec, tol_abs, tol_rel, (const double*)c->nvol);
     return check_launch(c, "fp_closure_nn (check)");
 }
 

@@ -116,9 +116,10 @@ __device__ __forceinline__ bool lu_solve(CellSystem& s, double tol, double y[9])
 }
 
 // cell gas state: tau = 2 mu / p (eq. tau), VHS viscosity, eps^2 = eps_hat/(theta tau)
-__device__ __forceinline__ double cell_tau(const fp_config& g, double n, double theta) {
+// ndens: real number density of the cell (particles times molecules per particle / volume)
+__device__ __forceinline__ double cell_tau(const fp_config& g, double ndens, double theta) {
     const double T = theta * g.mass / g.kB;
-    const double p = n * g.fnum_over_vol * g.kB * T;
+    const double p = ndens * g.kB * T;
     const double mu = g.mu_ref * pow(T / g.T_ref, g.omega);
     return 2.0 * mu / p;
 }

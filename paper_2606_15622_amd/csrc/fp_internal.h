@@ -12,7 +12,7 @@ namespace fpg {
 constexpr int MOM = 32, REC = 16, SAMP = 16;
 enum { M_N = 0, M_U = 1, M_TH = 4, M_P = 5, M_T = 11, M_R = 21, M_W = 27, M_H = 30 };
 enum { R_C = 0, R_G = 6, R_TAU = 9, R_TH = 10, R_E = 11, R_EPS2 = 12, R_SIG = 13, R_ST = 14 };
-enum { PURPOSE_COLLISION = 3, PURPOSE_WALL = 4 };
+enum { PURPOSE_COLLISION = 3, PURPOSE_WALL = 4, PURPOSE_INJECT = 5 };
 
 constexpr double TWO_PI = 6.283185307179586;
 
@@ -32,6 +32,13 @@ struct fp_ctx {
     int32_t* gidx = nullptr;     // [capacity] slot list for cells too large for LDS
     int32_t* blocksum = nullptr; // scan partials
     unsigned long long* errcount = nullptr;  // invalid keys
+    // open cylinder domain
+    double* vol = nullptr;       // [ncell] gas volume of every cell
+    double* nvol = nullptr;      // [ncell] real molecules per particle / gas volume
+    int32_t* inj = nullptr;      // [16] per-step counts of the inflow rectangles
+    double inj_rect[4][4] = {};  // x_a, x_b, y_a, y_b of the four inflow rectangles
+    double inj_lambda[4] = {};   // expected candidates per rectangle and step
+    int32_t inj_slot0[5] = {};   // slot prefix: floor(lambda_r) + 1 slots per rectangle
     std::string err;
 };
 
@@ -136,6 +143,8 @@ int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* o
 int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,
                    hipStream_t s);
 int launch_closure(fp_ctx* c, const double* mom, double* rec, int32_t* status, hipStream_t s);
+int launch_inject(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_next, uint32_t step,
+                  hipStream_t s);
 int launch_step(fp_ctx* c, fp_particles* p, const int32_t* offsets, const double* mom,
                 const double* rec, uint64_t step, uint32_t flags, hipStream_t s);
 int launch_sample(fp_ctx* c, const double* mom, double* samp, hipStream_t s);

@@ -112,6 +112,78 @@ __device__ __forceinline__ void fly(const fp_config& g, const Walls& W, double p
     if (TWO_D) pos[1] = st_round(pos[1], f32);
 }
 
+// diffuse re-emission from the cylinder surface at (px, py): normal n = (p - c)/R into the
+// gas, speed along n ~ v exp(-v^2/(2 R T_body)), Gaussian along the tangent (-n_y, n_x)
+// and along z; the body is at rest
+__device__ __forceinline__ void circle_emit(const fp_config& g, double px, double py, uint32_t pid,
+                                            uint32_t step, uint32_t bounce, double v[3]) {
+    const uint4 r = draw(g.seed, pid, step, PURPOSE_WALL, bounce);
+    const double u0 = u01d(r.x), u1 = u01d(r.y), u2 = u01d(r.z);
+    const double RT = g.kB / g.mass * g.T_body;
+    const double vn = sqrt(-2.0 * RT * log(u0));
+    const double rr = sqrt(-2.0 * log(u1));
+    const double za = rr * cos(TWO_PI * u2);
+    const double zb = rr * sin(TWO_PI * u2);
+    const double s = sqrt(RT);
+    const double nx = (px - g.circle[0]) / g.circle[2];
+    const double ny = (py - g.circle[1]) / g.circle[2];
+    const double vt = s * za;
+    v[0] = vn * nx - vt * ny;
+    v[1] = vn * ny + vt * nx;
+    v[2] = s * zb;
+}
+
+// free flight in the open cylinder domain: straight segments between diffuse hits on the
+// circle; returns true if the particle ends outside the box (deleted)
+__device__ __forceinline__ bool fly_open(const fp_config& g, double pos[2], double v[3],
+                                         uint32_t pid, uint32_t step, bool f32) {
+    const double cx = g.circle[0], cy = g.circle[1], R = g.circle[2];
+    double trem = g.dt;
+    for (int bounce = 0;; ++bounce) {
+        const double dxc = pos[0] - cx, dyc = pos[1] - cy;
+        const double a = v[0] * v[0] + v[1] * v[1];
+        const double b = dxc * v[0] + dyc * v[1];
+        const double c = dxc * dxc + dyc * dyc - R * R;
+        bool hit = false;
+        double th = 0.0;
+        if (c < 0.0) {
+            if (b < 0.0) {   // inside by rounding and moving in: hit at once
+                const double d = sqrt(dxc * dxc + dyc * dyc);
+                if (d > 0.0) {
+                    pos[0] = cx + R * (dxc / d);
+                    pos[1] = cy + R * (dyc / d);
+                }
+                hit = true;
+            }
+        } else if (b < 0.0 && a > 0.0) {
+            const double disc = b * b - a * c;
+            if (disc >= 0.0) {
+                const double q = -b + sqrt(disc);
+                const double t = c / q;
+                if (t <= trem) {
+                    hit = true;
+                    th = t;
+                    pos[0] = pos[0] + v[0] * th;
+                    pos[1] = pos[1] + v[1] * th;
+                }
+            }
+        }
+        if (!hit) {
+            pos[0] = pos[0] + v[0] * trem;
+            pos[1] = pos[1] + v[1] * trem;
+            break;
+        }
+        if (bounce == g.max_bounces) return false;   // stop on the surface
+        circle_emit(g, pos[0], pos[1], pid, step, (uint32_t)bounce, v);
+        v[0] = st_round(v[0], f32);
+        v[1] = st_round(v[1], f32);
+        v[2] = st_round(v[2], f32);
+        trem = trem - th;
+    }
+    const double x1 = g.x0 + g.lx, y1 = g.y0 + g.ly;
+    return pos[0] < g.x0 || pos[0] > x1 || pos[1] < g.y0 || pos[1] > y1;
+}
+
 template <bool TWO_D>
 __device__ __forceinline__ int32_t cell_key(const fp_config& g, double x, double y, double inv_dx,
                                             double inv_dy) {
@@ -187,7 +259,7 @@ __device__ __forceinline__ void collide_one<double>(const CellCoef<double>& q, d
     cn = fma(c0, N0, fma(c1, N1, c2 * N2));
 }
 
-template <typename T, int G, int K, bool TWO_D>
+template <typename T, int G, int K, int GEOM>
 __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
     fp_config g, int32_t ncell, const int32_t* __restrict__ offsets,
     const double* __restrict__ mom, const double* __restrict__ rec, T* __restrict__ px,
@@ -289,13 +361,21 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
             pvx[p] = v0; pvy[p] = v1; pvz[p] = v2;
             return;
         }
+        constexpr bool TWO_D = GEOM != FP_COUETTE1D;
         double pos[2] = {(double)px[p], TWO_D ? (double)py[p] : 0.0};
         double v[3] = {(double)v0, (double)v1, (double)v2};
-        fly<TWO_D>(g, W, pos, v, ppid[p], step, f32);
+        bool gone = false;
+        if constexpr (GEOM == FP_CYLINDER2D) {
+            gone = fly_open(g, pos, v, ppid[p], step, f32);
+            pos[0] = st_round(pos[0], f32);
+            pos[1] = st_round(pos[1], f32);
+        } else {
+            fly<TWO_D>(g, W, pos, v, ppid[p], step, f32);
+        }
         px[p] = (T)pos[0];
         if (TWO_D) py[p] = (T)pos[1];
         pvx[p] = (T)v[0]; pvy[p] = (T)v[1]; pvz[p] = (T)v[2];
-        pkey[p] = cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy);
+        pkey[p] = gone ? ncell : cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy);
     };
     auto newv = [&](T c, int i) -> T {
         return __builtin_fma(c - cb[i], sc, q.U[i]);
@@ -325,71 +405,188 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
 }
 
 // flight (or key recomputation) without a collision: one thread per particle
-template <typename T, bool TWO_D>
+template <typename T, int GEOM>
 __global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, T* __restrict__ px,
                                                          T* __restrict__ py, T* __restrict__ pvx,
                                                          T* __restrict__ pvy, T* __restrict__ pvz,
                                                          const uint32_t* __restrict__ ppid,
                                                          int32_t* __restrict__ pkey, uint32_t step,
                                                          int keys_only) {
+    constexpr bool TWO_D = GEOM != FP_COUETTE1D;
     const int64_t p = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
     if (p >= n) return;
     const double inv_dx = 1.0 / g.dx, inv_dy = 1.0 / g.dy;
     double pos[2] = {(double)px[p], TWO_D ? (double)py[p] : 0.0};
+    bool gone = false;
     if (!keys_only) {
-        const Walls W = make_walls(g);
+        const bool f32 = sizeof(T) == 4;
         double v[3] = {(double)pvx[p], (double)pvy[p], (double)pvz[p]};
-        fly<TWO_D>(g, W, pos, v, ppid[p], step, sizeof(T) == 4);
+        if constexpr (GEOM == FP_CYLINDER2D) {
+            gone = fly_open(g, pos, v, ppid[p], step, f32);
+            pos[0] = st_round(pos[0], f32);
+            pos[1] = st_round(pos[1], f32);
+        } else {
+            const Walls W = make_walls(g);
+            fly<TWO_D>(g, W, pos, v, ppid[p], step, f32);
+        }
         px[p] = (T)pos[0];
         if (TWO_D) py[p] = (T)pos[1];
         pvx[p] = (T)v[0]; pvy[p] = (T)v[1]; pvz[p] = (T)v[2];
     }
-    pkey[p] = cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy);
+    pkey[p] = gone ? g.nx * g.ny : cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy);
 }
 
-template <typename T, int G, bool TWO_D>
+template <typename T, int G, int GEOM>
 static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
                            const double* rec, uint32_t step, int move, hipStream_t s) {
     const int64_t threads = (int64_t)c->ncell * G;
     const unsigned grid = (unsigned)((threads + ST_BLOCK - 1) / ST_BLOCK);
-    hipLaunchKernelGGL((collide_kernel<T, G, ST_K, TWO_D>), dim3(grid), dim3(ST_BLOCK), 0, s,
+    hipLaunchKernelGGL((collide_kernel<T, G, ST_K, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
                        c->cfg, c->ncell, off, mom, rec, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy,
                        (T*)p->vz, p->pid, p->key, step, move);
 }
 
-template <typename T, bool TWO_D>
+template <typename T, int GEOM>
 static void collide_dispatch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
                              const double* rec, uint32_t step, int move, hipStream_t s) {
     switch (lanes_per_cell(p->n, c->ncell)) {
-        case 4: collide_launch<T, 4, TWO_D>(c, p, off, mom, rec, step, move, s); break;
-        case 8: collide_launch<T, 8, TWO_D>(c, p, off, mom, rec, step, move, s); break;
-        case 16: collide_launch<T, 16, TWO_D>(c, p, off, mom, rec, step, move, s); break;
-        case 32: collide_launch<T, 32, TWO_D>(c, p, off, mom, rec, step, move, s); break;
-        default: collide_launch<T, 64, TWO_D>(c, p, off, mom, rec, step, move, s); break;
+        case 4: collide_launch<T, 4, GEOM>(c, p, off, mom, rec, step, move, s); break;
+        case 8: collide_launch<T, 8, GEOM>(c, p, off, mom, rec, step, move, s); break;
+        case 16: collide_launch<T, 16, GEOM>(c, p, off, mom, rec, step, move, s); break;
+        case 32: collide_launch<T, 32, GEOM>(c, p, off, mom, rec, step, move, s); break;
+        default: collide_launch<T, 64, GEOM>(c, p, off, mom, rec, step, move, s); break;
     }
 }
 
 template <typename T>
 static void step_typed(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
                        const double* rec, uint32_t step, uint32_t flags, hipStream_t s) {
-    const bool two_d = c->cfg.geometry == FP_CAVITY2D;
+    const int geom = c->cfg.geometry;
     const int move = (flags & FP_STEP_MOVE) ? 1 : 0;
     if (flags & FP_STEP_COLLIDE) {
-        if (two_d) collide_dispatch<T, true>(c, p, off, mom, rec, step, move, s);
-        else collide_dispatch<T, false>(c, p, off, mom, rec, step, move, s);
+        if (geom == FP_CAVITY2D) collide_dispatch<T, FP_CAVITY2D>(c, p, off, mom, rec, step, move, s);
+        else if (geom == FP_CYLINDER2D) collide_dispatch<T, FP_CYLINDER2D>(c, p, off, mom, rec, step, move, s);
+        else collide_dispatch<T, FP_COUETTE1D>(c, p, off, mom, rec, step, move, s);
         return;
     }
     if (p->n == 0) return;
     const unsigned grid = (unsigned)((p->n + ST_BLOCK - 1) / ST_BLOCK);
     const int keys_only = (flags & FP_STEP_KEYS) ? 1 : 0;
-    if (two_d)
-        hipLaunchKernelGGL((move_kernel<T, true>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg, p->n,
-                           (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
+    if (geom == FP_CAVITY2D)
+        hipLaunchKernelGGL((move_kernel<T, FP_CAVITY2D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
+                           p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
+                           step, keys_only);
+    else if (geom == FP_CYLINDER2D)
+        hipLaunchKernelGGL((move_kernel<T, FP_CYLINDER2D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
+                           p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
                            step, keys_only);
     else
-        hipLaunchKernelGGL((move_kernel<T, false>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg, p->n,
-                           (T*)p->x, (T*)nullptr, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid,
+        hipLaunchKernelGGL((move_kernel<T, FP_COUETTE1D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
+                           p->n, (T*)p->x, (T*)nullptr, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid,
                            p->key, step, keys_only);
+}
+
+
+// ---- free-stream inflow of the open domain ------------------------------------------------
+// counts of the four rectangles: floor(lambda_r) + Bernoulli(lambda_r - floor(lambda_r))
+// with the uniform of counter (r, step, 5, 1); cnt[0..3] counts, cnt[4..8] prefix
+__global__ void inject_count_kernel(fp_config g, double l0, double l1, double l2, double l3,
+                                    uint32_t step, int32_t* __restrict__ cnt) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double lam[4] = {l0, l1, l2, l3};
+    int32_t pre = 0;
+    cnt[4] = 0;
+    for (int r = 0; r < 4; ++r) {
+        const double base = floor(lam[r]);
+        const uint4 d = draw(g.seed, (uint32_t)r, step, PURPOSE_INJECT, 1);
+        const int32_t k = (int32_t)base + (u01d(d.x) < lam[r] - base ? 1 : 0);
+        cnt[r] = k;
+        pre += k;
+        cnt[5 + r] = pre;
+    }
+}
+
+struct InjectGeom {
+    double rect[4][4];
+    int32_t slot0[5];
+};
+
+template <typename T>
+__global__ __launch_bounds__(ST_BLOCK) void inject_kernel(fp_config g, InjectGeom ig, uint32_t step,
+                                                          const int32_t* __restrict__ cnt,
+                                                          const uint32_t* __restrict__ pid_next,
+                                                          T* __restrict__ px, T* __restrict__ py,
+                                                          T* __restrict__ pvx, T* __restrict__ pvy,
+                                                          T* __restrict__ pvz, uint32_t* __restrict__ ppid,
+                                                          int32_t* __restrict__ pkey) {
+    const int32_t slot = blockIdx.x * ST_BLOCK + threadIdx.x;
+    if (slot >= ig.slot0[4]) return;
+    int r = 0;
+    while (r < 3 && slot >= ig.slot0[r + 1]) ++r;
+    const int32_t k = slot - ig.slot0[r];
+    const int32_t ncell = g.nx * g.ny;
+    const bool f32 = sizeof(T) == 4;
+    if (k >= cnt[r]) {
+        pkey[slot] = ncell;   // unused slot
+        return;
+    }
+    const int32_t gidx = (r == 0 ? 0 : cnt[4 + r]) + k;
+    const uint32_t id = pid_next[0] + (uint32_t)gidx;
+    const double xa = ig.rect[r][0], xb = ig.rect[r][1], ya = ig.rect[r][2], yb = ig.rect[r][3];
+    const uint4 d0 = draw(g.seed, id, step, PURPOSE_INJECT, 0);
+    const uint4 d1 = draw(g.seed, id, step, PURPOSE_INJECT, 2);
+    const double RT = g.kB / g.mass * g.T_inf;
+    const double s = sqrt(RT);
+    const double x = xa + u01d(d0.x) * (xb - xa);
+    const double y = ya + u01d(d0.y) * (yb - ya);
+    const double r0 = sqrt(-2.0 * log(u01d(d0.z)));
+    const double v0 = g.u_inf[0] + s * (r0 * cos(TWO_PI * u01d(d0.w)));
+    const double v1 = g.u_inf[1] + s * (r0 * sin(TWO_PI * u01d(d0.w)));
+    const double v2 = g.u_inf[2] + s * (sqrt(-2.0 * log(u01d(d1.x))) * cos(TWO_PI * u01d(d1.y)));
+    const double ex = x + v0 * g.dt;
+    const double ey = y + v1 * g.dt;
+    const double x1 = g.x0 + g.lx, y1 = g.y0 + g.ly;
+    if (!(ex >= g.x0 && ex <= x1 && ey >= g.y0 && ey <= y1)) {
+        pkey[slot] = ncell;   // did not enter
+        return;
+    }
+    const double sx = st_round(ex, f32), sy = st_round(ey, f32);
+    px[slot] = (T)sx;
+    py[slot] = (T)sy;
+    pvx[slot] = (T)v0;
+    pvy[slot] = (T)v1;
+    pvz[slot] = (T)v2;
+    ppid[slot] = id;
+    pkey[slot] = cell_key<true>(g, sx, sy, 1.0 / g.dx, 1.0 / g.dy);
+}
+
+__global__ void inject_advance_kernel(const int32_t* __restrict__ cnt, uint32_t* __restrict__ pid_next) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) pid_next[0] += (uint32_t)cnt[8];
+}
+
+template <typename T>
+static void inject_typed(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_next, uint32_t step,
+                         hipStream_t s) {
+    InjectGeom ig;
+    for (int r = 0; r < 4; ++r)
+        for (int k = 0; k < 4; ++k) ig.rect[r][k] = c->inj_rect[r][k];
+    for (int r = 0; r < 5; ++r) ig.slot0[r] = c->inj_slot0[r];
+    hipLaunchKernelGGL(inject_count_kernel, dim3(1), dim3(64), 0, s, c->cfg, c->inj_lambda[0],
+                       c->inj_lambda[1], c->inj_lambda[2], c->inj_lambda[3], step, c->inj);
+    const int32_t slots = ig.slot0[4];
+    if (slots > 0)
+        hipLaunchKernelGGL((inject_kernel<T>), dim3((slots + ST_BLOCK - 1) / ST_BLOCK), dim3(ST_BLOCK),
+                           0, s, c->cfg, ig, step, (const int32_t*)c->inj, (const uint32_t*)pid_next,
+                           (T*)p->x + at, (T*)p->y + at, (T*)p->vx + at, (T*)p->vy + at, (T*)p->vz + at,
+                           p->pid + at, p->key + at);
+    hipLaunchKernelGGL(inject_advance_kernel, dim3(1), dim3(64), 0, s, (const int32_t*)c->inj, pid_next);
+}
+
+int launch_inject(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_next, uint32_t step,
+                  hipStream_t s) {
+    if (c->cfg.precision == FP_F32) inject_typed<float>(c, p, at, pid_next, step, s);
+    else inject_typed<double>(c, p, at, pid_next, step, s);
+    return check_launch(c, "fp_inject");
 }
 
 int launch_step(fp_ctx* c, fp_particles* p, const int32_t* offsets, const double* mom,

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfpgpu.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "fp.h")
 
 FP_OK, FP_EINVAL, FP_ENOMEM, FP_EDEVICE, FP_ECAPACITY = 0, -1, -2, -3, -4
-FP_COUETTE1D, FP_CAVITY2D = 0, 1
+FP_COUETTE1D, FP_CAVITY2D, FP_CYLINDER2D = 0, 1, 2
 FP_F32, FP_F64 = 0, 1
 FP_EXACT, FP_PAPER = 0, 1
 (CELL_OK, CELL_EMPTY, CELL_FEW, CELL_SINGULAR, CELL_NONFINITE, CELL_NN,
@@ -38,6 +38,9 @@ class FPConfig(C.Structure):
         ("fnum_over_vol", C.c_double), ("eps_hat", C.c_double), ("pivot_tol", C.c_double),
         ("T_wall", C.c_double * 4), ("u_wall", (C.c_double * 3) * 4),
         ("seed", C.c_uint64),
+        ("circle", C.c_double * 3), ("T_body", C.c_double), ("n_inf", C.c_double),
+        ("u_inf", C.c_double * 3), ("T_inf", C.c_double), ("fnum", C.c_double),
+        ("depth", C.c_double),
     ]
 
 
@@ -69,6 +72,10 @@ def load():
         L.fp_closure_solve.argtypes = [vp, vp, vp, vp, vp]
         L.fp_step.argtypes = [vp, P(FPParticles), vp, vp, vp, u64, u32, vp]
         L.fp_sample.argtypes = [vp, vp, vp, vp]
+        L.fp_inject.argtypes = [vp, P(FPParticles), i64, vp, u64, vp]
+        L.fp_inject_slots.argtypes = [vp]
+        L.fp_inject_slots.restype = i64
+        L.fp_cell_volumes.argtypes = [vp, vp, vp]
         L.fp_nn_create.argtypes = [vp, i64, P(vp)]
         L.fp_nn_destroy.argtypes = [vp]
         L.fp_nn_load.argtypes = [vp, vp, vp, vp]
@@ -86,7 +93,8 @@ def load():
         for f in ("fp_bin", "fp_moments", "fp_closure_solve", "fp_step", "fp_sample", "fp_nn_create",
                   "fp_nn_load", "fp_closure_nn", "fp_nn_outputs", "fp_nn_features",
                   "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
-                  "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward"):
+                  "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
+                  "fp_inject", "fp_cell_volumes"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -101,7 +109,8 @@ def header_functions():
 
 def make_config(w: dict, capacity: int) -> FPConfig:
     c = FPConfig()
-    c.geometry = {"couette1d": FP_COUETTE1D, "cavity2d": FP_CAVITY2D}[w["geometry"]]
+    c.geometry = {"couette1d": FP_COUETTE1D, "cavity2d": FP_CAVITY2D,
+                  "cylinder2d": FP_CYLINDER2D}[w["geometry"]]
     c.precision = {"f32": FP_F32, "f64": FP_F64}[w["precision"]]
     c.conserve = {"exact": FP_EXACT, "paper": FP_PAPER}[w.get("conserve", "exact")]
     c.nx, c.ny = int(w["nx"]), int(w["ny"])
@@ -119,6 +128,14 @@ def make_config(w: dict, capacity: int) -> FPConfig:
         for j in range(3):
             c.u_wall[k][j] = float(w["u_wall"][k][j])
     c.seed = int(w["seed"])
+    for k in range(3):
+        c.circle[k] = float(w.get("circle", (0.0, 0.0, 0.0))[k])
+        c.u_inf[k] = float(w.get("u_inf", (0.0, 0.0, 0.0))[k])
+    c.T_body = float(w.get("T_body", 0.0))
+    c.n_inf = float(w.get("n_inf", 0.0))
+    c.T_inf = float(w.get("T_inf", 0.0))
+    c.fnum = float(w.get("fnum", 0.0))
+    c.depth = float(w.get("depth", 1.0))
     return c
 
 
@@ -234,6 +251,17 @@ class Context:
     def sample(self, mom, samp, stream=None):
         self._check(self.lib.fp_sample(self.h, _ptr(mom), _ptr(samp), _stream(stream)), "fp_sample")
 
+    def inject(self, p, at, pid_next, step, stream=None):
+        a = p.struct()
+        self._check(self.lib.fp_inject(self.h, C.byref(a), int(at), _ptr(pid_next), int(step),
+                                       _stream(stream)), "fp_inject")
+
+    def inject_slots(self):
+        return int(self.lib.fp_inject_slots(self.h))
+
+    def cell_volumes(self, vol, stream=None):
+        self._check(self.lib.fp_cell_volumes(self.h, _ptr(vol), _stream(stream)), "fp_cell_volumes")
+
     # ---- learned closure -------------------------------------------------------------
     def closure_build(self, mom, n, sys, stream=None):
         self._check(self.lib.fp_closure_build(self.h, _ptr(mom), int(n), _ptr(sys), _stream(stream)),
@@ -345,3 +373,60 @@ class Simulation:
         n_skip = self.w.get("n_skip", 0) if n_skip is None else n_skip
         for s in range(step0, step0 + nsteps):
             self.step(s, sample=s >= n_skip)
+
+
+class OpenSimulation:
+    """Loop of the open cylinder domain: bin -> moments -> [sample] -> closure ->
+    collide + move (deleting particles that leave the box) -> inflow injection.  The
+    number of particles kept by fp_bin is read back once per step (one host sync)."""
+
+    def __init__(self, w, state, capacity=None, device="cuda"):
+        self.w = w
+        n0 = state["x"].shape[0]
+        cap = int(capacity if capacity is not None else 2 * n0 + 1_000_000)
+        self.ctx = Context(w, cap)
+        self.slots = self.ctx.inject_slots()
+        self.a = Particles.from_numpy(w, state, capacity=cap, device=device)
+        self.b = Particles(0, self.a.dtype, True, device, capacity=cap)
+        nc = self.ctx.ncell
+        self.offsets = torch.zeros(nc + 1, dtype=torch.int32, device=device)
+        self.mom = torch.zeros((nc, MOM_STRIDE), dtype=torch.float64, device=device)
+        self.rec = torch.zeros((nc, REC_STRIDE), dtype=torch.float64, device=device)
+        self.status = torch.zeros(nc, dtype=torch.int32, device=device)
+        self.samp = torch.zeros((nc, SAMP_STRIDE), dtype=torch.float64, device=device)
+        self.pid_next = torch.tensor([int(state.get("pid_next", n0))], dtype=torch.int64,
+                                     device=device).to(torch.int32)
+        self.n_total = n0
+        if "key" not in state:
+            self.ctx.step(self.a, None, None, None, 0, STEP_KEYS)
+
+    def step(self, s, sample=False, closure=None):
+        self.a.n = self.n_total
+        self.b.n = self.n_total
+        self.ctx.bin(self.a, self.b, self.offsets)
+        self.a, self.b = self.b, self.a
+        live = int(self.offsets[-1])
+        self.a.n = live
+        self.ctx.moments(self.a, self.offsets, self.mom)
+        if sample:
+            self.ctx.sample(self.mom, self.samp)
+        if closure is None:
+            self.ctx.closure_solve(self.mom, self.rec, self.status)
+        else:
+            closure(self.mom, self.rec, self.status)
+        self.ctx.step(self.a, self.offsets, self.mom, self.rec, s, STEP_COLLIDE | STEP_MOVE)
+        self.ctx.inject(self.a, live, self.pid_next, s)
+        self.n_total = live + self.slots
+
+    def run(self, step0, nsteps, n_skip=None):
+        n_skip = self.w.get("n_skip", 0) if n_skip is None else n_skip
+        for s in range(step0, step0 + nsteps):
+            self.step(s, sample=s >= n_skip)
+
+    def live(self):
+        """Particles after the last move and injection, deleted and unused slots removed
+        (host copy, for checks)."""
+        self.a.n = self.n_total
+        out = self.a.numpy()
+        keep = out["key"] < self.ctx.ncell
+        return {k: v[keep] for k, v in out.items()}

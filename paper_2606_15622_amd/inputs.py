@@ -37,7 +37,7 @@ def _vhs_density(kn, length, T=T_REF, omega=OMEGA):
 def _base(**kw):
     R = KB / MASS_AR
     w = dict(kB=KB, mass=MASS_AR, mu_ref=MU_REF, T_ref=T_REF, omega=OMEGA,
-             eps_hat=0.01, n_min=4, max_bounces=8, pivot_tol=1e-12, conserve="exact",
+             eps_hat=0.01, n_min=5, max_bounces=8, pivot_tol=1e-12, conserve="exact",
              seed=1, x0=0.0, y0=0.0, T_init=273.0)
     w.update(kw)
     w["R"] = R

@@ -1,0 +1,147 @@
+"""Open cylinder domain (configuration 5) on the GPU against the oracle: cut-cell
+volumes, circle wall and exit deletion, inflow injection, short open runs, and one
+whole step at full size (400 x 300 cells, about 2e7 particles, FP32)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2606_15622_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def fp():
+    from paper_2606_15622_amd import fpgpu
+    fpgpu.load()
+    return fpgpu
+
+
+def small(prec="f64", **kw):
+    return I.cylinder(cell=1e-2, nx=80, ny=60, fnum=2.5e14, precision=prec, **kw)
+
+
+def test_cell_volumes_match_oracle():
+    F = fp()
+    w = I.cylinder(precision="f32")
+    ctx = F.Context(w, 1)
+    vol = torch.zeros(w["nx"] * w["ny"], dtype=torch.float64, device="cuda")
+    ctx.cell_volumes(vol)
+    torch.cuda.synchronize()
+    g = vol.cpu().numpy()
+    o = O.cell_volumes(w)
+    full = w["dx"] * w["dy"]
+    assert np.abs(g - o).max() <= 1e-12 * full
+    np.testing.assert_array_equal(g == 0, o == 0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_move_with_circle_and_exits(prec):
+    F = fp()
+    w = small(prec)
+    rng = np.random.default_rng(3)
+    n = 200_000
+    R = w["circle"][2]
+    ang = rng.uniform(0, 2 * np.pi, n)
+    rad = R + rng.uniform(0, 0.02, n)
+    s = {"x": rad * np.cos(ang), "y": rad * np.sin(ang)}
+    far = rng.random(n) < 0.3          # some near the open boundaries
+    s["x"][far] = rng.uniform(w["x0"], w["x0"] + w["lx"], far.sum())
+    s["y"][far] = rng.uniform(w["y0"], w["y0"] + w["ly"], far.sum())
+    v = rng.standard_normal((3, n)) * 2000.0
+    v[0] += 1500.0
+    s.update(vx=v[0], vy=v[1], vz=v[2], pid=np.arange(n, dtype=np.uint32))
+    if prec == "f32":
+        for k in ("x", "y", "vx", "vy", "vz"):
+            s[k] = s[k].astype(np.float32).astype(np.float64)
+    ctx = F.Context(w, n)
+    p = F.Particles.from_numpy(w, s)
+    ctx.step(p, None, None, None, 5, F.STEP_MOVE)
+    torch.cuda.synchronize()
+    g = p.numpy()
+    ox, oy, ovx, ovy, ovz, okey = O.move(w, s["x"], s["y"], s["vx"], s["vy"], s["vz"], s["pid"], 5)
+    nc = w["nx"] * w["ny"]
+    np.testing.assert_array_equal(g["key"], okey)
+    assert (okey == nc).sum() > 100                         # exits happened
+    bounced = (ovx != s["vx"])
+    assert bounced.sum() > 1000                               # circle hits happened
+    live = okey < nc
+    assert np.all(np.abs(g["x"][live] - ox[live]) <= 1e-12)
+    assert np.all(np.abs(g["y"][live] - oy[live]) <= 1e-12)
+    for k, ov in (("vx", ovx), ("vy", ovy), ("vz", ovz)):
+        assert np.all(np.abs(g[k] - ov) <= 1e-6 * 1000.0), k
+    np.testing.assert_array_equal(g["x"][~bounced & live], ox[~bounced & live])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_injection_matches_oracle(prec):
+    F = fp()
+    w = small(prec, mach=10.0)
+    slots_est = 200_000
+    ctx = F.Context(w, slots_est)
+    slots = ctx.inject_slots()
+    assert slots < slots_est
+    p = F.Particles(slots, torch.float32 if prec == "f32" else torch.float64, True, capacity=slots_est)
+    pid_next = torch.tensor([1000], dtype=torch.int32, device="cuda")
+    opn = 1000
+    nc = w["nx"] * w["ny"]
+    for step in (0, 7, 123):
+        ctx.inject(p, 0, pid_next, step)
+        torch.cuda.synchronize()
+        g = p.numpy()
+        keep = g["key"] < nc
+        o, opn = O.inject(w, step, opn)
+        np.testing.assert_array_equal(g["pid"][keep], o["pid"])
+        np.testing.assert_array_equal(g["key"][keep], o["key"])
+        for k in ("x", "y", "vx", "vy", "vz"):
+            assert np.all(np.abs(g[k][keep] - o[k]) <= 1e-9 * (1 + np.abs(o[k]))), k
+        assert int(pid_next.cpu()[0]) == opn
+
+
+def test_open_run_parity_fp64():
+    F = fp()
+    w = small("f64", mach=10.0)
+    s = I.freestream_state(w, seed=4)
+    s["key"] = O.keys(w, s["x"], s["y"])
+    n0 = s["x"].shape[0]
+    sim = F.OpenSimulation(w, s)
+    sim.run(0, 12, n_skip=0)
+    torch.cuda.synchronize()
+    g = sim.live()
+    o, opn, omom, orec, ost, osamp = O.run_open(w, s, n0, 0, 12, capacity=4 * n0, n_skip=0)
+    nc = w["nx"] * w["ny"]
+    o = {k: v[o["key"] < nc] for k, v in o.items()}
+    np.testing.assert_array_equal(g["pid"], o["pid"])
+    np.testing.assert_array_equal(g["key"], o["key"])
+    assert int(sim.pid_next.cpu()[0]) == opn
+    for k in ("x", "y"):
+        assert np.abs(g[k] - o[k]).max() <= 1e-9
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(g[k] - o[k]).max() <= 1e-7 * 3000.0, k
+    np.testing.assert_array_equal(sim.status.cpu().numpy(), ost)
+
+
+def test_cylinder_full_size_one_step():
+    """Configuration 5 at full size (400 x 300 cells of 2 mm, about 2e7 particles, FP32)."""
+    F = fp()
+    w = I.cylinder(precision="f32", seed=2)
+    s = I.freestream_state(w)
+    n0 = s["x"].shape[0]
+    assert n0 > 1.8e7
+    sim = F.OpenSimulation(w, s)
+    sim.step(0, sample=True)
+    torch.cuda.synchronize()
+    g = sim.live()
+    s["key"] = O.keys(w, s["x"], s["y"])
+    o, opn, omom, orec, ost, osamp = O.run_open(w, s, n0, 0, 1, capacity=n0 + 2_000_000, n_skip=0)
+    nc = w["nx"] * w["ny"]
+    o = {k: v[o["key"] < nc] for k, v in o.items()}
+    np.testing.assert_array_equal(g["pid"], o["pid"])
+    np.testing.assert_array_equal(g["key"], o["key"])
+    np.testing.assert_array_equal(sim.status.cpu().numpy(), ost)
+    sc = math.sqrt(I.KB / I.MASS_AR * w["T_inf"])
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(g[k] - o[k]).max() <= 1e-5 * (sc + 2700.0), k
+    assert np.abs(g["x"] - o["x"]).max() <= 1e-6

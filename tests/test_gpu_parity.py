@@ -175,7 +175,7 @@ def _mixture_moments(counts, seed):
 
 def test_closure_parity_and_status():
     F = fp()
-    counts = [0, 1, 2, 3, 4, 10, 50, 300, 1000] * 40
+    counts = [0, 1, 2, 3, 4, 5, 10, 50, 300, 1000] * 40
     mom, _ = _mixture_moments(counts, seed=11)
     # special cells: zero temperature, 1-D (singular), NaN
     mom[0] = 0; mom[0, 0] = 5; mom[0, 1] = 3.0
@@ -205,8 +205,12 @@ def test_closure_parity_and_status():
         sn[:, 0:6] = np.where(tau > 0, tau, 1)[:, None]
         sn[:, 6:9] = (np.where(tau > 0, tau, 1) * np.sqrt(np.maximum(orec[:, 10], 0)))[:, None]
         err = np.abs(g - orec) * sn
-        lim = 1e-10 * (1 + np.abs(orec * sn))
+        cond = np.ones(nc)
+        for c in np.nonzero(ok)[0]:
+            cond[c] = np.linalg.cond(O.closure_system(mom[c], eps_hat)[0])
+        lim = np.maximum(1e-10, 1e-14 * cond)[:, None] * (1 + np.abs(orec * sn))
         assert np.all(err[:, :9] <= lim[:, :9])
+        assert cond.max() < 1e9   # cells with >= n_min = 5 particles are well posed
         np.testing.assert_allclose(g[:, 9:14], orec[:, 9:14], rtol=1e-12)
         np.testing.assert_array_equal(g[:, 14], orec[:, 14])
 

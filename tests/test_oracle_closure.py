@@ -160,6 +160,19 @@ def test_axis_reflection_symmetric_cell():
     np.testing.assert_allclose(y[[1, 2, 4, 6, 7, 8]], 0.0, atol=1e-12)
 
 
+def test_four_particle_cells_are_singular():
+    """Four centred velocities span three directions: the 9x9 system has no unique
+    solution, which is why cells need at least five particles (default n_min)."""
+    import scipy.linalg as sl
+    vx, vy, vz, off = I.mixture_cells([4] * 50 + [5] * 50, seed=4)
+    mom = O.moments(off, vx, vy, vz)
+    piv4 = [np.abs(np.diag(sl.lu_factor(O.closure_system(m, 0.01)[0])[0])).min() for m in mom[:50]]
+    cond5 = [np.linalg.cond(O.closure_system(m, 0.01)[0]) for m in mom[50:]]
+    assert np.median(piv4) < 1e-12
+    assert max(cond5) < 1e9
+    assert I.couette()["n_min"] == 5
+
+
 def test_status_codes():
     w = I.couette(ncell=1, precision="f64", n_min=4)
     th = 1e4
