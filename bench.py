@@ -82,9 +82,11 @@ def timed_step(T, sim, s, sample):
     T.call("step", ctx.step, sim.a, sim.offsets, sim.mom, sim.rec, s, F.STEP_COLLIDE | F.STEP_MOVE)
 
 
-def run_workload(torch, F, I, w, steps, warmup):
+def run_workload(torch, F, I, w, steps, warmup, graph=True):
+    """Warm up eagerly, then time `steps` steps: replays of the step captured in a HIP
+    graph (graph=True) or eager launches.  Returns timings and per-kernel durations."""
     state = I.maxwellian_state(w)
-    sim = F.Simulation(w, state)
+    sim = F.GraphSimulation(w, state, step0=warmup) if graph else F.Simulation(w, state)
     sim.F = F
     n, nc = state["x"].shape[0], I.ncells(w)
     del state
@@ -93,12 +95,23 @@ def run_workload(torch, F, I, w, steps, warmup):
         sim.step(s, sample=True)
         s += 1
     torch.cuda.synchronize()
+    steps = steps + (steps % 2) if graph else steps
+    if graph:
+        sim.run_pairs(1, sample=True)        # capture outside the timed region
+        s += 2
+        torch.cuda.synchronize()
+        sim.step_ctr.fill_(s)
     t0 = time.perf_counter()
-    for _ in range(steps):
-        sim.step(s, sample=True)
-        s += 1
+    if graph:
+        sim.run_pairs(steps // 2, sample=True)
+    else:
+        for _ in range(steps):
+            sim.step(s, sample=True)
+            s += 1
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    if graph:
+        s = int(sim.step_ctr.cpu()[0])
     # per-entry-point durations over a second, event-instrumented pass
     T = Timed(torch, sim.ctx)
     for _ in range(min(steps, 50)):
@@ -151,7 +164,8 @@ def main():
     torch.cuda.set_device(0)
 
     w = I.cavity(kn=args.kn, ncell=100, ppc=100, precision="f32", seed=1)
-    res = run_workload(torch, F, I, w, args.steps, args.warmup)
+    res = run_workload(torch, F, I, w, args.steps, args.warmup, graph=True)
+    res_eager = run_workload(torch, F, I, w, min(args.steps, 50), 5, graph=False)
     n, nc = res["n"], res["nc"]
     ms_step = res["t"] / res["steps"] * 1e3
     pps = n * res["steps"] / res["t"]
@@ -174,10 +188,12 @@ def main():
         "closure_kernel_cell_closures_per_s": round(nc / (kern["closure"]["ms"] * 1e-3), 1),
         "kernels": kern,
         "roofline": roofline_of(res, dominant),
+        "timed_loop": "HIP graph replay of two captured steps",
+        "eager_particle_steps_per_s": round(res_eager["n"] * res_eager["steps"] / res_eager["t"], 1),
     }
     if not args.no_scaled:
         ws = I.cavity(kn=args.kn, ncell=448, ppc=100, precision="f32", seed=2)
-        rs = run_workload(torch, F, I, ws, args.scaled_steps, 5)
+        rs = run_workload(torch, F, I, ws, args.scaled_steps, 5, graph=True)
         out["scaled"] = {
             "workload": "cavity2d 448x448 cells, 100 particles/cell (2.0e7 particles)",
             "value": round(rs["n"] * rs["steps"] / rs["t"], 1), "unit": "particle-steps/s",

@@ -159,6 +159,14 @@ int fp_closure_solve(fp_ctx* ctx, const double* mom, double* rec, int32_t* statu
 int fp_step(fp_ctx* ctx, fp_particles* p, const int32_t* offsets, const double* mom,
             const double* rec, uint64_t step, uint32_t flags, hipStream_t s);
 
+/* fp_step with the step number read from device memory (*step_dev, one uint32) when the
+ * kernels run, so that a whole step can be captured once in a HIP graph and replayed
+ * for successive steps (advance the counter with fp_counter_add inside the graph). */
+int fp_step_dev(fp_ctx* ctx, fp_particles* p, const int32_t* offsets, const double* mom,
+                const double* rec, const uint32_t* step_dev, uint32_t flags, hipStream_t s);
+/* *ctr += inc on the device, ordered on the stream (a kernel, no memset: capturable). */
+int fp_counter_add(fp_ctx* ctx, uint32_t* ctr, uint32_t inc, hipStream_t s);
+
 /* Free-stream inflow of the open cylinder domain (boundary step of the loop).
  * Candidates are drawn uniformly in a buffer frame of width
  * (|u_inf| + 4 sqrt(2 R T_inf)) dt around the box (four rectangles: x-low, x-high, y-low,

@@ -240,7 +240,25 @@ extern "C" int fp_step(fp_ctx* c, fp_particles* p, const int32_t* offsets, const
     if ((flags & FP_STEP_KEYS) && (flags & FP_STEP_MOVE))
         return set_err(c, FP_EINVAL, "fp_step: MOVE already writes keys");
     if (step > 0xFFFFFFFFull) return set_err(c, FP_EINVAL, "fp_step: step beyond 2^32");
-    return launch_step(c, p, offsets, mom, rec, step, flags, s);
+    return launch_step(c, p, offsets, mom, rec, step, flags, nullptr, s);
+}
+
+extern "C" int fp_step_dev(fp_ctx* c, fp_particles* p, const int32_t* offsets, const double* mom,
+                           const double* rec, const uint32_t* step_dev, uint32_t flags,
+                           hipStream_t s) {
+    if (!c || !step_dev || (flags & ~7u) || !flags) return set_err(c, FP_EINVAL, "fp_step_dev: bad argument");
+    if (!particles_ok(c, p, (flags & (FP_STEP_MOVE | FP_STEP_KEYS)) != 0))
+        return set_err(c, FP_EINVAL, "fp_step_dev: bad particles");
+    if ((flags & FP_STEP_COLLIDE) && (!offsets || !mom || !rec))
+        return set_err(c, FP_EINVAL, "fp_step_dev: COLLIDE needs offsets, mom and rec");
+    if ((flags & FP_STEP_KEYS) && (flags & FP_STEP_MOVE))
+        return set_err(c, FP_EINVAL, "fp_step_dev: MOVE already writes keys");
+    return launch_step(c, p, offsets, mom, rec, 0, flags, step_dev, s);
+}
+
+extern "C" int fp_counter_add(fp_ctx* c, uint32_t* ctr, uint32_t inc, hipStream_t s) {
+    if (!c || !ctr) return set_err(c, FP_EINVAL, "fp_counter_add: bad argument");
+    return launch_counter_add(c, ctr, inc, s);
 }
 
 extern "C" int fp_sample(fp_ctx* c, const double* mom, double* samp, hipStream_t s) {

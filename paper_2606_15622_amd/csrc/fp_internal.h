@@ -146,7 +146,9 @@ int launch_closure(fp_ctx* c, const double* mom, double* rec, int32_t* status, h
 int launch_inject(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_next, uint32_t step,
                   hipStream_t s);
 int launch_step(fp_ctx* c, fp_particles* p, const int32_t* offsets, const double* mom,
-                const double* rec, uint64_t step, uint32_t flags, hipStream_t s);
+                const double* rec, uint64_t step, uint32_t flags, const uint32_t* step_dev,
+                hipStream_t s);
+int launch_counter_add(fp_ctx* c, uint32_t* ctr, uint32_t inc, hipStream_t s);
 int launch_sample(fp_ctx* c, const double* mom, double* samp, hipStream_t s);
 
 }  // namespace fpg

@@ -264,7 +264,9 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
     fp_config g, int32_t ncell, const int32_t* __restrict__ offsets,
     const double* __restrict__ mom, const double* __restrict__ rec, T* __restrict__ px,
     T* __restrict__ py, T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
-    const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step, int move) {
+    const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step_arg, int move,
+    const uint32_t* __restrict__ stepp) {
+    const uint32_t step = stepp ? stepp[0] : step_arg;
     const int64_t gt = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
     const int32_t cell = (int32_t)(gt / G);
     const int lg = (int)(gt % G);
@@ -410,8 +412,9 @@ __global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, 
                                                          T* __restrict__ py, T* __restrict__ pvx,
                                                          T* __restrict__ pvy, T* __restrict__ pvz,
                                                          const uint32_t* __restrict__ ppid,
-                                                         int32_t* __restrict__ pkey, uint32_t step,
-                                                         int keys_only) {
+                                                         int32_t* __restrict__ pkey, uint32_t step_arg,
+                                                         int keys_only, const uint32_t* __restrict__ stepp) {
+    const uint32_t step = stepp ? stepp[0] : step_arg;
     constexpr bool TWO_D = GEOM != FP_COUETTE1D;
     const int64_t p = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
     if (p >= n) return;
@@ -438,35 +441,39 @@ __global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, 
 
 template <typename T, int G, int GEOM>
 static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
-                           const double* rec, uint32_t step, int move, hipStream_t s) {
+                           const double* rec, uint32_t step, int move, const uint32_t* stepp,
+                           hipStream_t s) {
     const int64_t threads = (int64_t)c->ncell * G;
     const unsigned grid = (unsigned)((threads + ST_BLOCK - 1) / ST_BLOCK);
     hipLaunchKernelGGL((collide_kernel<T, G, ST_K, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
                        c->cfg, c->ncell, off, mom, rec, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy,
-                       (T*)p->vz, p->pid, p->key, step, move);
+                       (T*)p->vz, p->pid, p->key, step, move, stepp);
 }
 
 template <typename T, int GEOM>
 static void collide_dispatch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
-                             const double* rec, uint32_t step, int move, hipStream_t s) {
+                             const double* rec, uint32_t step, int move, const uint32_t* sp,
+                             hipStream_t s) {
     switch (lanes_per_cell(p->n, c->ncell)) {
-        case 4: collide_launch<T, 4, GEOM>(c, p, off, mom, rec, step, move, s); break;
-        case 8: collide_launch<T, 8, GEOM>(c, p, off, mom, rec, step, move, s); break;
-        case 16: collide_launch<T, 16, GEOM>(c, p, off, mom, rec, step, move, s); break;
-        case 32: collide_launch<T, 32, GEOM>(c, p, off, mom, rec, step, move, s); break;
-        default: collide_launch<T, 64, GEOM>(c, p, off, mom, rec, step, move, s); break;
+        case 4: collide_launch<T, 4, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
+        case 8: collide_launch<T, 8, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
+        case 16: collide_launch<T, 16, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
+        case 32: collide_launch<T, 32, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
+        default: collide_launch<T, 64, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
     }
 }
 
 template <typename T>
 static void step_typed(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
-                       const double* rec, uint32_t step, uint32_t flags, hipStream_t s) {
+                       const double* rec, uint32_t step, uint32_t flags, const uint32_t* sp,
+                       hipStream_t s) {
     const int geom = c->cfg.geometry;
     const int move = (flags & FP_STEP_MOVE) ? 1 : 0;
     if (flags & FP_STEP_COLLIDE) {
-        if (geom == FP_CAVITY2D) collide_dispatch<T, FP_CAVITY2D>(c, p, off, mom, rec, step, move, s);
-        else if (geom == FP_CYLINDER2D) collide_dispatch<T, FP_CYLINDER2D>(c, p, off, mom, rec, step, move, s);
-        else collide_dispatch<T, FP_COUETTE1D>(c, p, off, mom, rec, step, move, s);
+        if (geom == FP_CAVITY2D) collide_dispatch<T, FP_CAVITY2D>(c, p, off, mom, rec, step, move, sp, s);
+        else if (geom == FP_CYLINDER2D)
+            collide_dispatch<T, FP_CYLINDER2D>(c, p, off, mom, rec, step, move, sp, s);
+        else collide_dispatch<T, FP_COUETTE1D>(c, p, off, mom, rec, step, move, sp, s);
         return;
     }
     if (p->n == 0) return;
@@ -475,15 +482,15 @@ static void step_typed(fp_ctx* c, fp_particles* p, const int32_t* off, const dou
     if (geom == FP_CAVITY2D)
         hipLaunchKernelGGL((move_kernel<T, FP_CAVITY2D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
                            p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
-                           step, keys_only);
+                           step, keys_only, sp);
     else if (geom == FP_CYLINDER2D)
         hipLaunchKernelGGL((move_kernel<T, FP_CYLINDER2D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
                            p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
-                           step, keys_only);
+                           step, keys_only, sp);
     else
         hipLaunchKernelGGL((move_kernel<T, FP_COUETTE1D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
                            p->n, (T*)p->x, (T*)nullptr, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid,
-                           p->key, step, keys_only);
+                           p->key, step, keys_only, sp);
 }
 
 
@@ -590,12 +597,22 @@ int launch_inject(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_next, ui
 }
 
 int launch_step(fp_ctx* c, fp_particles* p, const int32_t* offsets, const double* mom,
-                const double* rec, uint64_t step, uint32_t flags, hipStream_t s) {
+                const double* rec, uint64_t step, uint32_t flags, const uint32_t* step_dev,
+                hipStream_t s) {
     if (c->cfg.precision == FP_F32)
-        step_typed<float>(c, p, offsets, mom, rec, (uint32_t)step, flags, s);
+        step_typed<float>(c, p, offsets, mom, rec, (uint32_t)step, flags, step_dev, s);
     else
-        step_typed<double>(c, p, offsets, mom, rec, (uint32_t)step, flags, s);
+        step_typed<double>(c, p, offsets, mom, rec, (uint32_t)step, flags, step_dev, s);
     return check_launch(c, "fp_step");
+}
+
+__global__ void counter_add_kernel(uint32_t* __restrict__ ctr, uint32_t inc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] += inc;
+}
+
+int launch_counter_add(fp_ctx* c, uint32_t* ctr, uint32_t inc, hipStream_t s) {
+    hipLaunchKernelGGL(counter_add_kernel, dim3(1), dim3(64), 0, s, ctr, inc);
+    return check_launch(c, "fp_counter_add");
 }
 
 }  // namespace fpg

@@ -72,6 +72,8 @@ def load():
         L.fp_closure_solve.argtypes = [vp, vp, vp, vp, vp]
         L.fp_step.argtypes = [vp, P(FPParticles), vp, vp, vp, u64, u32, vp]
         L.fp_sample.argtypes = [vp, vp, vp, vp]
+        L.fp_step_dev.argtypes = [vp, P(FPParticles), vp, vp, vp, vp, u32, vp]
+        L.fp_counter_add.argtypes = [vp, vp, u32, vp]
         L.fp_inject.argtypes = [vp, P(FPParticles), i64, vp, u64, vp]
         L.fp_inject_slots.argtypes = [vp]
         L.fp_inject_slots.restype = i64
@@ -94,7 +96,7 @@ def load():
                   "fp_nn_load", "fp_closure_nn", "fp_nn_outputs", "fp_nn_features",
                   "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
                   "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
-                  "fp_inject", "fp_cell_volumes"):
+                  "fp_inject", "fp_cell_volumes", "fp_step_dev", "fp_counter_add"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -251,6 +253,15 @@ class Context:
     def sample(self, mom, samp, stream=None):
         self._check(self.lib.fp_sample(self.h, _ptr(mom), _ptr(samp), _stream(stream)), "fp_sample")
 
+    def step_dev(self, p, offsets, mom, rec, step_dev, flags, stream=None):
+        a = p.struct()
+        self._check(self.lib.fp_step_dev(self.h, C.byref(a), _ptr(offsets), _ptr(mom), _ptr(rec),
+                                         _ptr(step_dev), int(flags), _stream(stream)), "fp_step_dev")
+
+    def counter_add(self, ctr, inc, stream=None):
+        self._check(self.lib.fp_counter_add(self.h, _ptr(ctr), int(inc), _stream(stream)),
+                    "fp_counter_add")
+
     def inject(self, p, at, pid_next, step, stream=None):
         a = p.struct()
         self._check(self.lib.fp_inject(self.h, C.byref(a), int(at), _ptr(pid_next), int(step),
@@ -373,6 +384,50 @@ class Simulation:
         n_skip = self.w.get("n_skip", 0) if n_skip is None else n_skip
         for s in range(step0, step0 + nsteps):
             self.step(s, sample=s >= n_skip)
+
+
+class GraphSimulation(Simulation):
+    """Simulation whose step is captured once in a HIP graph (torch.cuda.CUDAGraph) and
+    replayed; the Philox step number lives in device memory and the captured step
+    advances it.  Two steps are captured back to back so that the particle ping-pong
+    buffers return to their places; graphs with and without sampling are kept."""
+
+    def __init__(self, w, state, step0=0, device="cuda"):
+        super().__init__(w, state, device)
+        self.step_ctr = torch.tensor([step0], dtype=torch.int32, device=device)
+        self.graphs = {}
+
+    def _body(self, sample):
+        for _ in range(2):
+            self.ctx.bin(self.a, self.b, self.offsets)
+            self.a, self.b = self.b, self.a
+            self.ctx.moments(self.a, self.offsets, self.mom)
+            if sample:
+                self.ctx.sample(self.mom, self.samp)
+            self.ctx.closure_solve(self.mom, self.rec, self.status)
+            self.ctx.step_dev(self.a, self.offsets, self.mom, self.rec, self.step_ctr,
+                              STEP_COLLIDE | STEP_MOVE)
+            self.ctx.counter_add(self.step_ctr, 1)
+
+    def _graph(self, sample):
+        if sample not in self.graphs:
+            g = torch.cuda.CUDAGraph()
+            torch.cuda.synchronize()
+            saved = self.step_ctr.clone()
+            samp = self.samp.clone()
+            with torch.cuda.graph(g):
+                self._body(sample)
+            torch.cuda.synchronize()
+            self.step_ctr.copy_(saved)   # capture does not execute; keep the counter anyway
+            self.samp.copy_(samp)
+            self.graphs[sample] = g
+        return self.graphs[sample]
+
+    def run_pairs(self, npairs, sample=False):
+        """Advance 2 * npairs steps by graph replays."""
+        g = self._graph(sample)
+        for _ in range(npairs):
+            g.replay()
 
 
 class OpenSimulation:

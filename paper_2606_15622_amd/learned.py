@@ -171,3 +171,120 @@ def fields(w, samp):
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def couette_dataset(kns=(0.1, 0.5), n_transient=500, n_samples=5000, seed=1, device="cuda"):
+    """Moment records of the FP64 Couette channel (100 cells x 100 particles) at the given
+    Knudsen numbers: n_transient steps, then every step of n_samples."""
+    from . import inputs as I
+    moms = []
+    for i, kn in enumerate(kns):
+        w = I.couette(kn=kn, ncell=100, ppc=100, precision="f64", seed=seed + i)
+        state = I.maxwellian_state(w)
+        moms.append(harvest(w, state, n_transient, n_samples))
+    return torch.cat(moms, 0)
+
+
+def closure_timings(w, params, ncells=1_000_000, reps=20, seed=0, device="cuda"):
+    """Kernel times of the exact and learned closure on a synthetic batch of cells with
+    the moment records of a Couette harvest (HIP events on the launch stream)."""
+    from . import inputs as I
+    mom = couette_dataset(kns=(0.5,), n_transient=50, n_samples=max(ncells // 100, 1),
+                          seed=seed)[:ncells].contiguous()
+    n = mom.shape[0]
+    wd = dict(w, geometry="couette1d", nx=n, ny=1, lx=float(w["dx"]) * n, ly=1.0, dy=1.0)
+    ctx = F.Context(wd, 1)
+    net = F.Network(ctx, 0)
+    net.load(params)
+    rec = torch.zeros((n, F.REC_STRIDE), dtype=torch.float64, device=device)
+    st = torch.zeros(n, dtype=torch.int32, device=device)
+
+    def timeit(fn):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps * 1e-3
+
+    t_exact = timeit(lambda: ctx.closure_solve(mom, rec, st))
+    t_nn = timeit(lambda: net.closure(mom, rec, st, 0.05, 0.05))
+    fb = float(((st == F.CELL_NN_FALLBACK).sum()).item()) / max(n, 1)
+    return {"cells": n, "exact_s": t_exact, "learned_s": t_nn,
+            "exact_cells_per_s": n / t_exact, "learned_cells_per_s": n / t_nn,
+            "learned_fallback_fraction": fb}
+
+
+def main(argv=None):
+    """Configuration 3: train the surrogate on 1e6 Couette moment/coefficient pairs
+    (Kn 0.1 and 0.5) with the library's MFMA kernels, then run the 100 x 100 cavity at
+    Kn 1.0 with the learned closure (exact fallback), the exact closure (two seeds: the
+    seed-to-seed noise floor) and the Langevin drift, with common random numbers."""
+    import argparse
+    import json
+    import time
+    from . import inputs as I
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--samples", type=int, default=5000)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--avg", type=int, default=2000)
+    ap.add_argument("--tol", type=float, default=0.05)
+    ap.add_argument("--save", default=None, help="write the trained parameters (.npy)")
+    a = ap.parse_args(argv)
+    res = {}
+    t0 = time.time()
+    mom = couette_dataset(n_samples=a.samples)
+    feats, tg, sys = dataset(I.couette(), mom)
+    res["pairs"] = int(feats.shape[0])
+    res["harvest_s"] = time.time() - t0
+    sc = fit_scalers(feats, tg)
+    p0 = init_params(sc, seed=0)
+    t1 = time.time()
+    params, hist = train(I.couette(), p0, feats, tg, epochs=a.epochs, lr=a.lr, patience=10,
+                         log=lambda s: print(s, flush=True))
+    torch.cuda.synchronize()
+    res["train_s"] = time.time() - t1
+    res["val_loss"] = hist
+    if a.save:
+        np.save(a.save, params.cpu().numpy())
+    w = I.cavity(kn=1.0, ncell=100, ppc=100, precision="f32", n_steps=a.steps,
+                 n_skip=a.steps - a.avg)
+    runs = {}
+    for name, seed, kw in (("exact", 1, {}), ("exact_seed2", 2, {}),
+                           ("learned", 1, {"params": params, "tol_abs": a.tol, "tol_rel": a.tol}),
+                           ("langevin", 1, {"langevin": True})):
+        ww = dict(w, seed=seed)
+        sim = LearnedSimulation(ww, I.maxwellian_state(ww), **kw)
+        nn_cells = fb_cells = 0
+        torch.cuda.synchronize()
+        t = time.time()
+        for s in range(a.steps):
+            sim.step(s, sample=s >= w["n_skip"])
+            if name == "learned" and s % 50 == 0:
+                nn_cells += int((sim.status == F.CELL_NN).sum())
+                fb_cells += int((sim.status == F.CELL_NN_FALLBACK).sum())
+        torch.cuda.synchronize()
+        el = time.time() - t
+        runs[name] = fields(ww, sim.samp)
+        res[f"{name}_particle_steps_per_s"] = 1e6 * a.steps / el
+        if name == "learned":
+            res["learned_fallback_fraction"] = fb_cells / max(nn_cells + fb_cells, 1)
+    for name in ("learned", "exact_seed2", "langevin"):
+        res[f"relL2_{name}_vs_exact"] = {k: rel_l2(runs[name][k], runs["exact"][k])
+                                         for k in ("U", "T", "rho", "p")}
+    res["closure_timing"] = closure_timings(w, params)
+    print(json.dumps(res))
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+    return res
+
+
+if __name__ == "__main__":
+    main()

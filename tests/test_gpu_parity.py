@@ -381,3 +381,32 @@ def test_cavity_full_size_one_step():
     for k in ("vx", "vy", "vz"):
         assert np.abs(g[k] - o[k]).max() <= 1e-5 * sc, k
     assert np.abs(g["x"] - o["x"]).max() <= 1e-6 * w["lx"]
+
+
+def test_graph_replay_matches_eager_bitwise():
+    """The step captured once in a HIP graph and replayed equals the eager loop, on
+    every replay, with eager work and synchronisations between the replays."""
+    F = fp()
+    w = I.cavity(kn=1.0, ncell=40, ppc=100, precision="f32", seed=8)
+    s = I.maxwellian_state(w)
+    eager = F.Simulation(w, s)
+    graph = F.GraphSimulation(w, s, step0=2)
+    for k in range(2):                       # eager warm-up on both (loads every kernel)
+        eager.step(k, sample=True)
+        graph.step(k, sample=True)
+    step = 2
+    for rep in range(4):
+        sample = rep % 2 == 1
+        graph.run_pairs(1, sample=sample)
+        for _ in range(2):
+            eager.step(step, sample=sample)
+            step += 1
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()      # unrelated eager work
+        ga, ea = graph.a.numpy(), eager.a.numpy()
+        for k in ea:
+            np.testing.assert_array_equal(ga[k], ea[k], err_msg=f"replay {rep} {k}")
+        assert torch.equal(graph.samp, eager.samp)
+        assert torch.equal(graph.mom, eager.mom)
+        assert int(graph.step_ctr.cpu()[0]) == step
+        del junk
