@@ -54,32 +54,44 @@ static int validate(const fp_config* g, std::string& why) {
 }
 
 // ---- exact gas volume of the cells of the cylinder domain ------------------------------
-// Coordinates relative to the circle centre.  I(x) = int_{-R}^{x} sqrt(R^2 - X^2) dX and
-// G(x, y) = area of the disk part with X <= x and Y <= y; a rectangle's covered area is
-// G(xb,yb) - G(xa,yb) - G(xb,ya) + G(xa,ya).
-static double half_int(double x, double R) {
-    if (x <= -R) return 0.0;
-    if (x >= R) return 0.5 * M_PI * R * R;
-    return 0.5 * (x * std::sqrt(R * R - x * x) + R * R * std::asin(x / R)) + 0.25 * M_PI * R * R;
+// Coordinates relative to the circle centre.  The covered length of a vertical line at x
+// is min(yb, h) - max(ya, -h), h = sqrt(R^2 - x^2); its integral over the cell is split
+// where the chord ends cross the cell edges, and every piece uses
+//   I(x) = int_{-R}^{x} h dX = R^2 (phi - sin(phi) cos(phi)) / 2,  phi = acos(-x / R),
+// which, unlike the arcsine form, keeps its accuracy next to x = +-R.
+static double chord_int(double x, double R) {
+    const double t = std::max(-1.0, std::min(1.0, -x / R));
+    const double phi = std::acos(t);
+    return 0.5 * R * R * (phi - std::sin(phi) * std::cos(phi));
 }
 
-static double corner_area(double x, double y, double R) {
-    if (x <= -R || y <= -R || R <= 0.0) return 0.0;
-    if (x > R) x = R;
-    if (y >= R) return 2.0 * half_int(x, R);
-    const double a = std::sqrt(R * R - y * y);
-    if (y >= 0.0) {   // chord 2h outside |X| < a, y + h inside
-        double t = 2.0 * half_int(std::min(x, -a), R);
-        if (x > -a) {
-            const double x2 = std::min(x, a);
-            t += y * (x2 + a) + (half_int(x2, R) - half_int(-a, R));
+static double covered_area(double xa, double xb, double ya, double yb, double R) {
+    const double lo = std::max(xa, -R), hi = std::min(xb, R);
+    if (!(lo < hi)) return 0.0;
+    double br[6];
+    int nb = 0;
+    br[nb++] = lo;
+    br[nb++] = hi;
+    for (double y : {ya, yb})
+        if (std::fabs(y) < R) {
+            const double a = std::sqrt(R * R - y * y);
+            if (-a > lo && -a < hi) br[nb++] = -a;
+            if (a > lo && a < hi) br[nb++] = a;
         }
-        if (x > a) t += 2.0 * (half_int(x, R) - half_int(a, R));
-        return t;
+    std::sort(br, br + nb);
+    double tot = 0.0;
+    for (int k = 0; k + 1 < nb; ++k) {
+        const double p = br[k], q = br[k + 1];
+        if (!(q > p)) continue;
+        const double m = 0.5 * (p + q);
+        const double h = std::sqrt(std::max(R * R - m * m, 0.0));
+        if (std::min(yb, h) <= std::max(ya, -h)) continue;
+        const double dI = chord_int(q, R) - chord_int(p, R);
+        const double up = h < yb ? dI : yb * (q - p);      // integral of min(yb, h)
+        const double dn = -h > ya ? -dI : ya * (q - p);    // integral of max(ya, -h)
+        tot += up - dn;
     }
-    if (x <= -a) return 0.0;   // y < 0: only |X| < a contributes, y + h
-    const double x2 = std::min(x, a);
-    return y * (x2 + a) + (half_int(x2, R) - half_int(-a, R));
+    return tot;
 }
 
 static void gas_volumes(const fp_config& g, std::vector<double>& vol) {
@@ -89,11 +101,9 @@ static void gas_volumes(const fp_config& g, std::vector<double>& vol) {
     if (g.geometry != FP_CYLINDER2D) return;
     for (int32_t ky = 0; ky < g.ny; ++ky)
         for (int32_t kx = 0; kx < g.nx; ++kx) {
-            const double xa = g.x0 + kx * g.dx - cx, xb = xa + g.dx;
-            const double ya = g.y0 + ky * g.dy - cy, yb = ya + g.dy;
-            const double cov = corner_area(xb, yb, R) - corner_area(xa, yb, R) -
-                               corner_area(xb, ya, R) + corner_area(xa, ya, R);
-            double v = full - cov;
+            const double xa = g.x0 + kx * g.dx, xb = xa + g.dx;
+            const double ya = g.y0 + ky * g.dy, yb = ya + g.dy;
+            double v = full - (R > 0.0 ? covered_area(xa - cx, xb - cx, ya - cy, yb - cy, R) : 0.0);
             if (v < 1e-12 * full) v = 0.0;
             vol[(size_t)ky * g.nx + kx] = v * g.depth;
         }

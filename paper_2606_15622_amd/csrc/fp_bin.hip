@@ -244,7 +244,7 @@ static void gather_launch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
                           const int32_t* offsets, int32_t* perm, hipStream_t s) {
     const int groups = GatherShape<G>::GROUPS;
     const int grid = (c->ncell + groups - 1) / groups;
-    const bool two_d = c->cfg.geometry == FP_CAVITY2D;
+    const bool two_d = c->cfg.geometry != FP_COUETTE1D;
     hipLaunchKernelGGL((bin_gather_kernel<T, G>), dim3(grid), dim3(BIN_BLOCK), 0, s, c->ncell,
                        offsets, c->coff, c->cwave, c->cmask, c->gidx, (const T*)src->x,
                        two_d ? (const T*)src->y : (const T*)nullptr, (const T*)src->vx,

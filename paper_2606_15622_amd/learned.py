@@ -218,6 +218,26 @@ def closure_timings(w, params, ncells=1_000_000, reps=20, seed=0, device="cuda")
             "learned_fallback_fraction": fb}
 
 
+def cavity_cells(kns=(0.1, 0.5, 1.0), ncell=100, n_transient=300, n_samples=200, every=10,
+                 seed=7):
+    """Moment records of solved cavity cells (snapshots every `every` steps after a
+    transient) at several Knudsen numbers."""
+    from . import inputs as I
+    moms = []
+    for i, kn in enumerate(kns):
+        w = I.cavity(kn=kn, ncell=ncell, ppc=100, precision="f32", seed=seed + i)
+        moms.append(harvest(w, I.maxwellian_state(w), n_transient, n_samples, every=every))
+    return torch.cat(moms, 0)
+
+
+def finetune(w, params, mom, batch=200_000, epochs=20, lr=1e-4, seed=0, log=None):
+    """Fine-tune on the closure residual |A y - b|^2 of the cells' own normalised systems
+    (no targets needed), batches of `batch` cells; returns (params, history)."""
+    feats, tg, sys = dataset(w, mom)
+    return train(w, params, feats, tg, sys=sys, loss_kind=F.LOSS_RESIDUAL, epochs=epochs,
+                 batch=batch, lr=lr, patience=epochs, seed=seed, log=log)
+
+
 def main(argv=None):
     """Configuration 3: train the surrogate on 1e6 Couette moment/coefficient pairs
     (Kn 0.1 and 0.5) with the library's MFMA kernels, then run the 100 x 100 cavity at
@@ -236,6 +256,8 @@ def main(argv=None):
     ap.add_argument("--avg", type=int, default=2000)
     ap.add_argument("--tol", type=float, default=0.05)
     ap.add_argument("--save", default=None, help="write the trained parameters (.npy)")
+    ap.add_argument("--finetune", type=int, default=10,
+                    help="epochs of closure-residual fine-tuning on cavity cells (0: none)")
     a = ap.parse_args(argv)
     res = {}
     t0 = time.time()
@@ -253,12 +275,25 @@ def main(argv=None):
     res["val_loss"] = hist
     if a.save:
         np.save(a.save, params.cpu().numpy())
+    if a.finetune:
+        t2 = time.time()
+        cmom = cavity_cells()
+        res["finetune_cells"] = int(cmom.shape[0])
+        params_ft, hist_ft = finetune(I.couette(), params.clone(), cmom, epochs=a.finetune,
+                                      log=lambda s: print("finetune", s, flush=True))
+        res["finetune_residual_loss"] = hist_ft
+        res["finetune_s"] = time.time() - t2
+    else:
+        params_ft = None
     w = I.cavity(kn=1.0, ncell=100, ppc=100, precision="f32", n_steps=a.steps,
                  n_skip=a.steps - a.avg)
     runs = {}
-    for name, seed, kw in (("exact", 1, {}), ("exact_seed2", 2, {}),
-                           ("learned", 1, {"params": params, "tol_abs": a.tol, "tol_rel": a.tol}),
-                           ("langevin", 1, {"langevin": True})):
+    cases = [("exact", 1, {}), ("exact_seed2", 2, {}),
+             ("learned", 1, {"params": params, "tol_abs": a.tol, "tol_rel": a.tol}),
+             ("langevin", 1, {"langevin": True})]
+    if params_ft is not None:
+        cases.append(("learned_ft", 1, {"params": params_ft, "tol_abs": a.tol, "tol_rel": a.tol}))
+    for name, seed, kw in cases:
         ww = dict(w, seed=seed)
         sim = LearnedSimulation(ww, I.maxwellian_state(ww), **kw)
         nn_cells = fb_cells = 0
@@ -266,16 +301,16 @@ def main(argv=None):
         t = time.time()
         for s in range(a.steps):
             sim.step(s, sample=s >= w["n_skip"])
-            if name == "learned" and s % 50 == 0:
+            if name.startswith("learned") and s % 50 == 0:
                 nn_cells += int((sim.status == F.CELL_NN).sum())
                 fb_cells += int((sim.status == F.CELL_NN_FALLBACK).sum())
         torch.cuda.synchronize()
         el = time.time() - t
         runs[name] = fields(ww, sim.samp)
         res[f"{name}_particle_steps_per_s"] = 1e6 * a.steps / el
-        if name == "learned":
-            res["learned_fallback_fraction"] = fb_cells / max(nn_cells + fb_cells, 1)
-    for name in ("learned", "exact_seed2", "langevin"):
+        if name.startswith("learned"):
+            res[f"{name}_fallback_fraction"] = fb_cells / max(nn_cells + fb_cells, 1)
+    for name in [c[0] for c in cases if c[0] != "exact"]:
         res[f"relL2_{name}_vs_exact"] = {k: rel_l2(runs[name][k], runs["exact"][k])
                                          for k in ("U", "T", "rho", "p")}
     res["closure_timing"] = closure_timings(w, params)

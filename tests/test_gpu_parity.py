@@ -127,7 +127,7 @@ def test_bin_drops_invalid_keys_and_counts_them():
     w = I.cavity(ncell=10, precision="f32")
     s = I.scattered_state(w, 5000, seed=9)
     s["key"] = O.keys(w, s["x"], s["y"])
-    s["key"][[3, 77, 4000]] = [-1, 100, 10**6]
+    s["key"][[3, 77, 4000]] = [-1, 101, 10**6]      # 100 (= ncell) means deleted, not an error
     ctx = F.Context(w, 5000)
     a = F.Particles.from_numpy(w, s)
     b = F.Particles(5000, a.dtype, True)
