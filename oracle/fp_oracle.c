@@ -97,17 +97,20 @@ void or_keys(const or_config* cfg, int64_t n, const double* x, const double* y, 
 }
 
 /* Stable counting sort (sort step of the loop): slot order within a cell is the
- * previous order of the particles.  Particles with key == ncell are dropped. */
+ * previous order of the particles.  Particles with key == ncell (deleted) or a key
+ * outside [0, ncell] are dropped. */
 void or_bin(int32_t ncell, int64_t n, const int32_t* key, int64_t* perm, int32_t* offsets)
 {
     for (int32_t c = 0; c <= ncell; ++c) offsets[c] = 0;
+    /* key == ncell marks a deleted particle; keys outside [0, ncell] name no cell: both
+       take no part in the sort */
     for (int64_t p = 0; p < n; ++p)
-        if (key[p] < ncell) offsets[key[p] + 1] += 1;     /* key == ncell: deleted */
+        if (key[p] >= 0 && key[p] < ncell) offsets[key[p] + 1] += 1;
     for (int32_t c = 0; c < ncell; ++c) offsets[c + 1] += offsets[c];
     int32_t* cursor = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ncell > 0 ? ncell : 1));
     for (int32_t c = 0; c < ncell; ++c) cursor[c] = offsets[c];
     for (int64_t p = 0; p < n; ++p)
-        if (key[p] < ncell) perm[cursor[key[p]]++] = p;
+        if (key[p] >= 0 && key[p] < ncell) perm[cursor[key[p]]++] = p;
     free(cursor);
 }
 

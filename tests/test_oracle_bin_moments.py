@@ -35,6 +35,23 @@ def test_bin_is_stable_counting_sort():
         np.testing.assert_array_equal(off, np.searchsorted(np.sort(key), np.arange(ncell + 1)))
 
 
+def test_bin_drops_deleted_and_invalid_keys():
+    """key == ncell (deleted) and keys outside [0, ncell] take no part; the kept
+    particles come out in the stable order of their keys (numpy's stable argsort of the
+    kept subset)."""
+    rng = np.random.default_rng(1)
+    ncell, n = 50, 5000
+    key = rng.integers(0, ncell, n).astype(np.int32)
+    key[rng.random(n) < 0.1] = ncell
+    key[rng.choice(n, 7, replace=False)] = [-1, -100, ncell + 1, 10**6, -2**31, 2**31 - 1, ncell + 5]
+    perm, off = O.bin_particles(ncell, key)
+    keep = np.nonzero((key >= 0) & (key < ncell))[0]
+    ref = keep[np.argsort(key[keep], kind="stable")]
+    assert off[-1] == keep.size
+    np.testing.assert_array_equal(perm[: keep.size], ref)
+    np.testing.assert_array_equal(off, np.searchsorted(np.sort(key[keep]), np.arange(ncell + 1)))
+
+
 def _brute_moments(v):
     n = v.shape[0]
     U = v.mean(axis=0)
