@@ -39,47 +39,52 @@ def parse():
     return ap.parse_args()
 
 
-# algorithmic bytes per launch of each entry point (FP32 2-D particles):
+# algorithmic bytes per launch of each entry point (FP32 2-D particles): what the
+# operation must move at least, once each
 #   step (collide+move): read x y vx vy vz pid, write x y vx vy vz key = 48 B/particle;
 #                        per cell offsets 8 B, rec 128 B, U and T of mom 104 B
 #   moments:             read vx vy vz = 12 B/particle; per cell offsets 8 B + 256 B out
-#   bin:                 key read twice 8 B, gather read 24 B, write 28 B = 60 B/particle
+#   sort:                read key x y vx vy vz pid 28 B, write the same 28 B = 56 B/particle;
+#                        per cell 8 B of old and 4 B of new offsets
 #   closure:             256 B in + 128 B + 4 B out per cell
+#   sample:              256 B of moments in, 128 B of sums read and written per cell
 def alg_bytes(kind, n, nc):
     return {"step": 48 * n + 240 * nc, "moments": 12 * n + 264 * nc,
-            "bin": 60 * n + 24 * nc, "closure": 388 * nc, "sample": 384 * nc}[kind]
+            "sort": 56 * n + 12 * nc, "closure": 388 * nc, "sample": 512 * nc}[kind]
 
 
-class Timed:
-    """Wraps the Context calls with HIP events recorded on the launch stream."""
-
-    def __init__(self, torch, ctx):
-        self.torch = torch
-        self.ctx = ctx
-        self.ev = {}
-
-    def call(self, kind, fn, *a):
-        t = self.torch
-        s, e = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
-        s.record(t.cuda.current_stream())
-        fn(*a)
-        e.record(t.cuda.current_stream())
-        self.ev.setdefault(kind, []).append((s, e))
-
-    def means_ms(self):
-        return {k: float(np.mean([s.elapsed_time(e) for s, e in v])) for k, v in self.ev.items()}
+def time_entry(torch, fn, reps):
+    """Mean duration of one call of fn: reps calls captured in a HIP graph, the replay
+    bracketed by HIP events on the launch stream (no host launch gaps inside)."""
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    g.replay()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
 
 
-def timed_step(T, sim, s, sample):
-    F = sim.F
+def entry_times(torch, F, sim, s, reps=20):
+    """Per-entry-point durations on the state the loop left: sort (a -> b), then moments,
+    sample, closure and collide + move on b; each entry point repeated reps times on the
+    same inputs (idempotent except collide + move, which keeps flying the same cells)."""
     ctx = sim.ctx
-    T.call("bin", ctx.bin, sim.a, sim.b, sim.offsets)
-    sim.a, sim.b = sim.b, sim.a
-    T.call("moments", ctx.moments, sim.a, sim.offsets, sim.mom)
-    if sample:
-        T.call("sample", ctx.sample, sim.mom, sim.samp)
-    T.call("closure", ctx.closure_solve, sim.mom, sim.rec, sim.status)
-    T.call("step", ctx.step, sim.a, sim.offsets, sim.mom, sim.rec, s, F.STEP_COLLIDE | F.STEP_MOVE)
+    a, b, o0, o1 = sim.a, sim.b, sim.offs[0], sim.offs[1]
+    st = torch.tensor([s], dtype=torch.int32, device="cuda")
+    out = {"sort": time_entry(torch, lambda: ctx.rebin(a, o0, b, o1), reps)}
+    out["moments"] = time_entry(torch, lambda: ctx.moments(b, o1, sim.mom), reps)
+    samp = sim.samp.clone()
+    out["sample"] = time_entry(torch, lambda: ctx.sample(sim.mom, samp), reps)
+    out["closure"] = time_entry(torch, lambda: ctx.closure_solve(sim.mom, sim.rec, sim.status), reps)
+    out["step"] = time_entry(torch, lambda: ctx.step_dev(b, o1, sim.mom, sim.rec, st,
+                                                         F.STEP_COLLIDE | F.STEP_MOVE), reps)
+    return out
 
 
 def run_workload(torch, F, I, w, steps, warmup, graph=True):
@@ -112,13 +117,8 @@ def run_workload(torch, F, I, w, steps, warmup, graph=True):
     t = time.perf_counter() - t0
     if graph:
         s = int(sim.step_ctr.cpu()[0])
-    # per-entry-point durations over a second, event-instrumented pass
-    T = Timed(torch, sim.ctx)
-    for _ in range(min(steps, 50)):
-        timed_step(T, sim, s, True)
-        s += 1
-    torch.cuda.synchronize()
-    ms = T.means_ms()
+    # per-entry-point durations (graph-replayed repeats, HIP events)
+    ms = entry_times(torch, F, sim, s)
     kern = {}
     for k, v in ms.items():
         gbs = alg_bytes(k, n, nc) / (v * 1e-3) / 1e9
@@ -171,7 +171,7 @@ def main():
     pps = n * res["steps"] / res["t"]
     kern = res["kern"]
     dominant = max((k for k in kern if k in ("step", "moments", "closure")),
-                   key=lambda k: kern[k]["ms"])
+                   key=lambda k: kern[k]["ms"])   # single-kernel entry points
     out = {
         "metric": "particle-steps/s (cubic-FP step, exact closure)",
         "value": round(pps, 1),

@@ -76,7 +76,8 @@ typedef struct fp_config {
     int32_t nx, ny;          /* cells along x, y (ny = 1 for the 1-D channel) */
     int32_t n_min;           /* cells with fewer particles use the Langevin drift */
     int32_t max_bounces;     /* wall interactions per particle and step */
-    int32_t reserved0;
+    int32_t lanes;           /* lanes per cell of the per-cell kernels: 4, 8, 16, 32 or 64;
+                                0 = chosen from the particle and cell counts */
     int64_t capacity;        /* largest particle count any call will see */
     double x0, y0;           /* domain origin [m] */
     double lx, ly;           /* domain extent [m] */
@@ -133,6 +134,19 @@ int64_t fp_error_count(fp_ctx* ctx, hipStream_t s);
  * [0, ncell] are counted by fp_error_count and dropped as well. */
 int fp_bin(fp_ctx* ctx, const fp_particles* src, fp_particles* dst, int32_t* offsets,
            int32_t* perm, hipStream_t s);
+
+/* The sort of fp_bin (the same result, bit for bit) for particles that were sorted by cell
+ * one step earlier: the first src_offsets[ncell] particles of src are grouped by their
+ * previous cell, those of cell c at [src_offsets[c], src_offsets[c+1]) (src_offsets is
+ * what fp_bin or fp_rebin wrote then; fp_step has since given them new keys), and any
+ * particles after them (e.g. injected ones) are in no particular order.  A particle
+ * whose new cell is one of the 3 x 3 cells around its previous one is placed from
+ * per-cell direction counts, without global atomics; the others take a general path
+ * that is slower per particle.  src_offsets and offsets must not alias (keep two
+ * offsets arrays and alternate them); src_offsets must be non-decreasing with
+ * src_offsets[0] >= 0 and src_offsets[ncell] <= src->n. */
+int fp_rebin(fp_ctx* ctx, const fp_particles* src, const int32_t* src_offsets,
+             fp_particles* dst, int32_t* offsets, int32_t* perm, hipStream_t s);
 
 /* Central moments of every cell of particles sorted by cell (moments u^(p) entering
  * eq. system9x9 and Table matrix_system; layout mom above). */

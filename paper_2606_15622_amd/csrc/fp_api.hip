@@ -36,6 +36,9 @@ static int validate(const fp_config* g, std::string& why) {
     if (g->geometry == FP_COUETTE1D && g->ny != 1) return why = "1-D grid needs ny = 1", 0;
     if (g->capacity < 0 || g->capacity > ((int64_t)1 << 31) - 64) return why = "capacity", 0;
     if (g->max_bounces < 0 || g->max_bounces > 1000) return why = "max_bounces", 0;
+    if (g->lanes != 0 && g->lanes != 4 && g->lanes != 8 && g->lanes != 16 && g->lanes != 32 &&
+        g->lanes != 64)
+        return why = "lanes", 0;
     if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->lx) || !finite_pos(g->ly) ||
         !finite_pos(g->dt) || !finite_pos(g->kB) || !finite_pos(g->mass) ||
         !finite_pos(g->mu_ref) || !finite_pos(g->T_ref) || !finite_pos(g->fnum_over_vol))
@@ -135,8 +138,13 @@ extern "C" int fp_init(const fp_config* cfg, fp_ctx** out) {
     bool ok = dalloc(&c->cnt, nc) && dalloc(&c->ccnt, nc) && dalloc(&c->coff, nc + 1) &&
               dalloc(&c->ccur, nc) && dalloc(&c->cwave, cap) && dalloc(&c->cmask, cap) &&
               dalloc(&c->gidx, cap) && dalloc(&c->blocksum, 2 * 8192) &&
-              dalloc(&c->errcount, 1);
-    if (ok) ok = hipMemset(c->errcount, 0, sizeof(unsigned long long)) == hipSuccess;
+              dalloc(&c->errcount, 1) && dalloc(&c->ncnt, 9 * (nc - 1) + 1) && dalloc(&c->farn, 1);
+    // the sort counters start at zero; every fp_bin / fp_rebin leaves them zero again
+    if (ok) ok = hipMemset(c->errcount, 0, sizeof(unsigned long long)) == hipSuccess &&
+                 hipMemset(c->cnt, 0, sizeof(int32_t) * nc) == hipSuccess &&
+                 hipMemset(c->ccnt, 0, sizeof(int32_t) * nc) == hipSuccess &&
+                 hipMemset(c->ccur, 0, sizeof(int32_t) * nc) == hipSuccess &&
+                 hipMemset(c->farn, 0, sizeof(int32_t)) == hipSuccess;
     if (ok && cfg->geometry == FP_CYLINDER2D) {
         std::vector<double> vol, nvol;
         gas_volumes(*cfg, vol);
@@ -190,6 +198,8 @@ extern "C" void fp_destroy(fp_ctx* c) {
     (void)hipFree(c->gidx);
     (void)hipFree(c->blocksum);
     (void)hipFree(c->errcount);
+    (void)hipFree(c->ncnt);
+    (void)hipFree(c->farn);
     (void)hipFree(c->vol);
     (void)hipFree(c->nvol);
     (void)hipFree(c->inj);
@@ -225,6 +235,19 @@ extern "C" int fp_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int
     if (src->vx == dst->vx || src->x == dst->x || src->pid == dst->pid)
         return set_err(c, FP_EINVAL, "fp_bin: src and dst alias");
     return launch_bin(c, src, dst, offsets, perm, s);
+}
+
+extern "C" int fp_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_offsets,
+                        fp_particles* dst, int32_t* offsets, int32_t* perm, hipStream_t s) {
+    if (!c || !offsets || !src_offsets || !particles_ok(c, src, true) || !dst)
+        return set_err(c, FP_EINVAL, "fp_rebin: bad argument");
+    if (src->n > 0 && (!dst->vx || !dst->vy || !dst->vz || !dst->pid || !dst->key || !dst->x ||
+                       (c->cfg.geometry != FP_COUETTE1D && !dst->y)))
+        return set_err(c, FP_EINVAL, "fp_rebin: bad destination");
+    if (src->vx == dst->vx || src->x == dst->x || src->pid == dst->pid)
+        return set_err(c, FP_EINVAL, "fp_rebin: src and dst alias");
+    if (src_offsets == offsets) return set_err(c, FP_EINVAL, "fp_rebin: src_offsets and offsets alias");
+    return launch_rebin(c, src, src_offsets, dst, offsets, perm, s);
 }
 
 extern "C" int fp_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,

@@ -281,7 +281,7 @@ static void mb_launch(fp_ctx* c, const fp_particles* p, const int32_t* off, cons
 template <typename T>
 static void mb_dispatch(fp_ctx* c, const fp_particles* p, const int32_t* off, const double* mom,
                         const double* mbar, double* gx, double* gy, double* gz, hipStream_t s) {
-    switch (lanes_per_cell(p->n, c->ncell)) {
+    switch (lanes_per_cell(c, p->n)) {
         case 4: mb_launch<T, 4>(c, p, off, mom, mbar, gx, gy, gz, s); break;
         case 8: mb_launch<T, 8>(c, p, off, mom, mbar, gx, gy, gz, s); break;
         case 16: mb_launch<T, 16>(c, p, off, mom, mbar, gx, gy, gz, s); break;

@@ -13,16 +13,6 @@ namespace fpg {
 
 constexpr int BIN_BLOCK = 256;
 
-__global__ void bin_zero_kernel(int32_t* __restrict__ cnt, int32_t* __restrict__ ccnt,
-                                int32_t* __restrict__ ccur, int32_t len) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < len) {
-        cnt[i] = 0;
-        ccnt[i] = 0;
-        ccur[i] = 0;
-    }
-}
-
 // PLACE = false: count particles and contributions per key.
 // PLACE = true:  write the contribution records at their slots.
 template <bool PLACE>
@@ -171,6 +161,7 @@ template <typename T, int G>
 __global__ __launch_bounds__(BIN_BLOCK) void bin_gather_kernel(
     int32_t ncell, const int32_t* __restrict__ offsets, const int32_t* __restrict__ coff,
     const int32_t* __restrict__ cwave, const uint64_t* __restrict__ cmask,
+    int32_t* __restrict__ cnt, int32_t* __restrict__ ccnt, int32_t* __restrict__ ccur,
     int32_t* __restrict__ gidx, const T* __restrict__ sx, const T* __restrict__ sy,
     const T* __restrict__ svx, const T* __restrict__ svy, const T* __restrict__ svz,
     const uint32_t* __restrict__ spid, T* __restrict__ dx, T* __restrict__ dy,
@@ -181,6 +172,13 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_gather_kernel(
     __shared__ uint64_t s_m[S::GROUPS][S::CAPC];
     __shared__ int32_t s_idx[S::GROUPS][S::CAPP];
 
+    // counters of the count and place passes are spent: leave them zero for the next call
+    for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i <= ncell;
+         i += (int64_t)gridDim.x * BIN_BLOCK) {
+        cnt[i] = 0;
+        ccnt[i] = 0;
+        ccur[i] = 0;
+    }
     const int grp = threadIdx.x / G;
     const int lg = threadIdx.x % G;
     const int32_t cell = blockIdx.x * S::GROUPS + grp;
@@ -246,7 +244,8 @@ static void gather_launch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
     const int grid = (c->ncell + groups - 1) / groups;
     const bool two_d = c->cfg.geometry != FP_COUETTE1D;
     hipLaunchKernelGGL((bin_gather_kernel<T, G>), dim3(grid), dim3(BIN_BLOCK), 0, s, c->ncell,
-                       offsets, c->coff, c->cwave, c->cmask, c->gidx, (const T*)src->x,
+                       offsets, c->coff, c->cwave, c->cmask, c->cnt, c->ccnt, c->ccur, c->gidx,
+                       (const T*)src->x,
                        two_d ? (const T*)src->y : (const T*)nullptr, (const T*)src->vx,
                        (const T*)src->vy, (const T*)src->vz, src->pid, (T*)dst->x,
                        two_d ? (T*)dst->y : (T*)nullptr, (T*)dst->vx, (T*)dst->vy,
@@ -256,7 +255,7 @@ static void gather_launch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
 template <typename T>
 static void gather_dispatch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
                             const int32_t* offsets, int32_t* perm, hipStream_t s) {
-    switch (lanes_per_cell(src->n, c->ncell)) {
+    switch (lanes_per_cell(c, src->n)) {
         case 4: gather_launch<T, 4>(c, src, dst, offsets, perm, s); break;
         case 8: gather_launch<T, 8>(c, src, dst, offsets, perm, s); break;
         case 16: gather_launch<T, 16>(c, src, dst, offsets, perm, s); break;
@@ -265,15 +264,382 @@ static void gather_dispatch(fp_ctx* c, const fp_particles* src, fp_particles* ds
     }
 }
 
+// ---- re-sort of particles that were sorted by cell one step earlier ---------------------
+// After a step almost every particle sits in one of the 3 x 3 cells around its old cell.
+// Pass 1 counts, per old cell, the particles bound for each of those nine neighbours
+// (ncnt, plain stores) and appends every other particle (moved farther, or not grouped)
+// to a short list.  The destination count of a cell is then the sum of nine neighbour
+// entries plus its far arrivals.  In a destination cell the stable order is the order of
+// source indices: the neighbour runs come in the order of their old cells, and a far
+// arrival goes before every run whose old cell starts after it.  So each old cell pushes
+// its particles straight to their slots, and the far arrivals (sorted per destination by
+// source index on the fly) find theirs by counting.  The only global atomics are those of
+// the far list.
+
+__device__ __forceinline__ int near_dir(int32_t k, int32_t cx, int32_t cy, int32_t nx) {
+    const int32_t ky = k / nx, kx = k - ky * nx;
+    const int32_t dx = kx - cx, dy = ky - cy;
+    if (dx < -1 || dx > 1 || dy < -1 || dy > 1) return -1;
+    return (dy + 1) * 3 + (dx + 1);
+}
+
+__device__ __forceinline__ void far_append(int32_t k, int32_t j, int64_t cap, int32_t* farn,
+                                           uint64_t* flist, int32_t* fcnt) {
+    const int32_t slot = atomicAdd(farn, 1);
+    if (slot < cap) flist[slot] = ((uint64_t)(uint32_t)k << 32) | (uint32_t)j;
+    atomicAdd(&fcnt[k], 1);
+}
+
+// grid: ncell*G lanes for the old cells, then FAR_BLOCKS blocks for the ungrouped tail
+constexpr int FAR_BLOCKS = 64;
+
+template <int G>
+__global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
+    int32_t ncell, int32_t nx, int64_t n, int64_t cap, int32_t cell_blocks,
+    const int32_t* __restrict__ src_off, const int32_t* __restrict__ key,
+    int32_t* __restrict__ ncnt, int32_t* __restrict__ fcnt, int32_t* __restrict__ farn,
+    uint64_t* __restrict__ flist, unsigned long long* __restrict__ errcount) {
+    if ((int32_t)blockIdx.x >= cell_blocks) {
+        // particles after the grouped range: all take the general path
+        const int64_t t0 = src_off[ncell];
+        const int64_t stride = (int64_t)FAR_BLOCKS * BIN_BLOCK;
+        for (int64_t j = (t0 > 0 ? t0 : 0) + (int64_t)(blockIdx.x - cell_blocks) * BIN_BLOCK +
+                         threadIdx.x;
+             j < n; j += stride) {
+            const int32_t k = key[j];
+            if (k == ncell) continue;
+            if (k < 0 || k > ncell) {
+                atomicAdd(errcount, 1ull);
+                continue;
+            }
+            far_append(k, (int32_t)j, cap, farn, flist, fcnt);
+        }
+        return;
+    }
+    const int64_t gt = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x;
+    const int32_t cell = (int32_t)(gt / G);
+    const int lg = (int)(gt % G);
+    int c9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (cell < ncell) {
+        const int32_t b = max(src_off[cell], 0);
+        const int32_t e = (int32_t)min((int64_t)src_off[cell + 1], n);
+        const int32_t cy = cell / nx, cx = cell - cy * nx;
+        for (int32_t j = b + lg; j < e; j += G) {
+            const int32_t k = key[j];
+            if (k == ncell) continue;
+            if (k < 0 || k > ncell) {
+                atomicAdd(errcount, 1ull);
+                continue;
+            }
+            const int d = near_dir(k, cx, cy, nx);
+            if (d < 0) {
+                far_append(k, j, cap, farn, flist, fcnt);
+                continue;
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) c9[i] += d == i ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) c9[i] = group_sum_i<G>(c9[i]);
+    if (cell < ncell && lg == 0) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ncnt[(int64_t)cell * 9 + i] = c9[i];
+    }
+}
+
+// particles arriving in cell k from its neighbours (and from far away)
+__device__ __forceinline__ int32_t dest_count(int32_t k, int32_t nx, int32_t ny,
+                                              const int32_t* __restrict__ ncnt,
+                                              const int32_t* __restrict__ fcnt) {
+    const int32_t ky = k / nx, kx = k - ky * nx;
+    int32_t sum = fcnt[k];
+#pragma unroll
+    for (int ey = -1; ey <= 1; ++ey)
+#pragma unroll
+        for (int ex = -1; ex <= 1; ++ex) {
+            const int32_t sx = kx - ex, sy = ky - ey;
+            if (sx >= 0 && sx < nx && sy >= 0 && sy < ny)
+                sum += ncnt[(int64_t)(sy * nx + sx) * 9 + (ey + 1) * 3 + (ex + 1)];
+        }
+    return sum;
+}
+
+__global__ __launch_bounds__(BIN_BLOCK) void rebin_dest_kernel(int32_t ncell, int32_t nx,
+                                                                int32_t ny,
+                                                                const int32_t* __restrict__ ncnt,
+                                                                const int32_t* __restrict__ fcnt,
+                                                                int32_t* __restrict__ cnt) {
+    const int32_t k = blockIdx.x * BIN_BLOCK + threadIdx.x;
+    if (k < ncell) cnt[k] = dest_count(k, nx, ny, ncnt, fcnt);
+}
+
+// one workgroup: destination counts and both exclusive scans for grids of up to
+// SMALL_SCAN_CELLS cells (one launch instead of four)
+constexpr int SMALL_SCAN_BLOCK = 1024, SMALL_SCAN_ITEMS = 16;
+constexpr int SMALL_SCAN_CELLS = SMALL_SCAN_BLOCK * SMALL_SCAN_ITEMS;
+
+__device__ __forceinline__ int32_t wg_excl_scan(int32_t v, int32_t* sh, int32_t& total) {
+    // wave-level inclusive scan by shuffles, then the wave totals
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int i = 0; i < SMALL_SCAN_BLOCK / 64; ++i) {
+            const int32_t t = sh[i];
+            sh[i] = run;
+            run += t;
+        }
+        sh[SMALL_SCAN_BLOCK / 64] = run;
+    }
+    __syncthreads();
+    total = sh[SMALL_SCAN_BLOCK / 64];
+    const int32_t r = sh[wv] + x - v;
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(SMALL_SCAN_BLOCK) void rebin_small_scan_kernel(
+    int32_t ncell, int32_t nx, int32_t ny, const int32_t* __restrict__ ncnt,
+    const int32_t* __restrict__ fcnt, int32_t* __restrict__ offsets, int32_t* __restrict__ foff) {
+    __shared__ int32_t sh[SMALL_SCAN_BLOCK / 64 + 1];
+    const int32_t base = threadIdx.x * SMALL_SCAN_ITEMS;
+    int32_t va[SMALL_SCAN_ITEMS], vb[SMALL_SCAN_ITEMS];
+    int32_t sa = 0, sb = 0;
+#pragma unroll
+    for (int i = 0; i < SMALL_SCAN_ITEMS; ++i) {
+        const int32_t k = base + i;
+        va[i] = k < ncell ? dest_count(k, nx, ny, ncnt, fcnt) : 0;
+        vb[i] = k < ncell ? fcnt[k] : 0;
+        sa += va[i];
+        sb += vb[i];
+    }
+    int32_t ta, tb;
+    int32_t ea = wg_excl_scan(sa, sh, ta);
+    int32_t eb = wg_excl_scan(sb, sh, tb);
+#pragma unroll
+    for (int i = 0; i < SMALL_SCAN_ITEMS; ++i) {
+        const int32_t k = base + i;
+        if (k < ncell) {
+            offsets[k] = ea;
+            foff[k] = eb;
+        }
+        ea += va[i];
+        eb += vb[i];
+    }
+    if (threadIdx.x == 0) {
+        offsets[ncell] = ta;
+        foff[ncell] = tb;
+    }
+}
+
+// far list -> per-destination segments (order inside a segment is arbitrary)
+__global__ __launch_bounds__(BIN_BLOCK) void rebin_far_place_kernel(
+    int64_t cap, const int32_t* __restrict__ farn, const uint64_t* __restrict__ flist,
+    const int32_t* __restrict__ foff, int32_t* __restrict__ fcur, int32_t* __restrict__ fkey,
+    int32_t* __restrict__ fsrc) {
+    const int64_t nf = min((int64_t)farn[0], cap);
+    for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i < nf;
+         i += (int64_t)gridDim.x * BIN_BLOCK) {
+        const uint64_t v = flist[i];
+        const int32_t k = (int32_t)(v >> 32), p = (int32_t)(uint32_t)v;
+        const int32_t slot = foff[k] + atomicAdd(&fcur[k], 1);
+        if (slot < cap) {
+            fkey[slot] = k;
+            fsrc[slot] = p;
+        }
+    }
+}
+
+template <typename T>
+struct Rec {
+    const T *sx, *sy, *svx, *svy, *svz;
+    const uint32_t* spid;
+    T *dx, *dy, *dvx, *dvy, *dvz;
+    uint32_t* dpid;
+    int32_t *dkey, *perm;
+    __device__ __forceinline__ void copy(int32_t p, int32_t d, int32_t k) const {
+        dx[d] = sx[p];
+        if (sy) dy[d] = sy[p];
+        dvx[d] = svx[p];
+        dvy[d] = svy[p];
+        dvz[d] = svz[p];
+        dpid[d] = spid[p];
+        dkey[d] = k;
+        if (perm) perm[d] = p;
+    }
+};
+
+// grid: cell blocks (old cells push their near movers), then FAR_BLOCKS blocks for the far
+// arrivals.  Every block also clears a share of fcnt/fcur/farn for the next call.
+template <typename T, int G>
+__global__ __launch_bounds__(BIN_BLOCK) void rebin_push_kernel(
+    int32_t ncell, int32_t nx, int32_t ny, int64_t n, int64_t cap, int32_t cell_blocks,
+    const int32_t* __restrict__ src_off, const int32_t* __restrict__ key,
+    const int32_t* __restrict__ ncnt, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ foff, const int32_t* __restrict__ fkey,
+    const int32_t* __restrict__ fsrc, int32_t* __restrict__ fcnt, int32_t* __restrict__ fcur,
+    int32_t* __restrict__ farn, Rec<T> r) {
+    constexpr int GROUPS = BIN_BLOCK / G;
+    __shared__ int32_t s_base[GROUPS][9];
+    for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i <= ncell;
+         i += (int64_t)gridDim.x * BIN_BLOCK) {
+        fcnt[i] = 0;
+        fcur[i] = 0;
+        if (i == 0) farn[0] = 0;
+    }
+    const int64_t lim = min((int64_t)offsets[ncell], n);   // slots that exist in dst
+    const int32_t fend = (int32_t)min((int64_t)foff[ncell], cap);
+    if ((int32_t)blockIdx.x >= cell_blocks) {
+        const int32_t nf = fend;
+        for (int32_t i = (int32_t)(blockIdx.x - cell_blocks) * BIN_BLOCK + threadIdx.x; i < nf;
+             i += FAR_BLOCKS * BIN_BLOCK) {
+            const int32_t k = fkey[i], p = fsrc[i];
+            if (k < 0 || k >= ncell || p < 0 || p >= n) continue;   // only with bad src_off
+            const int32_t ky = k / nx, kx = k - ky * nx;
+            int32_t slot = offsets[k];
+            for (int ey = -1; ey <= 1; ++ey)
+                for (int ex = -1; ex <= 1; ++ex) {
+                    const int32_t sx = kx - ex, sy = ky - ey;
+                    if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) continue;
+                    const int32_t c2 = sy * nx + sx;
+                    if (src_off[c2] < p) slot += ncnt[(int64_t)c2 * 9 + (ey + 1) * 3 + (ex + 1)];
+                }
+            const int32_t f1 = min(foff[k + 1], fend);
+            for (int32_t q = foff[k]; q < f1; ++q) slot += fsrc[q] < p ? 1 : 0;
+            if (slot >= 0 && slot < lim) r.copy(p, slot, k);
+        }
+        return;
+    }
+    const int grp = threadIdx.x / G, lg = threadIdx.x % G;
+    const int32_t cell = (int32_t)blockIdx.x * GROUPS + grp;
+    const bool in = cell < ncell;
+    int32_t b = 0, e = 0, cx = 0, cy = 0;
+    if (in) {
+        b = max(src_off[cell], 0);
+        e = (int32_t)min((int64_t)src_off[cell + 1], n);
+        cy = cell / nx;
+        cx = cell - cy * nx;
+    }
+    // slot of the first particle of this cell in each neighbour: the destination start,
+    // plus the runs of neighbour old cells before this one, plus the far arrivals with a
+    // smaller source index
+    for (int d = lg; d < 9; d += G) {
+        int32_t base = 0;
+        const int32_t kx = cx + d % 3 - 1, ky = cy + d / 3 - 1;
+        if (in && kx >= 0 && kx < nx && ky >= 0 && ky < ny) {
+            const int32_t k = ky * nx + kx;
+            base = offsets[k];
+            for (int ey = -1; ey <= 1; ++ey)
+                for (int ex = -1; ex <= 1; ++ex) {
+                    const int32_t sx = kx - ex, sy = ky - ey;
+                    if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) continue;
+                    const int32_t c2 = sy * nx + sx;
+                    if (c2 < cell) base += ncnt[(int64_t)c2 * 9 + (ey + 1) * 3 + (ex + 1)];
+                }
+            const int32_t f1 = min(foff[k + 1], fend);
+            for (int32_t q = foff[k]; q < f1; ++q) base += fsrc[q] < b ? 1 : 0;
+        }
+        s_base[grp][d] = base;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int gl = lane - lg;
+    const uint64_t gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << gl);
+    const uint64_t below = (1ull << lane) - 1ull;
+    int32_t run[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t sb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sb[i] = s_base[grp][i];
+    for (int32_t j0 = b; j0 < e; j0 += G) {
+        const int32_t j = j0 + lg;
+        int d = -1, k = 0;
+        if (j < e) {
+            k = key[j];
+            if (k >= 0 && k < ncell) d = near_dir(k, cx, cy, nx);
+        }
+        int32_t slot = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const uint64_t m = __ballot(d == i) & gmask;
+            if (d == i) slot = sb[i] + run[i] + __popcll(m & below);
+            run[i] += __popcll(m);
+        }
+        if (d >= 0 && slot >= 0 && slot < lim) r.copy(j, slot, k);
+    }
+}
+
+template <typename T, int G>
+static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
+                         fp_particles* dst, int32_t* offsets, int32_t* perm, hipStream_t s) {
+    const int32_t nc = c->ncell, nx = c->cfg.nx, ny = c->cfg.ny;
+    const int64_t n = src->n, cap = c->cfg.capacity;
+    const bool two_d = c->cfg.geometry != FP_COUETTE1D;
+    const int32_t cblocks_count = (int32_t)(((int64_t)nc * G + BIN_BLOCK - 1) / BIN_BLOCK);
+    hipLaunchKernelGGL((rebin_count_kernel<G>), dim3(cblocks_count + FAR_BLOCKS), dim3(BIN_BLOCK), 0,
+                       s, nc, nx, n, cap, cblocks_count, src_off, (const int32_t*)src->key, c->ncnt,
+                       c->ccnt, c->farn, c->cmask, c->errcount);
+    if (nc <= SMALL_SCAN_CELLS) {
+        hipLaunchKernelGGL(rebin_small_scan_kernel, dim3(1), dim3(SMALL_SCAN_BLOCK), 0, s, nc, nx, ny,
+                           (const int32_t*)c->ncnt, (const int32_t*)c->ccnt, offsets, c->coff);
+    } else {
+        hipLaunchKernelGGL(rebin_dest_kernel, dim3((nc + BIN_BLOCK - 1) / BIN_BLOCK), dim3(BIN_BLOCK), 0,
+                           s, nc, nx, ny, (const int32_t*)c->ncnt, (const int32_t*)c->ccnt, c->cnt);
+        const int32_t nblocks = (nc + SCAN_TILE - 1) / SCAN_TILE;
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt,
+                           nc, c->blocksum);
+        hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(SCAN_BLOCK), 0, s, c->blocksum, nblocks);
+        hipLaunchKernelGGL(scan_final_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt, nc,
+                           c->blocksum, nblocks, offsets, c->coff);
+    }
+    hipLaunchKernelGGL(rebin_far_place_kernel, dim3(FAR_BLOCKS), dim3(BIN_BLOCK), 0, s, cap,
+                       (const int32_t*)c->farn, (const uint64_t*)c->cmask, (const int32_t*)c->coff,
+                       c->ccur, c->cwave, c->gidx);
+    Rec<T> r{(const T*)src->x,  two_d ? (const T*)src->y : nullptr, (const T*)src->vx,
+             (const T*)src->vy, (const T*)src->vz,                   src->pid,
+             (T*)dst->x,        two_d ? (T*)dst->y : nullptr,        (T*)dst->vx,
+             (T*)dst->vy,       (T*)dst->vz,                         dst->pid,
+             dst->key,          perm};
+    const int32_t cblocks_push = (nc + BIN_BLOCK / G - 1) / (BIN_BLOCK / G);
+    hipLaunchKernelGGL((rebin_push_kernel<T, G>), dim3(cblocks_push + FAR_BLOCKS), dim3(BIN_BLOCK), 0,
+                       s, nc, nx, ny, n, cap, cblocks_push, src_off, (const int32_t*)src->key,
+                       (const int32_t*)c->ncnt, (const int32_t*)offsets, (const int32_t*)c->coff,
+                       (const int32_t*)c->cwave, (const int32_t*)c->gidx, c->ccnt, c->ccur, c->farn, r);
+}
+
+template <typename T>
+static void rebin_dispatch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
+                           fp_particles* dst, int32_t* offsets, int32_t* perm, hipStream_t s) {
+    switch (lanes_per_cell(c, src->n)) {
+        case 4: rebin_launch<T, 4>(c, src, src_off, dst, offsets, perm, s); break;
+        case 8: rebin_launch<T, 8>(c, src, src_off, dst, offsets, perm, s); break;
+        case 16: rebin_launch<T, 16>(c, src, src_off, dst, offsets, perm, s); break;
+        case 32: rebin_launch<T, 32>(c, src, src_off, dst, offsets, perm, s); break;
+        default: rebin_launch<T, 64>(c, src, src_off, dst, offsets, perm, s); break;
+    }
+}
+
+int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_particles* dst,
+                 int32_t* offsets, int32_t* perm, hipStream_t s) {
+    if (c->cfg.precision == FP_F32)
+        rebin_dispatch<float>(c, src, src_off, dst, offsets, perm, s);
+    else
+        rebin_dispatch<double>(c, src, src_off, dst, offsets, perm, s);
+    return check_launch(c, "fp_rebin");
+}
+
 int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* offsets,
                int32_t* perm, hipStream_t s) {
+    // cnt, ccnt and ccur are zero on entry (fp_init, and every fp_bin/fp_rebin leaves them so)
     const int32_t nc = c->ncell;
     const int64_t n = src->n;
-    {
-        const int len = nc + 1;
-        hipLaunchKernelGGL(bin_zero_kernel, dim3((len + 255) / 256), dim3(256), 0, s, c->cnt,
-                           c->ccnt, c->ccur, len);
-    }
     const int64_t pgrid = (n + BIN_BLOCK - 1) / BIN_BLOCK;
     if (n > 0)
         hipLaunchKernelGGL(bin_wave_kernel<false>, dim3((unsigned)pgrid), dim3(BIN_BLOCK), 0, s,

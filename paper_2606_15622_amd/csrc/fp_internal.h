@@ -31,6 +31,8 @@ struct fp_ctx {
     uint64_t* cmask = nullptr;   // [capacity] contribution: lane mask
     int32_t* gidx = nullptr;     // [capacity] slot list for cells too large for LDS
     int32_t* blocksum = nullptr; // scan partials
+    int32_t* ncnt = nullptr;     // [ncell*9] re-sort: particles of each cell per neighbour direction
+    int32_t* farn = nullptr;     // [1] re-sort: length of the list of particles that moved far
     unsigned long long* errcount = nullptr;  // invalid keys
     // open cylinder domain
     double* vol = nullptr;       // [ncell] gas volume of every cell
@@ -128,10 +130,27 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int G>
+__device__ __forceinline__ int group_sum_i(int v) {
+    if constexpr (G >= 2) v += dpp_i<0xB1>(v);
+    if constexpr (G >= 4) v += dpp_i<0x4E>(v);
+    if constexpr (G >= 8) v += dpp_i<0x141>(v);
+    if constexpr (G >= 16) v += dpp_i<0x140>(v);
+    if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
 // ---- host-side launch shape of the per-cell kernels -------------------------------------
 // lanes per cell from the mean occupancy: about 16 particles per lane, 4..64 lanes
-inline int lanes_per_cell(int64_t n, int32_t ncell) {
-    const double avg = ncell > 0 ? (double)n / (double)ncell : 0.0;
+inline int lanes_per_cell(const fp_ctx* c, int64_t n) {
+    if (c->cfg.lanes > 0) return c->cfg.lanes;
+    const double avg = c->ncell > 0 ? (double)n / (double)c->ncell : 0.0;
     int g = 4;
     while (g < 64 && (double)g * 16.0 < avg * 1.25) g *= 2;
     return g;
@@ -140,6 +159,8 @@ inline int lanes_per_cell(int64_t n, int32_t ncell) {
 // ---- launchers implemented in the kernel files -------------------------------------------
 int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* offsets,
                int32_t* perm, hipStream_t s);
+int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_particles* dst,
+                 int32_t* offsets, int32_t* perm, hipStream_t s);
 int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,
                    hipStream_t s);
 int launch_closure(fp_ctx* c, const double* mom, double* rec, int32_t* status, hipStream_t s);

@@ -125,7 +125,7 @@ static void mom_launch(fp_ctx* c, const fp_particles* p, const int32_t* off, dou
 template <typename T>
 static void mom_dispatch(fp_ctx* c, const fp_particles* p, const int32_t* off, double* mom,
                          hipStream_t s) {
-    switch (lanes_per_cell(p->n, c->ncell)) {
+    switch (lanes_per_cell(c, p->n)) {
         case 4: mom_launch<T, 4>(c, p, off, mom, s); break;
         case 8: mom_launch<T, 8>(c, p, off, mom, s); break;
         case 16: mom_launch<T, 16>(c, p, off, mom, s); break;

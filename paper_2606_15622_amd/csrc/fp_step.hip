@@ -454,7 +454,7 @@ template <typename T, int GEOM>
 static void collide_dispatch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
                              const double* rec, uint32_t step, int move, const uint32_t* sp,
                              hipStream_t s) {
-    switch (lanes_per_cell(p->n, c->ncell)) {
+    switch (lanes_per_cell(c, p->n)) {
         case 4: collide_launch<T, 4, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
         case 8: collide_launch<T, 8, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
         case 16: collide_launch<T, 16, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;

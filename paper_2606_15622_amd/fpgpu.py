@@ -30,7 +30,7 @@ class FPConfig(C.Structure):
     _fields_ = [
         ("geometry", C.c_int32), ("precision", C.c_int32), ("conserve", C.c_int32),
         ("nx", C.c_int32), ("ny", C.c_int32), ("n_min", C.c_int32), ("max_bounces", C.c_int32),
-        ("reserved0", C.c_int32), ("capacity", C.c_int64),
+        ("lanes", C.c_int32), ("capacity", C.c_int64),
         ("x0", C.c_double), ("y0", C.c_double), ("lx", C.c_double), ("ly", C.c_double),
         ("dx", C.c_double), ("dy", C.c_double), ("dt", C.c_double),
         ("kB", C.c_double), ("mass", C.c_double),
@@ -68,6 +68,7 @@ def load():
         L.fp_error_count.argtypes = [vp, vp]
         L.fp_error_count.restype = i64
         L.fp_bin.argtypes = [vp, P(FPParticles), P(FPParticles), vp, vp, vp]
+        L.fp_rebin.argtypes = [vp, P(FPParticles), vp, P(FPParticles), vp, vp, vp]
         L.fp_moments.argtypes = [vp, P(FPParticles), vp, vp, vp]
         L.fp_closure_solve.argtypes = [vp, vp, vp, vp, vp]
         L.fp_step.argtypes = [vp, P(FPParticles), vp, vp, vp, u64, u32, vp]
@@ -92,7 +93,7 @@ def load():
         L.fp_nn_targets.argtypes = [vp, vp, i64, vp, vp]
         L.fp_closure_solve_backward.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fp_moments_backward.argtypes = [vp, P(FPParticles), vp, vp, vp, vp, vp, vp, vp]
-        for f in ("fp_bin", "fp_moments", "fp_closure_solve", "fp_step", "fp_sample", "fp_nn_create",
+        for f in ("fp_bin", "fp_rebin", "fp_moments", "fp_closure_solve", "fp_step", "fp_sample", "fp_nn_create",
                   "fp_nn_load", "fp_closure_nn", "fp_nn_outputs", "fp_nn_features",
                   "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
                   "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
@@ -118,6 +119,7 @@ def make_config(w: dict, capacity: int) -> FPConfig:
     c.nx, c.ny = int(w["nx"]), int(w["ny"])
     c.n_min = int(w.get("n_min", 4))
     c.max_bounces = int(w.get("max_bounces", 8))
+    c.lanes = int(w.get("lanes", 0))
     c.capacity = int(capacity)
     c.x0, c.y0, c.lx, c.ly = float(w["x0"]), float(w["y0"]), float(w["lx"]), float(w["ly"])
     c.dx, c.dy, c.dt = float(w["dx"]), float(w["dy"]), float(w["dt"])
@@ -235,6 +237,11 @@ class Context:
         a, b = src.struct(), dst.struct()
         self._check(self.lib.fp_bin(self.h, C.byref(a), C.byref(b), _ptr(offsets), _ptr(perm),
                                     _stream(stream)), "fp_bin")
+
+    def rebin(self, src, src_offsets, dst, offsets, perm=None, stream=None):
+        a, b = src.struct(), dst.struct()
+        self._check(self.lib.fp_rebin(self.h, C.byref(a), _ptr(src_offsets), C.byref(b),
+                                      _ptr(offsets), _ptr(perm), _stream(stream)), "fp_rebin")
 
     def moments(self, p, offsets, mom, stream=None):
         a = p.struct()
@@ -363,7 +370,9 @@ class Simulation:
         self.a = Particles.from_numpy(w, state, device=device)
         self.b = Particles(n, self.a.dtype, self.a.two_d, device)
         nc = self.ctx.ncell
-        self.offsets = torch.zeros(nc + 1, dtype=torch.int32, device=device)
+        # two offsets arrays: the re-sort reads the previous grouping and writes the next
+        self.offs = [torch.zeros(nc + 1, dtype=torch.int32, device=device) for _ in range(2)]
+        self.sorted = False        # a holds particles grouped by offs[0] with new keys
         self.mom = torch.zeros((nc, MOM_STRIDE), dtype=torch.float64, device=device)
         self.rec = torch.zeros((nc, REC_STRIDE), dtype=torch.float64, device=device)
         self.status = torch.zeros(nc, dtype=torch.int32, device=device)
@@ -371,9 +380,24 @@ class Simulation:
         if "key" not in state:
             self.ctx.step(self.a, None, None, None, 0, STEP_KEYS)
 
-    def step(self, s, sample=False):
-        self.ctx.bin(self.a, self.b, self.offsets)
+    @property
+    def offsets(self):
+        """Cell start indices of the particles in a (after the last sort)."""
+        return self.offs[0]
+
+    def sort(self, perm=None):
+        """a -> b sorted by key (fp_rebin from the previous grouping after the first
+        step, fp_bin before), then swap a and b; offsets describe the new a."""
+        if self.sorted:
+            self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1], perm)
+        else:
+            self.ctx.bin(self.a, self.b, self.offs[1], perm)
+        self.offs.reverse()
         self.a, self.b = self.b, self.a
+        self.sorted = True
+
+    def step(self, s, sample=False):
+        self.sort()
         self.ctx.moments(self.a, self.offsets, self.mom)
         if sample:
             self.ctx.sample(self.mom, self.samp)
@@ -399,8 +423,7 @@ class GraphSimulation(Simulation):
 
     def _body(self, sample):
         for _ in range(2):
-            self.ctx.bin(self.a, self.b, self.offsets)
-            self.a, self.b = self.b, self.a
+            self.sort()
             self.ctx.moments(self.a, self.offsets, self.mom)
             if sample:
                 self.ctx.sample(self.mom, self.samp)
@@ -415,11 +438,13 @@ class GraphSimulation(Simulation):
             torch.cuda.synchronize()
             saved = self.step_ctr.clone()
             samp = self.samp.clone()
+            was_sorted = self.sorted
             with torch.cuda.graph(g):
                 self._body(sample)
             torch.cuda.synchronize()
             self.step_ctr.copy_(saved)   # capture does not execute; keep the counter anyway
             self.samp.copy_(samp)
+            self.sorted = was_sorted
             self.graphs[sample] = g
         return self.graphs[sample]
 
@@ -433,7 +458,7 @@ class GraphSimulation(Simulation):
 class OpenSimulation:
     """Loop of the open cylinder domain: bin -> moments -> [sample] -> closure ->
     collide + move (deleting particles that leave the box) -> inflow injection.  The
-    number of particles kept by fp_bin is read back once per step (one host sync)."""
+    number of particles kept by the sort is read back once per step (one host sync)."""
 
     def __init__(self, w, state, capacity=None, device="cuda"):
         self.w = w
@@ -444,7 +469,8 @@ class OpenSimulation:
         self.a = Particles.from_numpy(w, state, capacity=cap, device=device)
         self.b = Particles(0, self.a.dtype, True, device, capacity=cap)
         nc = self.ctx.ncell
-        self.offsets = torch.zeros(nc + 1, dtype=torch.int32, device=device)
+        self.offs = [torch.zeros(nc + 1, dtype=torch.int32, device=device) for _ in range(2)]
+        self.sorted = False
         self.mom = torch.zeros((nc, MOM_STRIDE), dtype=torch.float64, device=device)
         self.rec = torch.zeros((nc, REC_STRIDE), dtype=torch.float64, device=device)
         self.status = torch.zeros(nc, dtype=torch.int32, device=device)
@@ -455,10 +481,21 @@ class OpenSimulation:
         if "key" not in state:
             self.ctx.step(self.a, None, None, None, 0, STEP_KEYS)
 
+    @property
+    def offsets(self):
+        return self.offs[0]
+
     def step(self, s, sample=False, closure=None):
         self.a.n = self.n_total
         self.b.n = self.n_total
-        self.ctx.bin(self.a, self.b, self.offsets)
+        # after the first step the live particles are grouped by their previous cells and
+        # the injected ones follow them: the re-sort applies
+        if self.sorted:
+            self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1])
+        else:
+            self.ctx.bin(self.a, self.b, self.offs[1])
+        self.offs.reverse()
+        self.sorted = True
         self.a, self.b = self.b, self.a
         live = int(self.offsets[-1])
         self.a.n = live

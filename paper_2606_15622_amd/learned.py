@@ -144,8 +144,7 @@ class LearnedSimulation(F.Simulation):
         self.tol = (tol_abs, tol_rel)
 
     def step(self, s, sample=False):
-        self.ctx.bin(self.a, self.b, self.offsets)
-        self.a, self.b = self.b, self.a
+        self.sort()
         self.ctx.moments(self.a, self.offsets, self.mom)
         if sample:
             self.ctx.sample(self.mom, self.samp)
