@@ -234,10 +234,12 @@ int fp_nn_create(fp_ctx* ctx, int64_t max_batch, fp_nn** out);
 void fp_nn_destroy(fp_nn* net);
 /* Convert params (FP_NN_PARAMS floats, device) into the network's BF16 image. */
 int fp_nn_load(fp_ctx* ctx, fp_nn* net, const float* params, hipStream_t s);
-/* Learned closure of every cell: network outputs de-standardised, then checked against
- * the cell's own normalised 9x9 system; accepted if |A y - b| <= tol_abs + tol_rel |b|
- * (status FP_CELL_NN), otherwise solved exactly (FP_CELL_NN_FALLBACK).  Cells that are
- * EMPTY/NONFINITE/FEW are treated as in fp_closure_solve.  Same rec layout. */
+/* Learned closure of every cell (Algorithm "Accelerated ML Simulation Loop"): network
+ * outputs de-standardised, then checked against the cell's own normalised 9x9 system;
+ * accepted if |A y - b| <= tol_abs + tol_rel |b| (status FP_CELL_NN), otherwise solved
+ * exactly (FP_CELL_NN_FALLBACK).  tol_abs = +infinity skips the check (and the assembly
+ * of the system): every finite output is accepted, non-finite ones fall back.  Cells that
+ * are EMPTY/NONFINITE/FEW are treated as in fp_closure_solve.  Same rec layout. */
 int fp_closure_nn(fp_ctx* ctx, const fp_nn* net, const double* mom, double* rec,
                   int32_t* status, double tol_abs, double tol_rel, hipStream_t s);
 /* Copy the standardised network outputs of the last fp_closure_nn ([ncell][16]). */

@@ -283,14 +283,44 @@ __device__ __forceinline__ int near_dir(int32_t k, int32_t cx, int32_t cy, int32
     return (dy + 1) * 3 + (dx + 1);
 }
 
-__device__ __forceinline__ void far_append(int32_t k, int32_t j, int64_t cap, int32_t* farn,
-                                           uint64_t* flist, int32_t* fcnt) {
-    const int32_t slot = atomicAdd(farn, 1);
+// exclusive prefix sum over a workgroup of BLOCK threads (wave shuffles, then the wave
+// totals in LDS); sh holds BLOCK/64 + 1 ints; total receives the sum over the block
+template <int BLOCK>
+__device__ __forceinline__ int32_t wg_excl_scan(int32_t v, int32_t* sh, int32_t& total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int i = 0; i < BLOCK / 64; ++i) {
+            const int32_t t = sh[i];
+            sh[i] = run;
+            run += t;
+        }
+        sh[BLOCK / 64] = run;
+    }
+    __syncthreads();
+    total = sh[BLOCK / 64];
+    const int32_t r = sh[wv] + x - v;
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ void far_put(int32_t k, int32_t j, int64_t slot, int64_t cap,
+                                        uint64_t* flist, int32_t* fcnt) {
     if (slot < cap) flist[slot] = ((uint64_t)(uint32_t)k << 32) | (uint32_t)j;
     atomicAdd(&fcnt[k], 1);
 }
 
-// grid: ncell*G lanes for the old cells, then FAR_BLOCKS blocks for the ungrouped tail
+// grid: ncell*G lanes for the old cells, then FAR_BLOCKS blocks for the ungrouped tail.
+// Far movers are appended to the list with one atomic per block (cells) or per wave
+// (tail) on its length: a single counter hit once per particle would serialise.
 constexpr int FAR_BLOCKS = 64;
 
 template <int G>
@@ -299,20 +329,31 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     const int32_t* __restrict__ src_off, const int32_t* __restrict__ key,
     int32_t* __restrict__ ncnt, int32_t* __restrict__ fcnt, int32_t* __restrict__ farn,
     uint64_t* __restrict__ flist, unsigned long long* __restrict__ errcount) {
+    __shared__ int32_t sh[BIN_BLOCK / 64 + 1];
+    __shared__ int32_t s_base;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
     if ((int32_t)blockIdx.x >= cell_blocks) {
         // particles after the grouped range: all take the general path
-        const int64_t t0 = src_off[ncell];
+        const int64_t t0 = max((int64_t)src_off[ncell], (int64_t)0);
         const int64_t stride = (int64_t)FAR_BLOCKS * BIN_BLOCK;
-        for (int64_t j = (t0 > 0 ? t0 : 0) + (int64_t)(blockIdx.x - cell_blocks) * BIN_BLOCK +
-                         threadIdx.x;
-             j < n; j += stride) {
-            const int32_t k = key[j];
-            if (k == ncell) continue;
-            if (k < 0 || k > ncell) {
-                atomicAdd(errcount, 1ull);
-                continue;
+        for (int64_t jb = t0 + (int64_t)(blockIdx.x - cell_blocks) * BIN_BLOCK; jb < n;
+             jb += stride) {
+            const int64_t j = jb + threadIdx.x;
+            int32_t k = ncell;
+            if (j < n) {
+                k = key[j];
+                if (k < 0 || k > ncell) {
+                    atomicAdd(errcount, 1ull);
+                    k = ncell;
+                }
             }
-            far_append(k, (int32_t)j, cap, farn, flist, fcnt);
+            const bool far = k < ncell;
+            const uint64_t m = __ballot(far);
+            int32_t wbase = 0;
+            if (lane == 0 && m) wbase = atomicAdd(farn, (int32_t)__popcll(m));
+            wbase = __shfl(wbase, 0, 64);
+            if (far) far_put(k, (int32_t)j, (int64_t)wbase + __popcll(m & below), cap, flist, fcnt);
         }
         return;
     }
@@ -320,24 +361,30 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     const int32_t cell = (int32_t)(gt / G);
     const int lg = (int)(gt % G);
     int c9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t nfar = 0, b = 0, e = 0, cx = 0, cy = 0;
     if (cell < ncell) {
-        const int32_t b = max(src_off[cell], 0);
-        const int32_t e = (int32_t)min((int64_t)src_off[cell + 1], n);
-        const int32_t cy = cell / nx, cx = cell - cy * nx;
-        for (int32_t j = b + lg; j < e; j += G) {
-            const int32_t k = key[j];
-            if (k == ncell) continue;
-            if (k < 0 || k > ncell) {
-                atomicAdd(errcount, 1ull);
-                continue;
-            }
-            const int d = near_dir(k, cx, cy, nx);
-            if (d < 0) {
-                far_append(k, j, cap, farn, flist, fcnt);
-                continue;
-            }
+        b = max(src_off[cell], 0);
+        e = (int32_t)min((int64_t)src_off[cell + 1], n);
+        cy = cell / nx;
+        cx = cell - cy * nx;
+        constexpr int KR = 4;
+        for (int32_t j0 = b + lg; j0 < e; j0 += G * KR) {
+            int32_t kk[KR];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) c9[i] += d == i ? 1 : 0;
+            for (int u = 0; u < KR; ++u) kk[u] = j0 + u * G < e ? key[j0 + u * G] : ncell;
+#pragma unroll
+            for (int u = 0; u < KR; ++u) {
+                const int32_t k = kk[u];
+                if (k == ncell) continue;
+                if (k < 0 || k > ncell) {
+                    atomicAdd(errcount, 1ull);
+                    continue;
+                }
+                const int d = near_dir(k, cx, cy, nx);
+                nfar += d < 0 ? 1 : 0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) c9[i] += d == i ? 1 : 0;
+            }
         }
     }
 #pragma unroll
@@ -345,6 +392,18 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     if (cell < ncell && lg == 0) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) ncnt[(int64_t)cell * 9 + i] = c9[i];
+    }
+    int32_t tot;
+    const int32_t pre = wg_excl_scan<BIN_BLOCK>(nfar, sh, tot);
+    if (tot == 0) return;                      // block-uniform
+    if (threadIdx.x == 0) s_base = atomicAdd(farn, tot);
+    __syncthreads();
+    if (nfar == 0) return;
+    int64_t slot = (int64_t)s_base + pre;
+    for (int32_t j = b + lg; j < e; j += G) {
+        const int32_t k = key[j];
+        if (k < 0 || k >= ncell || near_dir(k, cx, cy, nx) >= 0) continue;
+        far_put(k, j, slot++, cap, flist, fcnt);
     }
 }
 
@@ -379,33 +438,6 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_dest_kernel(int32_t ncell, in
 constexpr int SMALL_SCAN_BLOCK = 1024, SMALL_SCAN_ITEMS = 16;
 constexpr int SMALL_SCAN_CELLS = SMALL_SCAN_BLOCK * SMALL_SCAN_ITEMS;
 
-__device__ __forceinline__ int32_t wg_excl_scan(int32_t v, int32_t* sh, int32_t& total) {
-    // wave-level inclusive scan by shuffles, then the wave totals
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int32_t x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) sh[wv] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int i = 0; i < SMALL_SCAN_BLOCK / 64; ++i) {
-            const int32_t t = sh[i];
-            sh[i] = run;
-            run += t;
-        }
-        sh[SMALL_SCAN_BLOCK / 64] = run;
-    }
-    __syncthreads();
-    total = sh[SMALL_SCAN_BLOCK / 64];
-    const int32_t r = sh[wv] + x - v;
-    __syncthreads();
-    return r;
-}
-
 __global__ __launch_bounds__(SMALL_SCAN_BLOCK) void rebin_small_scan_kernel(
     int32_t ncell, int32_t nx, int32_t ny, const int32_t* __restrict__ ncnt,
     const int32_t* __restrict__ fcnt, int32_t* __restrict__ offsets, int32_t* __restrict__ foff) {
@@ -422,8 +454,8 @@ __global__ __launch_bounds__(SMALL_SCAN_BLOCK) void rebin_small_scan_kernel(
         sb += vb[i];
     }
     int32_t ta, tb;
-    int32_t ea = wg_excl_scan(sa, sh, ta);
-    int32_t eb = wg_excl_scan(sb, sh, tb);
+    int32_t ea = wg_excl_scan<SMALL_SCAN_BLOCK>(sa, sh, ta);
+    int32_t eb = wg_excl_scan<SMALL_SCAN_BLOCK>(sb, sh, tb);
 #pragma unroll
     for (int i = 0; i < SMALL_SCAN_ITEMS; ++i) {
         const int32_t k = base + i;
@@ -465,6 +497,17 @@ struct Rec {
     T *dx, *dy, *dvx, *dvy, *dvz;
     uint32_t* dpid;
     int32_t *dkey, *perm;
+    __device__ __forceinline__ void store(int32_t d, int32_t k, int32_t p, T x, T y, T vx, T vy,
+                                          T vz, uint32_t pid) const {
+        dx[d] = x;
+        if (dy) dy[d] = y;
+        dvx[d] = vx;
+        dvy[d] = vy;
+        dvz[d] = vz;
+        dpid[d] = pid;
+        dkey[d] = k;
+        if (perm) perm[d] = p;
+    }
     __device__ __forceinline__ void copy(int32_t p, int32_t d, int32_t k) const {
         dx[d] = sx[p];
         if (sy) dy[d] = sy[p];
@@ -558,21 +601,45 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_push_kernel(
     int32_t sb[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) sb[i] = s_base[grp][i];
-    for (int32_t j0 = b; j0 < e; j0 += G) {
-        const int32_t j = j0 + lg;
-        int d = -1, k = 0;
-        if (j < e) {
-            k = key[j];
-            if (k >= 0 && k < ncell) d = near_dir(k, cx, cy, nx);
-        }
-        int32_t slot = 0;
+    // KR sub-chunks of G consecutive particles per round: all their loads first, then
+    // the ranks (sub-chunks in source order, lanes in source order) and the stores
+    constexpr int KR = 4;
+    for (int32_t j0 = b; j0 < e; j0 += G * KR) {
+        int32_t kk[KR];
+        T rx[KR], ry[KR], rvx[KR], rvy[KR], rvz[KR];
+        uint32_t rpid[KR];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const uint64_t m = __ballot(d == i) & gmask;
-            if (d == i) slot = sb[i] + run[i] + __popcll(m & below);
-            run[i] += __popcll(m);
+        for (int u = 0; u < KR; ++u) {
+            const int32_t j = j0 + u * G + lg;
+            kk[u] = -1;
+            rx[u] = ry[u] = rvx[u] = rvy[u] = rvz[u] = (T)0;
+            rpid[u] = 0;
+            if (j < e) {
+                kk[u] = key[j];
+                rx[u] = r.sx[j];
+                if (r.sy) ry[u] = r.sy[j];
+                rvx[u] = r.svx[j];
+                rvy[u] = r.svy[j];
+                rvz[u] = r.svz[j];
+                rpid[u] = r.spid[j];
+            }
         }
-        if (d >= 0 && slot >= 0 && slot < lim) r.copy(j, slot, k);
+#pragma unroll
+        for (int u = 0; u < KR; ++u) {
+            const int32_t j = j0 + u * G + lg;
+            const int32_t k = kk[u];
+            int d = -1;
+            if (k >= 0 && k < ncell) d = near_dir(k, cx, cy, nx);
+            int32_t slot = 0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const uint64_t m = __ballot(d == i) & gmask;
+                if (d == i) slot = sb[i] + run[i] + __popcll(m & below);
+                run[i] += __popcll(m);
+            }
+            if (d >= 0 && slot >= 0 && slot < lim)
+                r.store(slot, k, j, rx[u], ry[u], rvx[u], rvy[u], rvz[u], rpid[u]);
+        }
     }
 }
 

@@ -52,9 +52,8 @@ __global__ __launch_bounds__(CL_BLOCK) void closure_kernel(fp_config g, int32_t 
         if (N < (double)g.n_min) {
             st = FP_CELL_FEW;
         } else {
-            CellSystem s;
-            build_system(m, g.eps_hat, s);
             bool accepted = false;
+            const bool unchecked = NN && tol_abs == INFINITY;   // accept any finite output
             if (NN) {
                 const float* yo = ynn + (int64_t)cell * 16;
 #pragma unroll
@@ -62,29 +61,39 @@ __global__ __launch_bounds__(CL_BLOCK) void closure_kernel(fp_config g, int32_t 
                 y[0] += 5.0 * g.eps_hat;
                 y[3] += 5.0 * g.eps_hat;
                 y[5] += 5.0 * g.eps_hat;
-                double rr = 0.0, bb = 0.0;
+                if (unchecked) {
+                    accepted = true;
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    double t = -s.a[i][9];
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) t = fma(s.a[i][k], y[k], t);
-                    rr = fma(t, t, rr);
-                    bb = fma(s.a[i][9], s.a[i][9], bb);
+                    for (int i = 0; i < 9; ++i) accepted = accepted && isfinite(y[i]);
                 }
-                accepted = sqrt(rr) <= tol_abs + tol_rel * sqrt(bb);
-#pragma unroll
-                for (int i = 0; i < 9; ++i) accepted = accepted && isfinite(y[i]);
             }
-            if (accepted) {
-                st = FP_CELL_NN;
-            } else {
-                const bool ok = lu_solve(s, g.pivot_tol, y);
-                bool fin = true;
+            if (!accepted) {
+                CellSystem s;
+                build_system(m, g.eps_hat, s);
+                if (NN && !unchecked) {
+                    double rr = 0.0, bb = 0.0;
 #pragma unroll
-                for (int i = 0; i < 9; ++i) fin = fin && isfinite(y[i]);
-                if (!ok || !fin) st = FP_CELL_SINGULAR;
-                else if (NN) st = FP_CELL_NN_FALLBACK;
+                    for (int i = 0; i < 9; ++i) {
+                        double t = -s.a[i][9];
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) t = fma(s.a[i][k], y[k], t);
+                        rr = fma(t, t, rr);
+                        bb = fma(s.a[i][9], s.a[i][9], bb);
+                    }
+                    accepted = sqrt(rr) <= tol_abs + tol_rel * sqrt(bb);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) accepted = accepted && isfinite(y[i]);
+                }
+                if (!accepted) {
+                    const bool ok = lu_solve(s, g.pivot_tol, y);
+                    bool fin = true;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) fin = fin && isfinite(y[i]);
+                    if (!ok || !fin) st = FP_CELL_SINGULAR;
+                    else if (NN) st = FP_CELL_NN_FALLBACK;
+                }
             }
+            if (accepted) st = FP_CELL_NN;
         }
         if (st == FP_CELL_OK || st == FP_CELL_NN || st == FP_CELL_NN_FALLBACK) {
             const double it = 1.0 / tau;

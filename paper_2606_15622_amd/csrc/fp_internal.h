@@ -33,6 +33,7 @@ struct fp_ctx {
     int32_t* blocksum = nullptr; // scan partials
     int32_t* ncnt = nullptr;     // [ncell*9] re-sort: particles of each cell per neighbour direction
     int32_t* farn = nullptr;     // [1] re-sort: length of the list of particles that moved far
+    int32_t* pend = nullptr;     // [ncell] step: flights left for flight_rest_kernel per cell
     unsigned long long* errcount = nullptr;  // invalid keys
     // open cylinder domain
     double* vol = nullptr;       // [ncell] gas volume of every cell
@@ -147,12 +148,12 @@ __device__ __forceinline__ int group_sum_i(int v) {
 }
 
 // ---- host-side launch shape of the per-cell kernels -------------------------------------
-// lanes per cell from the mean occupancy: about 16 particles per lane, 4..64 lanes
+// lanes per cell from the mean occupancy: about 8 particles per lane, 4..64 lanes
 inline int lanes_per_cell(const fp_ctx* c, int64_t n) {
     if (c->cfg.lanes > 0) return c->cfg.lanes;
     const double avg = c->ncell > 0 ? (double)n / (double)c->ncell : 0.0;
     int g = 4;
-    while (g < 64 && (double)g * 16.0 < avg * 1.25) g *= 2;
+    while (g < 64 && (double)g * 8.0 < avg * 1.25) g *= 2;
     return g;
 }
 

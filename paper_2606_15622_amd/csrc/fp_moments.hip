@@ -12,7 +12,7 @@
 namespace fpg {
 
 constexpr int MOM_BLOCK = 256;
-constexpr int MOM_K = 16;
+constexpr int MOM_K = 8;
 
 template <typename T, int G, int K>
 __global__ __launch_bounds__(MOM_BLOCK) void moments_kernel(

@@ -40,6 +40,12 @@ __device__ __forceinline__ int perm_k(int K) {
 }
 
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// inference: z * sigmoid(z) with the hardware exp2 and reciprocal (about 1 ulp; the
+// result is rounded to bfloat16 right after)
+__device__ __forceinline__ float silu_fast(float z) {
+    constexpr float LOG2E = 1.4426950408889634f;
+    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-LOG2E * z));
+}
 __device__ __forceinline__ float dsilu_f(float z) {
     const float s = 1.0f / (1.0f + __expf(-z));
     return s * (1.0f + z * (1.0f - s));
@@ -114,9 +120,19 @@ template <int KS>
 __device__ __forceinline__ void nn_layer(const __bf16* __restrict__ img_l, const float* __restrict__ bias,
                                          const bf16x8 (&bin)[8], bf16x8 (&bout)[8], int lane) {
     const int h = lane >> 5;
+    // accumulators start from the bias: output row u = 32 mt + 8 (j / 4) + 4 h + j % 4,
+    // four consecutive rows per 16-byte LDS read
     f32x16 acc[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) acc[mt] = f32x16{};
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int jq = 0; jq < 4; ++jq) {
+            const float4 bq = *(const float4*)(bias + mt * 32 + 8 * jq + 4 * h);
+            acc[mt][4 * jq + 0] = bq.x;
+            acc[mt][4 * jq + 1] = bq.y;
+            acc[mt][4 * jq + 2] = bq.z;
+            acc[mt][4 * jq + 3] = bq.w;
+        }
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
@@ -128,10 +144,8 @@ __device__ __forceinline__ void nn_layer(const __bf16* __restrict__ img_l, const
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int u = mt * 32 + 8 * (j >> 2) + 4 * h + (j & 3);
-            bout[2 * mt + (j >> 3)][j & 7] = (__bf16)silu_f(acc[mt][j] + bias[u]);
-        }
+        for (int j = 0; j < 16; ++j)
+            bout[2 * mt + (j >> 3)][j & 7] = (__bf16)silu_fast(acc[mt][j]);
 }
 
 __global__ __launch_bounds__(NN_BLOCK) void nn_infer_kernel(int32_t ncell, const double* __restrict__ mom,
@@ -140,7 +154,7 @@ __global__ __launch_bounds__(NN_BLOCK) void nn_infer_kernel(int32_t ncell, const
                                                              const float* __restrict__ gsec,
                                                              float* __restrict__ yout) {
     __shared__ __attribute__((aligned(16))) __bf16 img[IMG_BF];
-    __shared__ float sec[SEC_N];
+    __shared__ __attribute__((aligned(16))) float sec[SEC_N];
     for (int t = threadIdx.x; t < IMG_BF / 8; t += NN_BLOCK)
         ((bf16x8*)img)[t] = ((const bf16x8*)gimg)[t];
     for (int t = threadIdx.x; t < SEC_N; t += NN_BLOCK) sec[t] = gsec[t];

@@ -5,8 +5,8 @@
 //   c* = c E + (1 - E) tau N + sigma xi,  xi ~ N(0, I) from Philox    (eq. update_vel)
 // then the cell is recentred on U and its energy restored, exactly (EXACT) or with the
 // factor alpha of eq. update_alpha (PAPER).  c* of up to K particles per lane stays in
-// registers between the sum pass and the write pass; beyond that it is recomputed from
-// the same Philox counter (identical bits).  Per-particle arithmetic is in the storage
+// registers between the sum pass and the write pass; beyond that it waits in the
+// particle's own velocity slots.  Per-particle arithmetic is in the storage
 // precision; the cell sums and the rescale factor are FP64.
 // Flight (eq. update_pos) and the wall interactions are FP64 without contraction, so a
 // stored position and the wall decisions are the same numbers on any IEEE machine.
@@ -15,7 +15,7 @@
 namespace fpg {
 
 constexpr int ST_BLOCK = 256;
-constexpr int ST_K = 16;
+constexpr int ST_K = 8;
 
 struct Walls {
     double lo[2], hi[2];
@@ -29,25 +29,33 @@ __device__ __forceinline__ double st_round(double v, bool f32) {
 
 // diffuse re-emission from wall w (0: x lo, 1: x hi, 2: y lo, 3: y hi): inward normal
 // speed with density ~ v exp(-v^2/(2 R T_w)), Gaussian tangential velocity about u_w
+// value of wall w among four, by selects (a dynamic index would put the array in scratch)
+__device__ __forceinline__ double pick4(int w, double a0, double a1, double a2, double a3) {
+    return w == 0 ? a0 : (w == 1 ? a1 : (w == 2 ? a2 : a3));
+}
+
 __device__ __forceinline__ void wall_emit(const fp_config& g, const Walls& W, int w,
                                           uint32_t pid, uint32_t step, uint32_t bounce,
                                           double v[3]) {
     const uint4 r = draw(g.seed, pid, step, PURPOSE_WALL, bounce);
     const double u0 = u01d(r.x), u1 = u01d(r.y), u2 = u01d(r.z);
-    const double RT = W.RT[w];
+    const double RT = pick4(w, W.RT[0], W.RT[1], W.RT[2], W.RT[3]);
     const double vn = sqrt(-2.0 * RT * log(u0));
     const double rr = sqrt(-2.0 * log(u1));
     const double za = rr * cos(TWO_PI * u2);
     const double zb = rr * sin(TWO_PI * u2);
-    const double s = W.sRT[w];
+    const double s = pick4(w, W.sRT[0], W.sRT[1], W.sRT[2], W.sRT[3]);
+    const double uw0 = pick4(w, g.u_wall[0][0], g.u_wall[1][0], g.u_wall[2][0], g.u_wall[3][0]);
+    const double uw1 = pick4(w, g.u_wall[0][1], g.u_wall[1][1], g.u_wall[2][1], g.u_wall[3][1]);
+    const double uw2 = pick4(w, g.u_wall[0][2], g.u_wall[1][2], g.u_wall[2][2], g.u_wall[3][2]);
     if (w < 2) {
         v[0] = (w == 0) ? vn : -vn;
-        v[1] = g.u_wall[w][1] + s * za;
-        v[2] = g.u_wall[w][2] + s * zb;
+        v[1] = uw1 + s * za;
+        v[2] = uw2 + s * zb;
     } else {
         v[1] = (w == 2) ? vn : -vn;
-        v[0] = g.u_wall[w][0] + s * za;
-        v[2] = g.u_wall[w][2] + s * zb;
+        v[0] = uw0 + s * za;
+        v[2] = uw2 + s * zb;
     }
 }
 
@@ -265,7 +273,7 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
     const double* __restrict__ mom, const double* __restrict__ rec, T* __restrict__ px,
     T* __restrict__ py, T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
     const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step_arg, int move,
-    const uint32_t* __restrict__ stepp) {
+    const uint32_t* __restrict__ stepp, int32_t* __restrict__ pend) {
     const uint32_t step = stepp ? stepp[0] : step_arg;
     const int64_t gt = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
     const int32_t cell = (int32_t)(gt / G);
@@ -320,11 +328,13 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
             else { s3 += (double)nn; s4 += (double)cn; }
         }
     }
+    // beyond the register cache, c* waits in the velocity arrays (same lane, same slot)
     for (int32_t j = lg + K * G; j < na; j += G) {
         const int32_t p = b + j;
         T cs[3], nn, cn;
         collide_one<T>(q, pvx[p], pvy[p], pvz[p], draw(g.seed, ppid[p], step, PURPOSE_COLLISION, 0),
                        cs, nn, cn);
+        pvx[p] = cs[0]; pvy[p] = cs[1]; pvz[p] = cs[2];
         const double d0 = cs[0], d1 = cs[1], d2 = cs[2];
         s0 += d0; s1 += d1; s2 += d2;
         if (exact) s3 = fma(d0, d0, fma(d1, d1, fma(d2, d2, s3)));
@@ -355,17 +365,102 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
         sc = (T)scale;
     }
 
-    // pass B: final velocity, then flight and key
+    // pass B: final velocity, then flight and key.  The common flight (straight, no wall
+    // or body in reach) is decided here; a particle that may meet a wall or the body gets
+    // its new velocity stored and takes the full flight in flight_rest_kernel, which keeps
+    // the FP64 re-emission code (and its registers) out of this kernel.
     const Walls W = make_walls(g);
     const double inv_dx = 1.0 / g.dx, inv_dy = 1.0 / g.dy;
-    auto finish = [&](int32_t p, T v0, T v1, T v2) {
+    constexpr bool TWO_D = GEOM != FP_COUETTE1D;
+    auto store_done = [&](int32_t p, double x, double y, T v0, T v1, T v2, bool gone) {
+        px[p] = (T)x;
+        if (TWO_D) py[p] = (T)y;
+        pvx[p] = v0; pvy[p] = v1; pvz[p] = v2;
+        pkey[p] = gone ? ncell : cell_key<TWO_D>(g, x, y, inv_dx, inv_dy);
+    };
+    // returns false when the full flight is still to do (velocity already stored)
+    auto finish_fast = [&](int32_t p, T v0, T v1, T v2) -> bool {
         if (!move) {
             pvx[p] = v0; pvy[p] = v1; pvz[p] = v2;
-            return;
+            return true;
         }
-        constexpr bool TWO_D = GEOM != FP_COUETTE1D;
+        const double x0 = (double)px[p], y0 = TWO_D ? (double)py[p] : 0.0;
+        const double w0 = (double)v0, w1 = (double)v1;
+        const double ex = __dadd_rn(x0, __dmul_rn(w0, g.dt));
+        const double ey = TWO_D ? __dadd_rn(y0, __dmul_rn(w1, g.dt)) : 0.0;
+        bool plain, gone = false;
+        if constexpr (GEOM == FP_CYLINDER2D) {
+            // no hit is possible when the body is out of reach by a wide margin
+            const double dxc = x0 - g.circle[0], dyc = y0 - g.circle[1];
+            const double reach = g.circle[2] + sqrt(w0 * w0 + w1 * w1) * g.dt;
+            plain = dxc * dxc + dyc * dyc > reach * reach * (1.0 + 1e-6) + 1e-300;
+            gone = ex < g.x0 || ex > g.x0 + g.lx || ey < g.y0 || ey > g.y0 + g.ly;
+        } else {
+            plain = !((ex < W.lo[0] && w0 < 0.0) || (ex > W.hi[0] && w0 > 0.0) ||
+                      (TWO_D && ((ey < W.lo[1] && w1 < 0.0) || (ey > W.hi[1] && w1 > 0.0))));
+        }
+        if (!plain) {
+            pvx[p] = v0; pvy[p] = v1; pvz[p] = v2;
+            return false;
+        }
+        store_done(p, st_round(ex, f32), TWO_D ? st_round(ey, f32) : 0.0, v0, v1, v2, gone);
+        return true;
+    };
+    auto newv = [&](T c, int i) -> T {
+        return __builtin_fma(c - cb[i], sc, q.U[i]);
+    };
+    // a particle that may meet a wall or the body keeps key -1 and its new velocity; the
+    // per-cell count lets flight_rest_kernel find it
+    int32_t npend = 0;
+    auto finish = [&](int32_t p, T v0, T v1, T v2) {
+        if (!finish_fast(p, v0, v1, v2)) {
+            pkey[p] = -1;
+            ++npend;
+        }
+    };
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int32_t j = lg + k * G;
+        if (j < n) {
+            const int32_t p = b + j;
+            if (active) finish(p, newv(cs0[k], 0), newv(cs1[k], 1), newv(cs2[k], 2));
+            else finish(p, pvx[p], pvy[p], pvz[p]);
+        }
+    }
+    for (int32_t j = lg + K * G; j < n; j += G) {
+        const int32_t p = b + j;
+        if (active) finish(p, newv(pvx[p], 0), newv(pvy[p], 1), newv(pvz[p], 2));
+        else finish(p, pvx[p], pvy[p], pvz[p]);
+    }
+    if (move) {
+        npend = group_sum_i<G>(npend);
+        if (in && lg == 0) pend[cell] = npend;
+    }
+}
+
+// the flights collide_kernel left: particles with key -1 in cells with pend > 0 fly from
+// their stored position with their stored (new) velocity, through walls / past the body
+template <typename T, int G, int GEOM>
+__global__ __launch_bounds__(ST_BLOCK) void flight_rest_kernel(
+    fp_config g, int32_t ncell, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ pend, T* __restrict__ px, T* __restrict__ py,
+    T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
+    const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step_arg,
+    const uint32_t* __restrict__ stepp) {
+    const int64_t gt = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
+    const int32_t cell = (int32_t)(gt / G);
+    const int lg = (int)(gt % G);
+    if (cell >= ncell || pend[cell] == 0) return;
+    const uint32_t step = stepp ? stepp[0] : step_arg;
+    const bool f32 = sizeof(T) == 4;
+    constexpr bool TWO_D = GEOM != FP_COUETTE1D;
+    const Walls W = make_walls(g);
+    const double inv_dx = 1.0 / g.dx, inv_dy = 1.0 / g.dy;
+    const int32_t b = offsets[cell], e = offsets[cell + 1];
+    for (int32_t p = b + lg; p < e; p += G) {
+        if (pkey[p] != -1) continue;
         double pos[2] = {(double)px[p], TWO_D ? (double)py[p] : 0.0};
-        double v[3] = {(double)v0, (double)v1, (double)v2};
+        double v[3] = {(double)pvx[p], (double)pvy[p], (double)pvz[p]};
         bool gone = false;
         if constexpr (GEOM == FP_CYLINDER2D) {
             gone = fly_open(g, pos, v, ppid[p], step, f32);
@@ -378,31 +473,6 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
         if (TWO_D) py[p] = (T)pos[1];
         pvx[p] = (T)v[0]; pvy[p] = (T)v[1]; pvz[p] = (T)v[2];
         pkey[p] = gone ? ncell : cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy);
-    };
-    auto newv = [&](T c, int i) -> T {
-        return __builtin_fma(c - cb[i], sc, q.U[i]);
-    };
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int32_t j = lg + k * G;
-        if (j < n) {
-            const int32_t p = b + j;
-            if (active)
-                finish(p, newv(cs0[k], 0), newv(cs1[k], 1), newv(cs2[k], 2));
-            else
-                finish(p, pvx[p], pvy[p], pvz[p]);
-        }
-    }
-    for (int32_t j = lg + K * G; j < n; j += G) {
-        const int32_t p = b + j;
-        if (active) {
-            T cs[3], nn, cn;
-            collide_one<T>(q, pvx[p], pvy[p], pvz[p],
-                           draw(g.seed, ppid[p], step, PURPOSE_COLLISION, 0), cs, nn, cn);
-            finish(p, newv(cs[0], 0), newv(cs[1], 1), newv(cs[2], 2));
-        } else {
-            finish(p, pvx[p], pvy[p], pvz[p]);
-        }
     }
 }
 
@@ -447,7 +517,11 @@ static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const
     const unsigned grid = (unsigned)((threads + ST_BLOCK - 1) / ST_BLOCK);
     hipLaunchKernelGGL((collide_kernel<T, G, ST_K, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
                        c->cfg, c->ncell, off, mom, rec, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy,
-                       (T*)p->vz, p->pid, p->key, step, move, stepp);
+                       (T*)p->vz, p->pid, p->key, step, move, stepp, c->pend);
+    if (move)
+        hipLaunchKernelGGL((flight_rest_kernel<T, G, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
+                           c->cfg, c->ncell, off, (const int32_t*)c->pend, (T*)p->x, (T*)p->y,
+                           (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key, step, stepp);
 }
 
 template <typename T, int GEOM>

@@ -210,9 +210,11 @@ def closure_timings(w, params, ncells=1_000_000, reps=20, seed=0, device="cuda")
         return s.elapsed_time(e) / reps * 1e-3
 
     t_exact = timeit(lambda: ctx.closure_solve(mom, rec, st))
+    t_free = timeit(lambda: net.closure(mom, rec, st, float("inf"), 0.0))
     t_nn = timeit(lambda: net.closure(mom, rec, st, 0.05, 0.05))
     fb = float(((st == F.CELL_NN_FALLBACK).sum()).item()) / max(n, 1)
-    return {"cells": n, "exact_s": t_exact, "learned_s": t_nn,
+    return {"cells": n, "exact_s": t_exact, "learned_s": t_nn, "learned_unchecked_s": t_free,
+            "learned_unchecked_cells_per_s": n / t_free,
             "exact_cells_per_s": n / t_exact, "learned_cells_per_s": n / t_nn,
             "learned_fallback_fraction": fb}
 

@@ -120,6 +120,32 @@ def test_forced_fallback_is_bitwise_the_exact_closure():
     np.testing.assert_array_equal(a[:, :14], b[:, :14])
 
 
+def test_unchecked_closure_equals_accept_all():
+    """tol_abs = +inf skips the residual check: the record is the one the check path
+    writes when it accepts everything (same bits), and status NN for every valid cell."""
+    F = fp()
+    nc = 1000 + 33
+    mom = cells(nc, 6)
+    mom[7] = 0
+    mom[7, 0] = 1                      # an empty cell
+    w = I.couette(ncell=nc, eps_hat=0.01)
+    ctx = F.Context(w, 1)
+    net = F.Network(ctx, 0)
+    net.load(dev(M.pack(random_params(3)).astype(np.float32), torch.float32))
+    md = dev(mom, torch.float64)
+    r1 = torch.zeros((nc, 16), dtype=torch.float64, device="cuda")
+    r2 = torch.zeros_like(r1)
+    s1 = torch.zeros(nc, dtype=torch.int32, device="cuda")
+    s2 = torch.zeros_like(s1)
+    net.closure(md, r1, s1, 1e300, 0.0)
+    net.closure(md, r2, s2, float("inf"), 0.0)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(s1.cpu().numpy(), s2.cpu().numpy())
+    np.testing.assert_array_equal(r1.cpu().numpy(), r2.cpu().numpy())
+    st = s2.cpu().numpy()
+    assert st[7] == F.CELL_EMPTY and np.sum(st == F.CELL_NN) == nc - 1
+
+
 @pytest.mark.parametrize("loss_kind", [0, 1])
 def test_gradient_matches_bf16_oracle(loss_kind):
     F = fp()
