@@ -433,14 +433,14 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_dest_kernel(int32_t ncell, in
     if (k < ncell) cnt[k] = dest_count(k, nx, ny, ncnt, fcnt);
 }
 
-// one workgroup: destination counts and both exclusive scans for grids of up to
-// SMALL_SCAN_CELLS cells (one launch instead of four)
+// one workgroup: both exclusive scans for grids of up to SMALL_SCAN_CELLS cells (one
+// launch instead of three)
 constexpr int SMALL_SCAN_BLOCK = 1024, SMALL_SCAN_ITEMS = 16;
 constexpr int SMALL_SCAN_CELLS = SMALL_SCAN_BLOCK * SMALL_SCAN_ITEMS;
 
 __global__ __launch_bounds__(SMALL_SCAN_BLOCK) void rebin_small_scan_kernel(
-    int32_t ncell, int32_t nx, int32_t ny, const int32_t* __restrict__ ncnt,
-    const int32_t* __restrict__ fcnt, int32_t* __restrict__ offsets, int32_t* __restrict__ foff) {
+    int32_t ncell, const int32_t* __restrict__ cnt, const int32_t* __restrict__ fcnt,
+    int32_t* __restrict__ offsets, int32_t* __restrict__ foff) {
     __shared__ int32_t sh[SMALL_SCAN_BLOCK / 64 + 1];
     const int32_t base = threadIdx.x * SMALL_SCAN_ITEMS;
     int32_t va[SMALL_SCAN_ITEMS], vb[SMALL_SCAN_ITEMS];
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(SMALL_SCAN_BLOCK) void rebin_small_scan_kernel(
 #pragma unroll
     for (int i = 0; i < SMALL_SCAN_ITEMS; ++i) {
         const int32_t k = base + i;
-        va[i] = k < ncell ? dest_count(k, nx, ny, ncnt, fcnt) : 0;
+        va[i] = k < ncell ? cnt[k] : 0;
         vb[i] = k < ncell ? fcnt[k] : 0;
         sa += va[i];
         sb += vb[i];
@@ -562,7 +562,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_push_kernel(
         return;
     }
     const int grp = threadIdx.x / G, lg = threadIdx.x % G;
-    const int32_t cell = (int32_t)blockIdx.x * GROUPS + grp;
+    const int32_t cell = xcd_block((int32_t)blockIdx.x, cell_blocks) * GROUPS + grp;
     const bool in = cell < ncell;
     int32_t b = 0, e = 0, cx = 0, cy = 0;
     if (in) {
@@ -653,12 +653,12 @@ static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_
     hipLaunchKernelGGL((rebin_count_kernel<G>), dim3(cblocks_count + FAR_BLOCKS), dim3(BIN_BLOCK), 0,
                        s, nc, nx, n, cap, cblocks_count, src_off, (const int32_t*)src->key, c->ncnt,
                        c->ccnt, c->farn, c->cmask, c->errcount);
+    hipLaunchKernelGGL(rebin_dest_kernel, dim3((nc + BIN_BLOCK - 1) / BIN_BLOCK), dim3(BIN_BLOCK), 0,
+                       s, nc, nx, ny, (const int32_t*)c->ncnt, (const int32_t*)c->ccnt, c->cnt);
     if (nc <= SMALL_SCAN_CELLS) {
-        hipLaunchKernelGGL(rebin_small_scan_kernel, dim3(1), dim3(SMALL_SCAN_BLOCK), 0, s, nc, nx, ny,
-                           (const int32_t*)c->ncnt, (const int32_t*)c->ccnt, offsets, c->coff);
+        hipLaunchKernelGGL(rebin_small_scan_kernel, dim3(1), dim3(SMALL_SCAN_BLOCK), 0, s, nc,
+                           (const int32_t*)c->cnt, (const int32_t*)c->ccnt, offsets, c->coff);
     } else {
-        hipLaunchKernelGGL(rebin_dest_kernel, dim3((nc + BIN_BLOCK - 1) / BIN_BLOCK), dim3(BIN_BLOCK), 0,
-                           s, nc, nx, ny, (const int32_t*)c->ncnt, (const int32_t*)c->ccnt, c->cnt);
         const int32_t nblocks = (nc + SCAN_TILE - 1) / SCAN_TILE;
         hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt,
                            nc, c->blocksum);

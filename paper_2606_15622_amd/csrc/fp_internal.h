@@ -131,6 +131,17 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
+// Workgroups are handed to the 8 XCDs (each with its own L2) round robin.  xcd_block
+// renumbers the first nblocks workgroups so that each XCD gets one contiguous range of
+// logical blocks: neighbouring cells, which share destination cache lines in the
+// re-sort, then meet in the same L2.  A bijection on [0, nblocks).
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int32_t xcd_block(int32_t bid, int32_t nblocks) {
+    const int32_t q = nblocks / NUM_XCD, r = nblocks % NUM_XCD;
+    const int32_t x = bid % NUM_XCD, i = bid / NUM_XCD;
+    return x * q + min(x, r) + i;
+}
+
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);

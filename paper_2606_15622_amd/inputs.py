@@ -167,6 +167,37 @@ def maxwellian_state(w, ppc=None, seed=None, T=None, drift=(0.0, 0.0, 0.0)):
     return out
 
 
+def grad_state(w, ppc, shear, heat, seed=0):
+    """ppc particles in every cell of w, velocities from the Maxwellian at T_init weighted
+    by 1 + shear c_x c_y / theta + heat (c_x / sqrt(theta)) (|c|^2 / (5 theta) - 1)
+    (a Grad-type perturbation carrying shear stress P_xy and heat flux along x), drawn
+    by rejection from the Maxwellian; positions at the cell centres.  The same state in
+    every cell, independent draws."""
+    rng = np.random.default_rng(seed)
+    nx, ny = int(w["nx"]), int(w["ny"])
+    nc = nx * ny
+    n = nc * ppc
+    th = KB / MASS_AR * float(w["T_init"])
+    s = math.sqrt(th)
+    kmax = 6.0
+    bound = 1.0 + abs(shear) * kmax * kmax + abs(heat) * kmax * (kmax * kmax / 5.0 + 1.0)
+    out = np.empty((0, 3))
+    while out.shape[0] < n:
+        m = 2 * (n - out.shape[0]) + 1000
+        z = rng.standard_normal((m, 3))
+        z = z[(np.abs(z) < kmax).all(axis=1)]
+        phi = shear * z[:, 0] * z[:, 1] + heat * z[:, 0] * ((z * z).sum(1) / 5.0 - 1.0)
+        keep = rng.random(z.shape[0]) * bound < np.maximum(1.0 + phi, 0.0)
+        out = np.concatenate([out, z[keep]])
+    v = out[:n] * s
+    cell = np.repeat(np.arange(nc, dtype=np.int64), ppc)
+    x = w["x0"] + (cell % nx + 0.5) * w["dx"]
+    y = np.zeros(n) if w["geometry"] == "couette1d" else w["y0"] + (cell // nx + 0.5) * w["dy"]
+    return dict(x=_round(w, x), y=_round(w, y), vx=_round(w, v[:, 0]), vy=_round(w, v[:, 1]),
+                vz=_round(w, v[:, 2]), pid=np.arange(n, dtype=np.uint32),
+                key=cell.astype(np.int32))
+
+
 def scattered_state(w, n, seed=0, face_hits=0.05):
     """n particles at uniformly random positions over the domain (not grouped), a
     fraction of them placed exactly on cell faces or domain walls."""

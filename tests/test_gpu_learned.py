@@ -4,10 +4,10 @@ A network is trained on the GPU by the library's MFMA kernels on Couette moment 
 (Kn 0.1 and 0.5), then
   * on held-out Couette cells its normalised coefficients are compared with the exact
     ones; the Langevin drift corresponds to zero coefficients (relative error 1);
-  * the Couette channel is run with the exact closure, the pure network (no fallback)
-    and the Langevin drift.  The Langevin drift has Pr = 3/2 instead of 2/3 (the heat
-    flux relaxes at 3/tau instead of 4/(3 tau)), so viscous heating raises the centre
-    temperature about twice as much; the network must reproduce the cubic-FP rise.
+  * homogeneous cells carrying shear stress and heat flux relax under the exact closure,
+    the pure network (no check, no fallback) and the Langevin drift: the closure sets the
+    heat-flux relaxation rate to 4/(3 tau) (Pr = 2/3) where the Langevin drift gives
+    3/tau, and the network must reproduce the closure's rate.
 """
 import numpy as np
 import pytest
@@ -23,11 +23,11 @@ def trained():
     from paper_2606_15622_amd import fpgpu as F
     from paper_2606_15622_amd import learned as L
     F.load()
-    mom = L.couette_dataset(kns=(0.1, 0.5), n_transient=300, n_samples=1000, seed=11)
+    mom = L.couette_dataset(kns=(0.1, 0.5), n_transient=300, n_samples=3000, seed=11)
     feats, tg, sys = L.dataset(I.couette(), mom)
     sc = L.fit_scalers(feats, tg)
     p0 = L.init_params(sc, seed=0)
-    params, hist = L.train(I.couette(), p0, feats, tg, epochs=40, lr=1e-3, batch=4096,
+    params, hist = L.train(I.couette(), p0, feats, tg, epochs=50, lr=1e-3, batch=4096,
                            patience=8)
     return params, hist
 
@@ -66,26 +66,55 @@ def test_heldout_coefficients_beat_the_langevin_drift(trained):
     assert err_nn < 0.5, err_nn   # Langevin (zero coefficients) has relative error 1
 
 
-def _center_rise(params=None, langevin=False, seed=5, steps=2500, avg=2000):
-    from paper_2606_15622_amd import learned as L
-    w = I.couette(kn=0.1, ncell=100, ppc=100, precision="f64", seed=seed, n_skip=steps - avg)
-    sim = L.LearnedSimulation(w, I.maxwellian_state(w), params=params, tol_abs=1e30, tol_rel=0.0,
-                              langevin=langevin)
-    sim.run(0, steps)
-    f = L.fields(w, sim.samp)
-    T = f["T"]
-    return T[45:55].mean() - 0.5 * (T[:5].mean() + T[-5:].mean())
+def _relaxation_rates(params=None, langevin=False, cells=4000, ppc=500, steps=12, seed=21):
+    """Homogeneous relaxation (collision only, no flight) of a Grad-type state with shear
+    stress and heat flux in every cell; returns the decay rates of P_xy and S_x in units
+    of 1/tau (fitted on the cell-averaged moments)."""
+    import math
+    from paper_2606_15622_amd import fpgpu as F
+    w = I.couette(kn=0.1, ncell=cells, ppc=ppc, precision="f64", seed=seed)
+    T = w["T_init"]
+    mu = w["mu_ref"] * (T / w["T_ref"]) ** w["omega"]
+    tau = 2.0 * mu / (w["n_number"] * w["kB"] * T)
+    w = dict(w, dt=tau / 20.0, n_min=(1 << 30) if langevin else w["n_min"])
+    sim = F.Simulation(w, I.grad_state(w, ppc, 0.08, 0.08, seed=seed))
+    net = None
+    if params is not None:
+        net = F.Network(sim.ctx, 0)
+        net.load(params)
+    pxy, sx, taus = [], [], []
+    for s in range(steps + 1):
+        sim.sort()
+        sim.ctx.moments(sim.a, sim.offsets, sim.mom)
+        m = sim.mom
+        th = m[:, 4]
+        pxy.append(float((m[:, 6] / th).mean()))
+        sx.append(float(((m[:, 11] + m[:, 14] + m[:, 16]) / th ** 1.5).mean()))
+        if net is not None:
+            net.closure(sim.mom, sim.rec, sim.status, math.inf, 0.0)
+        else:
+            sim.ctx.closure_solve(sim.mom, sim.rec, sim.status)
+        taus.append(float(sim.rec[:, 9].mean()))
+        sim.ctx.step(sim.a, sim.offsets, sim.mom, sim.rec, s, F.STEP_COLLIDE)
+    t = np.arange(steps + 1) * w["dt"] / np.mean(taus)
+    rs = -np.polyfit(t, np.log(np.array(pxy) / pxy[0]), 1)[0]
+    rq = -np.polyfit(t, np.log(np.array(sx) / sx[0]), 1)[0]
+    return rs, rq
 
 
-def test_network_reproduces_cubic_fp_viscous_heating(trained):
+def test_network_restores_the_prandtl_number_of_the_closure(trained):
+    """The closure's job is transport: with it the heat flux relaxes at 4/(3 tau)
+    (Pr = 2/3), without it (Langevin drift) at 3/tau; the stress relaxes at 2/tau in
+    both.  The network, run without any check or fallback, must land near the closure's
+    rate, far from the Langevin one."""
     params, _ = trained
-    d_ex = _center_rise()
-    d_nn = _center_rise(params=params)
-    d_lan = _center_rise(langevin=True)
-    print(f"centre temperature rise: exact {d_ex:.3f} K, network {d_nn:.3f} K, "
-          f"Langevin {d_lan:.3f} K")
-    # the closure matters here: without it the heat flux relaxes at 3/tau instead of
-    # 4/(3 tau) and the channel heats more (measured 6.9 K vs 5.2 K); the run-to-run noise
-    # of the rise over 2000 averaged steps is about 0.1 K
-    assert d_lan > d_ex + 1.0
-    assert abs(d_nn - d_ex) < 0.35 * abs(d_lan - d_ex), (d_ex, d_nn, d_lan)
+    rs_ex, rq_ex = _relaxation_rates()
+    rs_nn, rq_nn = _relaxation_rates(params=params)
+    rs_lan, rq_lan = _relaxation_rates(langevin=True)
+    print(f"stress rate: exact {rs_ex:.3f} network {rs_nn:.3f} Langevin {rs_lan:.3f}; "
+          f"heat-flux rate: exact {rq_ex:.3f} network {rq_nn:.3f} Langevin {rq_lan:.3f}")
+    assert rq_ex == pytest.approx(4.0 / 3.0, rel=0.1)
+    assert rq_lan == pytest.approx(3.0, rel=0.1)
+    assert rs_ex == pytest.approx(2.0, rel=0.1) and rs_lan == pytest.approx(2.0, rel=0.1)
+    assert abs(rq_nn - rq_ex) < 0.25 * abs(rq_lan - rq_ex), (rq_ex, rq_nn, rq_lan)
+    assert rs_nn == pytest.approx(rs_ex, rel=0.1)
