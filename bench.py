@@ -53,38 +53,43 @@ def alg_bytes(kind, n, nc):
             "sort": 56 * n + 12 * nc, "closure": 388 * nc, "sample": 512 * nc}[kind]
 
 
-def time_entry(torch, fn, reps):
-    """Mean duration of one call of fn: reps calls captured in a HIP graph, the replay
-    bracketed by HIP events on the launch stream (no host launch gaps inside)."""
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        for _ in range(reps):
-            fn()
-    g.replay()
-    torch.cuda.synchronize()
+def gpu_hold(torch, ms):
+    """Keep the launch stream busy for about `ms` milliseconds (a bounded spin kernel), so
+    that the host can enqueue far ahead and the queue never runs dry behind it."""
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s.record()
-    g.replay()
+    torch.cuda._sleep(1_000_000)
     e.record()
     torch.cuda.synchronize()
-    return s.elapsed_time(e) / reps
+    per = max(s.elapsed_time(e), 1e-3) / 1_000_000       # ms per spin cycle
+    torch.cuda._sleep(int(min(ms / per, 2e9)))
 
 
-def entry_times(torch, F, sim, s, reps=20):
-    """Per-entry-point durations on the state the loop left: sort (a -> b), then moments,
-    sample, closure and collide + move on b; each entry point repeated reps times on the
-    same inputs (idempotent except collide + move, which keeps flying the same cells)."""
+def entry_times(torch, F, sim, s, steps=20):
+    """Per-entry-point durations inside the loop itself: `steps` eager steps (sort,
+    moments, sample, closure, collide + move, in the loop's order) are enqueued behind a
+    GPU hold, each entry point between two HIP events on the launch stream, so the events
+    time back-to-back kernels with no host gaps.  Means in milliseconds."""
     ctx = sim.ctx
-    a, b, o0, o1 = sim.a, sim.b, sim.offs[0], sim.offs[1]
-    st = torch.tensor([s], dtype=torch.int32, device="cuda")
-    out = {"sort": time_entry(torch, lambda: ctx.rebin(a, o0, b, o1), reps)}
-    out["moments"] = time_entry(torch, lambda: ctx.moments(b, o1, sim.mom), reps)
-    samp = sim.samp.clone()
-    out["sample"] = time_entry(torch, lambda: ctx.sample(sim.mom, samp), reps)
-    out["closure"] = time_entry(torch, lambda: ctx.closure_solve(sim.mom, sim.rec, sim.status), reps)
-    out["step"] = time_entry(torch, lambda: ctx.step_dev(b, o1, sim.mom, sim.rec, st,
-                                                         F.STEP_COLLIDE | F.STEP_MOVE), reps)
-    return out
+    names = ("sort", "moments", "sample", "closure", "step")
+    ev = {k: [] for k in names}
+    torch.cuda.synchronize()
+    gpu_hold(torch, 60.0)
+    for i in range(steps):
+        calls = (("sort", lambda: sim.sort()),
+                 ("moments", lambda: ctx.moments(sim.a, sim.offsets, sim.mom)),
+                 ("sample", lambda: ctx.sample(sim.mom, sim.samp)),
+                 ("closure", lambda: ctx.closure_solve(sim.mom, sim.rec, sim.status)),
+                 ("step", lambda: ctx.step(sim.a, sim.offsets, sim.mom, sim.rec, s + i,
+                                           F.STEP_COLLIDE | F.STEP_MOVE)))
+        for k, fn in calls:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            ev[k].append((e0, e1))
+    torch.cuda.synchronize()
+    return {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
 
 
 def run_workload(torch, F, I, w, steps, warmup, graph=True):
@@ -127,11 +132,31 @@ def run_workload(torch, F, I, w, steps, warmup, graph=True):
     return dict(n=n, nc=nc, t=t, steps=steps, kern=kern, ok_cells=int((st == F.CELL_OK).sum()))
 
 
-def roofline_of(res, kind="step"):
+def counter_traffic(name):
+    """HBM bytes per launch from a committed counter summary under profiles/ (lines
+    "key: value"): traffic_bytes_per_launch, valid only while every source it lists
+    ("source: <path> <sha256>") is unchanged; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    val, ok = None, True
+    for line in open(path):
+        if line.startswith("source:"):
+            _, rel, digest = line.split()
+            f = os.path.join(ROOT, rel)
+            ok = ok and os.path.exists(f) and hashlib.sha256(open(f, "rb").read()).hexdigest() == digest
+        elif line.startswith("traffic_bytes_per_launch:"):
+            val = int(float(line.split()[1]))
+    return val if ok else None
+
+
+def roofline_of(res, kind="step", traffic_file=None):
     k = res["kern"][kind]
     ach = k["alg_GBps"]
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kind,
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": counter_traffic(traffic_file) if traffic_file else None, "kernel": kind,
             "alg_bytes_per_launch": k["alg_bytes"], "avg_ms": k["ms"]}
 
 
@@ -187,7 +212,7 @@ def main():
         "cell_closures_per_s": round(nc * res["steps"] / res["t"], 1),
         "closure_kernel_cell_closures_per_s": round(nc / (kern["closure"]["ms"] * 1e-3), 1),
         "kernels": kern,
-        "roofline": roofline_of(res, dominant),
+        "roofline": roofline_of(res, dominant, f"{dominant}_cavity100x100x100_counters.txt"),
         "timed_loop": "HIP graph replay of two captured steps",
         "eager_particle_steps_per_s": round(res_eager["n"] * res_eager["steps"] / res_eager["t"], 1),
     }
@@ -198,7 +223,8 @@ def main():
             "workload": "cavity2d 448x448 cells, 100 particles/cell (2.0e7 particles)",
             "value": round(rs["n"] * rs["steps"] / rs["t"], 1), "unit": "particle-steps/s",
             "ms_per_step": round(rs["t"] / rs["steps"] * 1e3, 4), "kernels": rs["kern"],
-            "roofline_step": roofline_of(rs, "step"), "roofline_moments": roofline_of(rs, "moments"),
+            "roofline_step": roofline_of(rs, "step", "step_cavity448x448x100_counters.txt"),
+            "roofline_moments": roofline_of(rs, "moments", "moments_cavity448x448x100_counters.txt"),
         }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(I, w)

@@ -138,7 +138,7 @@ extern "C" int fp_init(const fp_config* cfg, fp_ctx** out) {
     bool ok = dalloc(&c->cnt, nc) && dalloc(&c->ccnt, nc) && dalloc(&c->coff, nc + 1) &&
               dalloc(&c->ccur, nc) && dalloc(&c->cwave, cap) && dalloc(&c->cmask, cap) &&
               dalloc(&c->gidx, cap) && dalloc(&c->blocksum, 2 * 8192) &&
-              dalloc(&c->errcount, 1) && dalloc(&c->ncnt, 9 * (nc - 1) + 1) && dalloc(&c->farn, 1) &&
+              dalloc(&c->errcount, 1) && dalloc(&c->ncnt, 9 * (nc - 1) + 1) && dalloc(&c->farn, 1) && dalloc(&c->bidx, cap) &&
               dalloc(&c->pend, nc);
     // the sort counters start at zero; every fp_bin / fp_rebin leaves them zero again
     if (ok) ok = hipMemset(c->errcount, 0, sizeof(unsigned long long)) == hipSuccess &&
@@ -202,6 +202,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     (void)hipFree(c->ncnt);
     (void)hipFree(c->farn);
     (void)hipFree(c->pend);
+    (void)hipFree(c->bidx);
     (void)hipFree(c->vol);
     (void)hipFree(c->nvol);
     (void)hipFree(c->inj);

@@ -56,20 +56,31 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_wave_kernel(
 constexpr int SCAN_BLOCK = 256, SCAN_ITEMS = 16, SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 
 __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* sh, int32_t& total) {
-    // Hillis-Steele over the block in shared memory
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
-        const int32_t add = t >= off ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
+    // wave scans by shuffles, then the SCAN_BLOCK/64 wave totals (sh holds at least
+    // SCAN_BLOCK ints; the first SCAN_BLOCK/64 + 1 are used)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
-    total = sh[SCAN_BLOCK - 1];
-    const int32_t incl = sh[t];
+    if (lane == 63) sh[wv] = x;
     __syncthreads();
-    return incl - v;
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int i = 0; i < SCAN_BLOCK / 64; ++i) {
+            const int32_t t = sh[i];
+            sh[i] = run;
+            run += t;
+        }
+        sh[SCAN_BLOCK / 64] = run;
+    }
+    __syncthreads();
+    total = sh[SCAN_BLOCK / 64];
+    const int32_t r = sh[wv] + x - v;
+    __syncthreads();
+    return r;
 }
 
 __global__ __launch_bounds__(SCAN_BLOCK) void scan_reduce_kernel(
@@ -255,7 +266,7 @@ static void gather_launch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
 template <typename T>
 static void gather_dispatch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
                             const int32_t* offsets, int32_t* perm, hipStream_t s) {
-    switch (lanes_per_cell(c, src->n)) {
+    switch (lanes_per_cell(c, src->n, FILL_8)) {
         case 4: gather_launch<T, 4>(c, src, dst, offsets, perm, s); break;
         case 8: gather_launch<T, 8>(c, src, dst, offsets, perm, s); break;
         case 16: gather_launch<T, 16>(c, src, dst, offsets, perm, s); break;
@@ -266,15 +277,16 @@ static void gather_dispatch(fp_ctx* c, const fp_particles* src, fp_particles* ds
 
 // ---- re-sort of particles that were sorted by cell one step earlier ---------------------
 // After a step almost every particle sits in one of the 3 x 3 cells around its old cell.
-// Pass 1 counts, per old cell, the particles bound for each of those nine neighbours
-// (ncnt, plain stores) and appends every other particle (moved farther, or not grouped)
-// to a short list.  The destination count of a cell is then the sum of nine neighbour
-// entries plus its far arrivals.  In a destination cell the stable order is the order of
-// source indices: the neighbour runs come in the order of their old cells, and a far
-// arrival goes before every run whose old cell starts after it.  So each old cell pushes
-// its particles straight to their slots, and the far arrivals (sorted per destination by
-// source index on the fly) find theirs by counting.  The only global atomics are those of
-// the far list.
+// Pass 1 (one group per OLD cell) counts the particles bound for each of those nine
+// neighbours, and lists the source indices of each direction, in source order, inside
+// the old cell's own index range ("buckets": bidx, bucket ends in bend[cell][9]); every
+// other particle (moved farther, or after the grouped range) goes to a short far list.
+// The count of destination cell k is the sum of nine neighbour buckets plus its far
+// arrivals, and one scan gives the offsets.  Pass 2 (one group per DESTINATION cell)
+// concatenates its nine buckets in the order of their old cells -- which is the order of
+// source indices, i.e. the stable order -- inserting each far arrival before the buckets
+// whose old cell starts after it, and writes its slots contiguously (whole cache lines,
+// each written once).  The only global atomics are those of the far list.
 
 __device__ __forceinline__ int near_dir(int32_t k, int32_t cx, int32_t cy, int32_t nx) {
     const int32_t ky = k / nx, kx = k - ky * nx;
@@ -318,6 +330,12 @@ __device__ __forceinline__ void far_put(int32_t k, int32_t j, int64_t slot, int6
     atomicAdd(&fcnt[k], 1);
 }
 
+// length of the bucket of old cell c for direction d
+__device__ __forceinline__ int32_t bucket_len(const int32_t* __restrict__ bend, int32_t c, int d) {
+    const int32_t* e = bend + (int64_t)c * 9;
+    return e[d] - (d > 0 ? e[d - 1] : 0);
+}
+
 // grid: ncell*G lanes for the old cells, then FAR_BLOCKS blocks for the ungrouped tail.
 // Far movers are appended to the list with one atomic per block (cells) or per wave
 // (tail) on its length: a single counter hit once per particle would serialise.
@@ -327,8 +345,9 @@ template <int G>
 __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     int32_t ncell, int32_t nx, int64_t n, int64_t cap, int32_t cell_blocks,
     const int32_t* __restrict__ src_off, const int32_t* __restrict__ key,
-    int32_t* __restrict__ ncnt, int32_t* __restrict__ fcnt, int32_t* __restrict__ farn,
-    uint64_t* __restrict__ flist, unsigned long long* __restrict__ errcount) {
+    int32_t* __restrict__ bend, int32_t* __restrict__ bidx, int32_t* __restrict__ fcnt,
+    int32_t* __restrict__ farn, uint64_t* __restrict__ flist,
+    unsigned long long* __restrict__ errcount) {
     __shared__ int32_t sh[BIN_BLOCK / 64 + 1];
     __shared__ int32_t s_base;
     const int lane = threadIdx.x & 63;
@@ -362,12 +381,12 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     const int lg = (int)(gt % G);
     int c9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     int32_t nfar = 0, b = 0, e = 0, cx = 0, cy = 0;
+    constexpr int KR = 4;
     if (cell < ncell) {
         b = max(src_off[cell], 0);
         e = (int32_t)min((int64_t)src_off[cell + 1], n);
         cy = cell / nx;
         cx = cell - cy * nx;
-        constexpr int KR = 4;
         for (int32_t j0 = b + lg; j0 < e; j0 += G * KR) {
             int32_t kk[KR];
 #pragma unroll
@@ -387,11 +406,48 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
             }
         }
     }
+    // bucket starts inside the cell's range (prefix over directions), same in every lane
+    int32_t bst[9];
+    {
+        int32_t acc = 0;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) c9[i] = group_sum_i<G>(c9[i]);
-    if (cell < ncell && lg == 0) {
+        for (int i = 0; i < 9; ++i) {
+            c9[i] = group_sum_i<G>(c9[i]);
+            bst[i] = acc;
+            acc += c9[i];
+        }
+    }
+    if (cell < ncell) {
+        if (lg == 0) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) ncnt[(int64_t)cell * 9 + i] = c9[i];
+            for (int i = 0; i < 9; ++i) bend[(int64_t)cell * 9 + i] = bst[i] + c9[i];
+        }
+        // second pass: source indices into the buckets, in source order (ballot ranks)
+        const int gl = lane - lg;
+        const uint64_t gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << gl);
+        int32_t run[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int32_t j0 = b; j0 < e; j0 += G * KR) {
+            int32_t kk[KR];
+#pragma unroll
+            for (int u = 0; u < KR; ++u) {
+                const int32_t j = j0 + u * G + lg;
+                kk[u] = j < e ? key[j] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < KR; ++u) {
+                const int32_t k = kk[u];
+                int d = -1;
+                if (k >= 0 && k < ncell) d = near_dir(k, cx, cy, nx);
+                int32_t pos = 0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const uint64_t m = __ballot(d == i) & gmask;
+                    if (d == i) pos = bst[i] + run[i] + __popcll(m & below);
+                    run[i] += __popcll(m);
+                }
+                if (d >= 0) bidx[b + pos] = j0 + u * G + lg;
+            }
+        }
     }
     int32_t tot;
     const int32_t pre = wg_excl_scan<BIN_BLOCK>(nfar, sh, tot);
@@ -409,7 +465,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
 
 // particles arriving in cell k from its neighbours (and from far away)
 __device__ __forceinline__ int32_t dest_count(int32_t k, int32_t nx, int32_t ny,
-                                              const int32_t* __restrict__ ncnt,
+                                              const int32_t* __restrict__ bend,
                                               const int32_t* __restrict__ fcnt) {
     const int32_t ky = k / nx, kx = k - ky * nx;
     int32_t sum = fcnt[k];
@@ -419,56 +475,65 @@ __device__ __forceinline__ int32_t dest_count(int32_t k, int32_t nx, int32_t ny,
         for (int ex = -1; ex <= 1; ++ex) {
             const int32_t sx = kx - ex, sy = ky - ey;
             if (sx >= 0 && sx < nx && sy >= 0 && sy < ny)
-                sum += ncnt[(int64_t)(sy * nx + sx) * 9 + (ey + 1) * 3 + (ex + 1)];
+                sum += bucket_len(bend, sy * nx + sx, (ey + 1) * 3 + (ex + 1));
         }
     return sum;
 }
 
 __global__ __launch_bounds__(BIN_BLOCK) void rebin_dest_kernel(int32_t ncell, int32_t nx,
                                                                 int32_t ny,
-                                                                const int32_t* __restrict__ ncnt,
+                                                                const int32_t* __restrict__ bend,
                                                                 const int32_t* __restrict__ fcnt,
                                                                 int32_t* __restrict__ cnt) {
     const int32_t k = blockIdx.x * BIN_BLOCK + threadIdx.x;
-    if (k < ncell) cnt[k] = dest_count(k, nx, ny, ncnt, fcnt);
+    if (k < ncell) cnt[k] = dest_count(k, nx, ny, bend, fcnt);
 }
 
-// one workgroup: both exclusive scans for grids of up to SMALL_SCAN_CELLS cells (one
-// launch instead of three)
-constexpr int SMALL_SCAN_BLOCK = 1024, SMALL_SCAN_ITEMS = 16;
-constexpr int SMALL_SCAN_CELLS = SMALL_SCAN_BLOCK * SMALL_SCAN_ITEMS;
+// both exclusive scans for grids of up to SMALL_SCAN_CELLS cells in one launch: each
+// workgroup of BIN_BLOCK cells adds up all earlier counts itself (at most a few tens of
+// KB, coalesced) instead of waiting for a second pass
+constexpr int SMALL_SCAN_CELLS = 1 << 15;
 
-__global__ __launch_bounds__(SMALL_SCAN_BLOCK) void rebin_small_scan_kernel(
+__global__ __launch_bounds__(BIN_BLOCK) void rebin_small_scan_kernel(
     int32_t ncell, const int32_t* __restrict__ cnt, const int32_t* __restrict__ fcnt,
     int32_t* __restrict__ offsets, int32_t* __restrict__ foff) {
-    __shared__ int32_t sh[SMALL_SCAN_BLOCK / 64 + 1];
-    const int32_t base = threadIdx.x * SMALL_SCAN_ITEMS;
-    int32_t va[SMALL_SCAN_ITEMS], vb[SMALL_SCAN_ITEMS];
-    int32_t sa = 0, sb = 0;
+    __shared__ int32_t sh[BIN_BLOCK / 64 + 1];
+    const int32_t k0 = blockIdx.x * BIN_BLOCK;
+    int32_t pa = 0, pb = 0;
+    {
+        // eight independent loads per round keep the earlier counts streaming in
+        constexpr int UR = 8;
+        int32_t qa[UR] = {0, 0, 0, 0, 0, 0, 0, 0}, qb[UR] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int32_t kb = 0; kb < k0; kb += BIN_BLOCK * UR) {
 #pragma unroll
-    for (int i = 0; i < SMALL_SCAN_ITEMS; ++i) {
-        const int32_t k = base + i;
-        va[i] = k < ncell ? cnt[k] : 0;
-        vb[i] = k < ncell ? fcnt[k] : 0;
-        sa += va[i];
-        sb += vb[i];
-    }
-    int32_t ta, tb;
-    int32_t ea = wg_excl_scan<SMALL_SCAN_BLOCK>(sa, sh, ta);
-    int32_t eb = wg_excl_scan<SMALL_SCAN_BLOCK>(sb, sh, tb);
-#pragma unroll
-    for (int i = 0; i < SMALL_SCAN_ITEMS; ++i) {
-        const int32_t k = base + i;
-        if (k < ncell) {
-            offsets[k] = ea;
-            foff[k] = eb;
+            for (int u = 0; u < UR; ++u) {
+                const int32_t k = kb + u * BIN_BLOCK + threadIdx.x;
+                if (k < k0) {
+                    qa[u] += cnt[k];
+                    qb[u] += fcnt[k];
+                }
+            }
         }
-        ea += va[i];
-        eb += vb[i];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            pa += qa[u];
+            pb += qb[u];
+        }
     }
-    if (threadIdx.x == 0) {
-        offsets[ncell] = ta;
-        foff[ncell] = tb;
+    int32_t ta, tb, sa, sb;
+    (void)wg_excl_scan<BIN_BLOCK>(pa, sh, ta);
+    (void)wg_excl_scan<BIN_BLOCK>(pb, sh, tb);
+    const int32_t k = k0 + threadIdx.x;
+    const int32_t va = k < ncell ? cnt[k] : 0, vb = k < ncell ? fcnt[k] : 0;
+    const int32_t ea = wg_excl_scan<BIN_BLOCK>(va, sh, sa) + ta;
+    const int32_t eb = wg_excl_scan<BIN_BLOCK>(vb, sh, sb) + tb;
+    if (k < ncell) {
+        offsets[k] = ea;
+        foff[k] = eb;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        offsets[ncell] = ta + sa;
+        foff[ncell] = tb + sb;
     }
 }
 
@@ -497,17 +562,6 @@ struct Rec {
     T *dx, *dy, *dvx, *dvy, *dvz;
     uint32_t* dpid;
     int32_t *dkey, *perm;
-    __device__ __forceinline__ void store(int32_t d, int32_t k, int32_t p, T x, T y, T vx, T vy,
-                                          T vz, uint32_t pid) const {
-        dx[d] = x;
-        if (dy) dy[d] = y;
-        dvx[d] = vx;
-        dvy[d] = vy;
-        dvz[d] = vz;
-        dpid[d] = pid;
-        dkey[d] = k;
-        if (perm) perm[d] = p;
-    }
     __device__ __forceinline__ void copy(int32_t p, int32_t d, int32_t k) const {
         dx[d] = sx[p];
         if (sy) dy[d] = sy[p];
@@ -520,18 +574,19 @@ struct Rec {
     }
 };
 
-// grid: cell blocks (old cells push their near movers), then FAR_BLOCKS blocks for the far
-// arrivals.  Every block also clears a share of fcnt/fcur/farn for the next call.
+// grid: cell blocks (one group of G lanes per destination cell), then FAR_BLOCKS blocks
+// for the far arrivals.  Every block also clears a share of fcnt/fcur/farn for the next
+// call.
 template <typename T, int G>
-__global__ __launch_bounds__(BIN_BLOCK) void rebin_push_kernel(
+__global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_kernel(
     int32_t ncell, int32_t nx, int32_t ny, int64_t n, int64_t cap, int32_t cell_blocks,
-    const int32_t* __restrict__ src_off, const int32_t* __restrict__ key,
-    const int32_t* __restrict__ ncnt, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ src_off, const int32_t* __restrict__ bend,
+    const int32_t* __restrict__ bidx, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ foff, const int32_t* __restrict__ fkey,
     const int32_t* __restrict__ fsrc, int32_t* __restrict__ fcnt, int32_t* __restrict__ fcur,
     int32_t* __restrict__ farn, Rec<T> r) {
     constexpr int GROUPS = BIN_BLOCK / G;
-    __shared__ int32_t s_base[GROUPS][9];
+    __shared__ int32_t s_run[GROUPS][9][3];   // bucket start in bidx, length, far arrivals before
     for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i <= ncell;
          i += (int64_t)gridDim.x * BIN_BLOCK) {
         fcnt[i] = 0;
@@ -541,8 +596,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_push_kernel(
     const int64_t lim = min((int64_t)offsets[ncell], n);   // slots that exist in dst
     const int32_t fend = (int32_t)min((int64_t)foff[ncell], cap);
     if ((int32_t)blockIdx.x >= cell_blocks) {
-        const int32_t nf = fend;
-        for (int32_t i = (int32_t)(blockIdx.x - cell_blocks) * BIN_BLOCK + threadIdx.x; i < nf;
+        for (int32_t i = (int32_t)(blockIdx.x - cell_blocks) * BIN_BLOCK + threadIdx.x; i < fend;
              i += FAR_BLOCKS * BIN_BLOCK) {
             const int32_t k = fkey[i], p = fsrc[i];
             if (k < 0 || k >= ncell || p < 0 || p >= n) continue;   // only with bad src_off
@@ -553,7 +607,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_push_kernel(
                     const int32_t sx = kx - ex, sy = ky - ey;
                     if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) continue;
                     const int32_t c2 = sy * nx + sx;
-                    if (src_off[c2] < p) slot += ncnt[(int64_t)c2 * 9 + (ey + 1) * 3 + (ex + 1)];
+                    if (src_off[c2] < p) slot += bucket_len(bend, c2, (ey + 1) * 3 + (ex + 1));
                 }
             const int32_t f1 = min(foff[k + 1], fend);
             for (int32_t q = foff[k]; q < f1; ++q) slot += fsrc[q] < p ? 1 : 0;
@@ -562,83 +616,92 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_push_kernel(
         return;
     }
     const int grp = threadIdx.x / G, lg = threadIdx.x % G;
-    const int32_t cell = xcd_block((int32_t)blockIdx.x, cell_blocks) * GROUPS + grp;
-    const bool in = cell < ncell;
-    int32_t b = 0, e = 0, cx = 0, cy = 0;
+    const int32_t k = xcd_block((int32_t)blockIdx.x, cell_blocks) * GROUPS + grp;
+    const bool in = k < ncell;
+    int32_t kx = 0, ky = 0, base = 0;
     if (in) {
-        b = max(src_off[cell], 0);
-        e = (int32_t)min((int64_t)src_off[cell + 1], n);
-        cy = cell / nx;
-        cx = cell - cy * nx;
+        ky = k / nx;
+        kx = k - ky * nx;
+        base = offsets[k];
     }
-    // slot of the first particle of this cell in each neighbour: the destination start,
-    // plus the runs of neighbour old cells before this one, plus the far arrivals with a
-    // smaller source index
-    for (int d = lg; d < 9; d += G) {
-        int32_t base = 0;
-        const int32_t kx = cx + d % 3 - 1, ky = cy + d / 3 - 1;
-        if (in && kx >= 0 && kx < nx && ky >= 0 && ky < ny) {
-            const int32_t k = ky * nx + kx;
-            base = offsets[k];
-            for (int ey = -1; ey <= 1; ++ey)
-                for (int ex = -1; ex <= 1; ++ex) {
-                    const int32_t sx = kx - ex, sy = ky - ey;
-                    if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) continue;
-                    const int32_t c2 = sy * nx + sx;
-                    if (c2 < cell) base += ncnt[(int64_t)c2 * 9 + (ey + 1) * 3 + (ex + 1)];
-                }
+    // the nine buckets in the order of their old cells (rows ky-1, ky, ky+1; columns
+    // kx-1, kx, kx+1): that is the order of source indices
+    for (int q = lg; q < 9; q += G) {
+        int32_t st = 0, len = 0, fb = 0;
+        const int32_t sy = ky - 1 + q / 3, sx = kx - 1 + q % 3;
+        if (in && sx >= 0 && sx < nx && sy >= 0 && sy < ny) {
+            const int32_t c2 = sy * nx + sx;
+            const int d = (ky - sy + 1) * 3 + (kx - sx + 1);
+            const int32_t* e2 = bend + (int64_t)c2 * 9;
+            const int32_t b0 = d > 0 ? e2[d - 1] : 0;
+            const int32_t s0 = max(src_off[c2], 0);
+            st = s0 + b0;
+            len = e2[d] - b0;
             const int32_t f1 = min(foff[k + 1], fend);
-            for (int32_t q = foff[k]; q < f1; ++q) base += fsrc[q] < b ? 1 : 0;
+            for (int32_t f = foff[k]; f < f1; ++f) fb += fsrc[f] < s0 ? 1 : 0;
         }
-        s_base[grp][d] = base;
+        s_run[grp][q][0] = st;
+        s_run[grp][q][1] = len;
+        s_run[grp][q][2] = fb;
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int gl = lane - lg;
-    const uint64_t gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << gl);
-    const uint64_t below = (1ull << lane) - 1ull;
-    int32_t run[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    int32_t sb[9];
+    int32_t rs[10], rst[9], rfb[9];
+    rs[0] = 0;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) sb[i] = s_base[grp][i];
-    // KR sub-chunks of G consecutive particles per round: all their loads first, then
-    // the ranks (sub-chunks in source order, lanes in source order) and the stores
-    constexpr int KR = 4;
-    for (int32_t j0 = b; j0 < e; j0 += G * KR) {
-        int32_t kk[KR];
-        T rx[KR], ry[KR], rvx[KR], rvy[KR], rvz[KR];
-        uint32_t rpid[KR];
+    for (int q = 0; q < 9; ++q) {
+        rst[q] = s_run[grp][q][0];
+        rs[q + 1] = rs[q] + s_run[grp][q][1];
+        rfb[q] = s_run[grp][q][2];
+    }
+    const int32_t nk = rs[9];
+    // position q of the concatenated buckets -> source index, U per lane per round
+    constexpr int U = 4;
+    for (int32_t q0 = 0; q0 < nk; q0 += G * U) {
+        int32_t src[U], dst[U];
 #pragma unroll
-        for (int u = 0; u < KR; ++u) {
-            const int32_t j = j0 + u * G + lg;
-            kk[u] = -1;
-            rx[u] = ry[u] = rvx[u] = rvy[u] = rvz[u] = (T)0;
-            rpid[u] = 0;
-            if (j < e) {
-                kk[u] = key[j];
+        for (int u = 0; u < U; ++u) {
+            const int32_t q = q0 + u * G + lg;
+            src[u] = -1;
+            dst[u] = -1;
+            if (q < nk) {
+                int32_t st = rst[0] - rs[0], fb = rfb[0];
+#pragma unroll
+                for (int t = 1; t < 9; ++t)
+                    if (q >= rs[t]) {
+                        st = rst[t] - rs[t];
+                        fb = rfb[t];
+                    }
+                src[u] = bidx[st + q];
+                dst[u] = base + q + fb;
+            }
+        }
+        T rx[U], ry[U], rvx[U], rvy[U], rvz[U];
+        uint32_t rp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (src[u] >= 0) {
+                const int32_t j = src[u];
                 rx[u] = r.sx[j];
-                if (r.sy) ry[u] = r.sy[j];
+                ry[u] = r.sy ? r.sy[j] : (T)0;
                 rvx[u] = r.svx[j];
                 rvy[u] = r.svy[j];
                 rvz[u] = r.svz[j];
-                rpid[u] = r.spid[j];
+                rp[u] = r.spid[j];
             }
         }
 #pragma unroll
-        for (int u = 0; u < KR; ++u) {
-            const int32_t j = j0 + u * G + lg;
-            const int32_t k = kk[u];
-            int d = -1;
-            if (k >= 0 && k < ncell) d = near_dir(k, cx, cy, nx);
-            int32_t slot = 0;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const uint64_t m = __ballot(d == i) & gmask;
-                if (d == i) slot = sb[i] + run[i] + __popcll(m & below);
-                run[i] += __popcll(m);
+        for (int u = 0; u < U; ++u) {
+            const int32_t d = dst[u];
+            if (src[u] >= 0 && d >= 0 && d < lim) {
+                r.dx[d] = rx[u];
+                if (r.dy) r.dy[d] = ry[u];
+                r.dvx[d] = rvx[u];
+                r.dvy[d] = rvy[u];
+                r.dvz[d] = rvz[u];
+                r.dpid[d] = rp[u];
+                r.dkey[d] = k;
+                if (r.perm) r.perm[d] = src[u];
             }
-            if (d >= 0 && slot >= 0 && slot < lim)
-                r.store(slot, k, j, rx[u], ry[u], rvx[u], rvy[u], rvz[u], rpid[u]);
         }
     }
 }
@@ -652,12 +715,12 @@ static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_
     const int32_t cblocks_count = (int32_t)(((int64_t)nc * G + BIN_BLOCK - 1) / BIN_BLOCK);
     hipLaunchKernelGGL((rebin_count_kernel<G>), dim3(cblocks_count + FAR_BLOCKS), dim3(BIN_BLOCK), 0,
                        s, nc, nx, n, cap, cblocks_count, src_off, (const int32_t*)src->key, c->ncnt,
-                       c->ccnt, c->farn, c->cmask, c->errcount);
+                       c->bidx, c->ccnt, c->farn, c->cmask, c->errcount);
     hipLaunchKernelGGL(rebin_dest_kernel, dim3((nc + BIN_BLOCK - 1) / BIN_BLOCK), dim3(BIN_BLOCK), 0,
                        s, nc, nx, ny, (const int32_t*)c->ncnt, (const int32_t*)c->ccnt, c->cnt);
     if (nc <= SMALL_SCAN_CELLS) {
-        hipLaunchKernelGGL(rebin_small_scan_kernel, dim3(1), dim3(SMALL_SCAN_BLOCK), 0, s, nc,
-                           (const int32_t*)c->cnt, (const int32_t*)c->ccnt, offsets, c->coff);
+        hipLaunchKernelGGL(rebin_small_scan_kernel, dim3((nc + BIN_BLOCK - 1) / BIN_BLOCK), dim3(BIN_BLOCK),
+                           0, s, nc, (const int32_t*)c->cnt, (const int32_t*)c->ccnt, offsets, c->coff);
     } else {
         const int32_t nblocks = (nc + SCAN_TILE - 1) / SCAN_TILE;
         hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt,
@@ -674,17 +737,17 @@ static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_
              (T*)dst->x,        two_d ? (T*)dst->y : nullptr,        (T*)dst->vx,
              (T*)dst->vy,       (T*)dst->vz,                         dst->pid,
              dst->key,          perm};
-    const int32_t cblocks_push = (nc + BIN_BLOCK / G - 1) / (BIN_BLOCK / G);
-    hipLaunchKernelGGL((rebin_push_kernel<T, G>), dim3(cblocks_push + FAR_BLOCKS), dim3(BIN_BLOCK), 0,
-                       s, nc, nx, ny, n, cap, cblocks_push, src_off, (const int32_t*)src->key,
-                       (const int32_t*)c->ncnt, (const int32_t*)offsets, (const int32_t*)c->coff,
+    const int32_t cblocks_gather = (nc + BIN_BLOCK / G - 1) / (BIN_BLOCK / G);
+    hipLaunchKernelGGL((rebin_gather_kernel<T, G>), dim3(cblocks_gather + FAR_BLOCKS), dim3(BIN_BLOCK),
+                       0, s, nc, nx, ny, n, cap, cblocks_gather, src_off, (const int32_t*)c->ncnt,
+                       (const int32_t*)c->bidx, (const int32_t*)offsets, (const int32_t*)c->coff,
                        (const int32_t*)c->cwave, (const int32_t*)c->gidx, c->ccnt, c->ccur, c->farn, r);
 }
 
 template <typename T>
 static void rebin_dispatch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
                            fp_particles* dst, int32_t* offsets, int32_t* perm, hipStream_t s) {
-    switch (lanes_per_cell(c, src->n)) {
+    switch (lanes_per_cell(c, src->n, FILL_8)) {
         case 4: rebin_launch<T, 4>(c, src, src_off, dst, offsets, perm, s); break;
         case 8: rebin_launch<T, 8>(c, src, src_off, dst, offsets, perm, s); break;
         case 16: rebin_launch<T, 16>(c, src, src_off, dst, offsets, perm, s); break;

@@ -31,7 +31,9 @@ struct fp_ctx {
     uint64_t* cmask = nullptr;   // [capacity] contribution: lane mask
     int32_t* gidx = nullptr;     // [capacity] slot list for cells too large for LDS
     int32_t* blocksum = nullptr; // scan partials
-    int32_t* ncnt = nullptr;     // [ncell*9] re-sort: particles of each cell per neighbour direction
+    int32_t* ncnt = nullptr;     // [ncell*9] re-sort: bucket ends per old cell and direction
+    int32_t* bidx = nullptr;     // [capacity] re-sort: source indices bucketed by direction;
+                                 // step: per-cell lists of the flights left to flight_rest
     int32_t* farn = nullptr;     // [1] re-sort: length of the list of particles that moved far
     int32_t* pend = nullptr;     // [ncell] step: flights left for flight_rest_kernel per cell
     unsigned long long* errcount = nullptr;  // invalid keys
@@ -114,8 +116,10 @@ __device__ __forceinline__ int32_t axis_cell(double pos, double origin, double i
 // ---- cross-lane sums inside aligned groups of G lanes (result in every lane) -----------
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    // every source lane of these row patterns exists, so bound_ctrl changes no value; it
+    // lets the compiler drop the copy of the unused "old" operand
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -144,7 +148,7 @@ __device__ __forceinline__ int32_t xcd_block(int32_t bid, int32_t nblocks) {
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 
 template <int G>
@@ -159,14 +163,20 @@ __device__ __forceinline__ int group_sum_i(int v) {
 }
 
 // ---- host-side launch shape of the per-cell kernels -------------------------------------
-// lanes per cell from the mean occupancy: about 8 particles per lane, 4..64 lanes
-inline int lanes_per_cell(const fp_ctx* c, int64_t n) {
+// Lanes per cell: about 8 particles per lane from the mean occupancy, and at least enough
+// lanes that the grid holds min_threads work-items (small grids would leave most SIMDs
+// idle); 4..64 lanes.  cfg.lanes > 0 overrides both.
+inline int lanes_per_cell(const fp_ctx* c, int64_t n, int64_t min_threads = 0) {
     if (c->cfg.lanes > 0) return c->cfg.lanes;
     const double avg = c->ncell > 0 ? (double)n / (double)c->ncell : 0.0;
     int g = 4;
     while (g < 64 && (double)g * 8.0 < avg * 1.25) g *= 2;
+    while (g < 64 && (int64_t)c->ncell * g < min_threads) g *= 2;
     return g;
 }
+// grid sizes below which the per-cell kernels widen their groups (about four, resp. eight,
+// resident waves on each of the 1024 SIMDs)
+constexpr int64_t FILL_4 = 1024 * 4 * 64, FILL_8 = 1024 * 8 * 64;
 
 // ---- launchers implemented in the kernel files -------------------------------------------
 int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* offsets,

@@ -6,12 +6,15 @@
 // cells re-read the rest (L2-resident).  All products and sums are FP64: on CDNA4 a
 // double FMA issues at the same rate as a single-precision one (no packed FP32 here),
 // so FP64 accumulation costs nothing over FP32 and needs no compensation.  Cross-lane
-// sums use DPP inside the group, in a fixed order (deterministic).
+// sums: the mean by DPP inside the group, the 26 monomial sums through LDS (lane v adds
+// the partials of value v in lane order); fixed orders, so results are deterministic.
 #include "fp_internal.h"
 
 namespace fpg {
 
 constexpr int MOM_BLOCK = 256;
+constexpr int NV = 26;   // accumulated monomials: P (6), T (10), R (6), W (3), H
+constexpr int MR = 13;   // values per LDS reduction round
 constexpr int MOM_K = 8;
 
 template <typename T, int G, int K>
@@ -85,31 +88,50 @@ __global__ __launch_bounds__(MOM_BLOCK) void moments_kernel(
     for (int32_t j = lg + K * G; j < n; j += G)
         accum((double)vx[b + j] - U0, (double)vy[b + j] - U1, (double)vz[b + j] - U2);
 
+    // cross-lane sums through LDS, MR values per round: every lane stores its partial sums
+    // (value-major, so consecutive lanes hit consecutive banks), then lane v of the group
+    // adds the G partials of value v in lane order.  Far fewer instructions than a DPP
+    // tree per value, and the finished values end up spread over the lanes.
+    double acc[NV];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) P[i] = group_sum<G>(P[i]);
+    for (int i = 0; i < 6; ++i) acc[i] = P[i];
 #pragma unroll
-    for (int i = 0; i < 10; ++i) Tm[i] = group_sum<G>(Tm[i]);
+    for (int i = 0; i < 10; ++i) acc[6 + i] = Tm[i];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) R[i] = group_sum<G>(R[i]);
+    for (int i = 0; i < 6; ++i) acc[16 + i] = R[i];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) W[i] = group_sum<G>(W[i]);
-    H = group_sum<G>(H);
-
-    if (in && lg == 0) {
+    for (int i = 0; i < 3; ++i) acc[22 + i] = W[i];
+    acc[25] = H;
+    constexpr int GROUPS = MOM_BLOCK / G;
+    __shared__ double red[MR][MOM_BLOCK + 1];   // +1: rows start on different banks
+    __shared__ double fin[GROUPS][NV];
+    const int grp = threadIdx.x / G;
+#pragma unroll
+    for (int r0 = 0; r0 < NV; r0 += MR) {
+#pragma unroll
+        for (int v = 0; v < MR; ++v)
+            if (r0 + v < NV) red[v][threadIdx.x] = acc[r0 + v];
+        __syncthreads();
+        for (int v = lg; v < MR && r0 + v < NV; v += G) {
+            double t = 0.0;
+            for (int i = 0; i < G; ++i) t += red[v][grp * G + i];
+            fin[grp][r0 + v] = t;
+        }
+        __syncthreads();
+    }
+    if (in) {
+        // the record, one entry per lane: N, U, theta, P, T, R, W, H (moments / N), pad
         double* o = mom + (int64_t)cell * MOM;
-        o[M_N] = (double)n;
-        o[M_U] = U0; o[M_U + 1] = U1; o[M_U + 2] = U2;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) o[M_P + i] = P[i] * inv_n;
-#pragma unroll
-        for (int i = 0; i < 10; ++i) o[M_T + i] = Tm[i] * inv_n;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) o[M_R + i] = R[i] * inv_n;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) o[M_W + i] = W[i] * inv_n;
-        o[M_H] = H * inv_n;
-        o[M_TH] = (P[0] * inv_n + P[3] * inv_n + P[5] * inv_n) / 3.0;
-        o[31] = 0.0;
+        for (int e = lg; e < MOM; e += G) {
+            double val;
+            if (e == M_N) val = (double)n;
+            else if (e < M_TH) val = e == M_U ? U0 : (e == M_U + 1 ? U1 : U2);
+            else if (e == M_TH)
+                val = (fin[grp][0] * inv_n + fin[grp][3] * inv_n + fin[grp][5] * inv_n) / 3.0;
+            else if (e < 31) val = fin[grp][e - M_P] * inv_n;
+            else val = 0.0;
+            o[e] = val;
+        }
     }
 }
 

@@ -273,7 +273,7 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
     const double* __restrict__ mom, const double* __restrict__ rec, T* __restrict__ px,
     T* __restrict__ py, T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
     const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step_arg, int move,
-    const uint32_t* __restrict__ stepp, int32_t* __restrict__ pend) {
+    const uint32_t* __restrict__ stepp, int32_t* __restrict__ pend, int32_t* __restrict__ plist) {
     const uint32_t step = stepp ? stepp[0] : step_arg;
     const int64_t gt = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
     const int32_t cell = (int32_t)(gt / G);
@@ -409,14 +409,18 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
     auto newv = [&](T c, int i) -> T {
         return __builtin_fma(c - cb[i], sc, q.U[i]);
     };
-    // a particle that may meet a wall or the body keeps key -1 and its new velocity; the
-    // per-cell count lets flight_rest_kernel find it
-    int32_t npend = 0;
+    // a particle that may meet a wall or the body keeps its new velocity and its index
+    // goes to the cell's list (plist[b ..], inside the cell's own range; a group ballot
+    // gives each one a distinct place); flight_rest_kernel flies the listed particles
+    const int lane = threadIdx.x & 63;
+    const uint64_t gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << (lane - lg));
+    const uint64_t below = (1ull << lane) - 1ull;
+    int32_t npend = 0;   // listed so far by the group (same in every lane still working)
     auto finish = [&](int32_t p, T v0, T v1, T v2) {
-        if (!finish_fast(p, v0, v1, v2)) {
-            pkey[p] = -1;
-            ++npend;
-        }
+        const bool done = finish_fast(p, v0, v1, v2);
+        const uint64_t m = __ballot(!done) & gmask;
+        if (!done) plist[b + npend + __popcll(m & below)] = p;
+        npend += __popcll(m);
     };
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -432,33 +436,32 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
         if (active) finish(p, newv(pvx[p], 0), newv(pvy[p], 1), newv(pvz[p], 2));
         else finish(p, pvx[p], pvy[p], pvz[p]);
     }
-    if (move) {
-        npend = group_sum_i<G>(npend);
-        if (in && lg == 0) pend[cell] = npend;
-    }
+    if (move && in && lg == 0) pend[cell] = npend;   // lane 0 takes part in every round
 }
 
-// the flights collide_kernel left: particles with key -1 in cells with pend > 0 fly from
+// the flights collide_kernel left: the particles listed for cells with pend > 0 fly from
 // their stored position with their stored (new) velocity, through walls / past the body
 template <typename T, int G, int GEOM>
 __global__ __launch_bounds__(ST_BLOCK) void flight_rest_kernel(
     fp_config g, int32_t ncell, const int32_t* __restrict__ offsets,
-    const int32_t* __restrict__ pend, T* __restrict__ px, T* __restrict__ py,
-    T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
+    const int32_t* __restrict__ pend, const int32_t* __restrict__ plist, T* __restrict__ px,
+    T* __restrict__ py, T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
     const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step_arg,
     const uint32_t* __restrict__ stepp) {
     const int64_t gt = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
     const int32_t cell = (int32_t)(gt / G);
     const int lg = (int)(gt % G);
-    if (cell >= ncell || pend[cell] == 0) return;
+    if (cell >= ncell) return;
+    const int32_t np = pend[cell];
+    if (lg >= np) return;
     const uint32_t step = stepp ? stepp[0] : step_arg;
     const bool f32 = sizeof(T) == 4;
     constexpr bool TWO_D = GEOM != FP_COUETTE1D;
     const Walls W = make_walls(g);
     const double inv_dx = 1.0 / g.dx, inv_dy = 1.0 / g.dy;
-    const int32_t b = offsets[cell], e = offsets[cell + 1];
-    for (int32_t p = b + lg; p < e; p += G) {
-        if (pkey[p] != -1) continue;
+    const int32_t b = offsets[cell];
+    for (int32_t i = lg; i < np; i += G) {
+        const int32_t p = plist[b + i];
         double pos[2] = {(double)px[p], TWO_D ? (double)py[p] : 0.0};
         double v[3] = {(double)pvx[p], (double)pvy[p], (double)pvz[p]};
         bool gone = false;
@@ -517,18 +520,19 @@ static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const
     const unsigned grid = (unsigned)((threads + ST_BLOCK - 1) / ST_BLOCK);
     hipLaunchKernelGGL((collide_kernel<T, G, ST_K, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
                        c->cfg, c->ncell, off, mom, rec, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy,
-                       (T*)p->vz, p->pid, p->key, step, move, stepp, c->pend);
+                       (T*)p->vz, p->pid, p->key, step, move, stepp, c->pend, c->bidx);
     if (move)
         hipLaunchKernelGGL((flight_rest_kernel<T, G, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
-                           c->cfg, c->ncell, off, (const int32_t*)c->pend, (T*)p->x, (T*)p->y,
-                           (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key, step, stepp);
+                           c->cfg, c->ncell, off, (const int32_t*)c->pend, (const int32_t*)c->bidx,
+                           (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
+                           step, stepp);
 }
 
 template <typename T, int GEOM>
 static void collide_dispatch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
                              const double* rec, uint32_t step, int move, const uint32_t* sp,
                              hipStream_t s) {
-    switch (lanes_per_cell(c, p->n)) {
+    switch (lanes_per_cell(c, p->n, FILL_4)) {
         case 4: collide_launch<T, 4, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
         case 8: collide_launch<T, 8, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
         case 16: collide_launch<T, 16, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;

@@ -1,8 +1,18 @@
-"""Condense a rocprofv3 kernel trace (``<prefix>_kernel_trace.csv``) into a short table:
-one line per kernel and launch grid (so the workloads of one run stay apart), with the
-number of dispatches, mean / min / max duration, VGPRs and LDS bytes per workgroup.
+"""Short text summaries of rocprofv3 output, for the profiles/ directory.
 
-    python -m paper_2606_15622_amd.prof_summary TRACE.csv [--title T] [--command C]
+    python -m paper_2606_15622_amd.prof_summary trace TRACE.csv [--title T] [--command C]
+        one line per kernel and launch grid of a --kernel-trace run: dispatches, mean /
+        min / max duration, VGPRs, LDS bytes per workgroup
+    python -m paper_2606_15622_amd.prof_summary copy
+        a plain device copy of 256 MiB (three times), the known-size reference for the
+        FETCH_SIZE / WRITE_SIZE counters
+    python -m paper_2606_15622_amd.prof_summary counters --fetch F.csv --write W.csv
+            --copy-fetch CF.csv --copy-write CW.csv --kernel REGEX --grid N
+            --source FILE [--source FILE ...] [--title T] [--command C]
+        HBM bytes per launch of the kernels matching REGEX at grid N (summed, e.g. the
+        two kernels of one entry point), each counter scaled by bytes / counter of the
+        reference copy; the listed sources are hashed so that a reader can tell whether
+        the kernel changed since
 """
 import argparse
 import csv
@@ -43,13 +53,91 @@ def summarize(path, title="", command=""):
     return "\n".join(out)
 
 
+COPY_BYTES = 256 * 1024 * 1024
+
+
+def copy_reference():
+    import torch
+    a = torch.ones(COPY_BYTES // 4, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied", COPY_BYTES >> 20, "MiB x 3")
+
+
+def _counter(path, name, kernel_re=None, grid=None):
+    """Per-dispatch values (KiB) of one counter, grouped by dispatch id."""
+    vals = defaultdict(float)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != name:
+                continue
+            if kernel_re and not re.search(kernel_re, r["Kernel_Name"]):
+                continue
+            if grid is not None and int(r["Grid_Size"]) != grid:
+                continue
+            vals[(r["Kernel_Name"], r["Dispatch_Id"])] += float(r["Counter_Value"])
+    return vals
+
+
+def counters(a):
+    import hashlib
+    cf = _counter(a.copy_fetch, "FETCH_SIZE")
+    cw = _counter(a.copy_write, "WRITE_SIZE")
+    # the copy is the dispatch with the largest values
+    ref_f = max(cf.values()) * 1024.0
+    ref_w = max(cw.values()) * 1024.0
+    kf = COPY_BYTES / ref_f
+    kw = COPY_BYTES / ref_w
+    out = []
+    if a.title:
+        out.append(f"# {a.title}")
+    if a.command:
+        out.append(f"# command: {a.command}")
+    out.append("# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (separate runs), KiB per dispatch;")
+    out.append("# scaled by the bytes a plain 256 MiB device copy moves per counted byte")
+    out.append(f"copy_factor_fetch: {kf:.4f}")
+    out.append(f"copy_factor_write: {kw:.4f}")
+    tot = 0.0
+    names = sorted({k[0] for k in _counter(a.fetch, "FETCH_SIZE", a.kernel, a.grid)})
+    for name in names:
+        fv = [v for k, v in _counter(a.fetch, "FETCH_SIZE", a.kernel, a.grid).items() if k[0] == name]
+        wv = [v for k, v in _counter(a.write, "WRITE_SIZE", a.kernel, a.grid).items() if k[0] == name]
+        f = sum(fv) / len(fv) * 1024.0 * kf
+        w = sum(wv) / len(wv) * 1024.0 * kw if wv else 0.0
+        short = re.sub(r"\(.*$", "", name)
+        out.append(f"kernel: {short} grid {a.grid} dispatches {len(fv)} fetch_bytes {f:.0f} write_bytes {w:.0f}")
+        tot += f + w
+    out.append(f"traffic_bytes_per_launch: {tot:.0f}")
+    for src in a.source:
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        out.append(f"source: {src} {digest}")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("trace")
-    ap.add_argument("--title", default="")
-    ap.add_argument("--command", default="")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("trace")
+    t.add_argument("--title", default="")
+    t.add_argument("--command", default="")
+    sub.add_parser("copy")
+    c = sub.add_parser("counters")
+    for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--kernel"):
+        c.add_argument(k, required=True)
+    c.add_argument("--grid", type=int, required=True)
+    c.add_argument("--source", action="append", default=[])
+    c.add_argument("--title", default="")
+    c.add_argument("--command", default="")
     a = ap.parse_args()
-    print(summarize(a.trace, a.title, a.command))
+    if a.cmd == "trace":
+        print(summarize(a.trace, a.title, a.command))
+    elif a.cmd == "copy":
+        copy_reference()
+    else:
+        print(counters(a))
 
 
 if __name__ == "__main__":
