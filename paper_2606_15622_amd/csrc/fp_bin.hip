@@ -281,8 +281,8 @@ static void gather_dispatch(fp_ctx* c, const fp_particles* src, fp_particles* ds
 // neighbours, and lists the source indices of each direction, in source order, inside
 // the old cell's own index range ("buckets": bidx, bucket ends in bend[cell][9]); every
 // other particle (moved farther, or after the grouped range) goes to a short far list.
-// The count of destination cell k is the sum of nine neighbour buckets plus its far
-// arrivals, and one scan gives the offsets.  Pass 2 (one group per DESTINATION cell)
+// Every old cell adds its bucket lengths to the counts of the destinations (nine integer
+// atomics), far arrivals add one each, and one scan gives the offsets.  Pass 2 (one group per DESTINATION cell)
 // concatenates its nine buckets in the order of their old cells -- which is the order of
 // source indices, i.e. the stable order -- inserting each far arrival before the buckets
 // whose old cell starts after it, and writes its slots contiguously (whole cache lines,
@@ -325,8 +325,9 @@ __device__ __forceinline__ int32_t wg_excl_scan(int32_t v, int32_t* sh, int32_t&
 }
 
 __device__ __forceinline__ void far_put(int32_t k, int32_t j, int64_t slot, int64_t cap,
-                                        uint64_t* flist, int32_t* fcnt) {
+                                        uint64_t* flist, int32_t* cnt, int32_t* fcnt) {
     if (slot < cap) flist[slot] = ((uint64_t)(uint32_t)k << 32) | (uint32_t)j;
+    atomicAdd(&cnt[k], 1);
     atomicAdd(&fcnt[k], 1);
 }
 
@@ -345,8 +346,8 @@ template <int G>
 __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     int32_t ncell, int32_t nx, int64_t n, int64_t cap, int32_t cell_blocks,
     const int32_t* __restrict__ src_off, const int32_t* __restrict__ key,
-    int32_t* __restrict__ bend, int32_t* __restrict__ bidx, int32_t* __restrict__ fcnt,
-    int32_t* __restrict__ farn, uint64_t* __restrict__ flist,
+    int32_t* __restrict__ bend, int32_t* __restrict__ bidx, int32_t* __restrict__ cnt,
+    int32_t* __restrict__ fcnt, int32_t* __restrict__ farn, uint64_t* __restrict__ flist,
     unsigned long long* __restrict__ errcount) {
     __shared__ int32_t sh[BIN_BLOCK / 64 + 1];
     __shared__ int32_t s_base;
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
             int32_t wbase = 0;
             if (lane == 0 && m) wbase = atomicAdd(farn, (int32_t)__popcll(m));
             wbase = __shfl(wbase, 0, 64);
-            if (far) far_put(k, (int32_t)j, (int64_t)wbase + __popcll(m & below), cap, flist, fcnt);
+            if (far) far_put(k, (int32_t)j, (int64_t)wbase + __popcll(m & below), cap, flist, cnt, fcnt);
         }
         return;
     }
@@ -422,6 +423,13 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
 #pragma unroll
             for (int i = 0; i < 9; ++i) bend[(int64_t)cell * 9 + i] = bst[i] + c9[i];
         }
+        // this cell's share of the destination counts (integer adds: order-free)
+        if (lg < 9 && c9[0] + c9[1] + c9[2] + c9[3] + c9[4] + c9[5] + c9[6] + c9[7] + c9[8] > 0) {
+            int32_t cnt_d = 0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) cnt_d = lg == i ? c9[i] : cnt_d;
+            if (cnt_d > 0) atomicAdd(&cnt[cell + (lg / 3 - 1) * nx + (lg % 3 - 1)], cnt_d);
+        }
         // second pass: source indices into the buckets, in source order (ballot ranks)
         const int gl = lane - lg;
         const uint64_t gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << gl);
@@ -459,74 +467,37 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     for (int32_t j = b + lg; j < e; j += G) {
         const int32_t k = key[j];
         if (k < 0 || k >= ncell || near_dir(k, cx, cy, nx) >= 0) continue;
-        far_put(k, j, slot++, cap, flist, fcnt);
+        far_put(k, j, slot++, cap, flist, cnt, fcnt);
     }
-}
-
-// particles arriving in cell k from its neighbours (and from far away)
-__device__ __forceinline__ int32_t dest_count(int32_t k, int32_t nx, int32_t ny,
-                                              const int32_t* __restrict__ bend,
-                                              const int32_t* __restrict__ fcnt) {
-    const int32_t ky = k / nx, kx = k - ky * nx;
-    int32_t sum = fcnt[k];
-#pragma unroll
-    for (int ey = -1; ey <= 1; ++ey)
-#pragma unroll
-        for (int ex = -1; ex <= 1; ++ex) {
-            const int32_t sx = kx - ex, sy = ky - ey;
-            if (sx >= 0 && sx < nx && sy >= 0 && sy < ny)
-                sum += bucket_len(bend, sy * nx + sx, (ey + 1) * 3 + (ex + 1));
-        }
-    return sum;
-}
-
-__global__ __launch_bounds__(BIN_BLOCK) void rebin_dest_kernel(int32_t ncell, int32_t nx,
-                                                                int32_t ny,
-                                                                const int32_t* __restrict__ bend,
-                                                                const int32_t* __restrict__ fcnt,
-                                                                int32_t* __restrict__ cnt) {
-    const int32_t k = blockIdx.x * BIN_BLOCK + threadIdx.x;
-    if (k < ncell) cnt[k] = dest_count(k, nx, ny, bend, fcnt);
 }
 
 // both exclusive scans for grids of up to SMALL_SCAN_CELLS cells in one launch: each
-// workgroup of BIN_BLOCK cells adds up all earlier counts itself (at most a few tens of
-// KB, coalesced) instead of waiting for a second pass
-constexpr int SMALL_SCAN_CELLS = 1 << 15;
+// workgroup of SSB cells adds up all earlier counts itself (at most a few tens of KB,
+// coalesced, one round of loads) instead of waiting for a second pass
+constexpr int SSB = 1024, SS_UR = 16;
+constexpr int SMALL_SCAN_CELLS = SSB * SS_UR;
 
-__global__ __launch_bounds__(BIN_BLOCK) void rebin_small_scan_kernel(
+__global__ __launch_bounds__(SSB) void rebin_small_scan_kernel(
     int32_t ncell, const int32_t* __restrict__ cnt, const int32_t* __restrict__ fcnt,
     int32_t* __restrict__ offsets, int32_t* __restrict__ foff) {
-    __shared__ int32_t sh[BIN_BLOCK / 64 + 1];
-    const int32_t k0 = blockIdx.x * BIN_BLOCK;
+    __shared__ int32_t sh[SSB / 64 + 1];
+    const int32_t k0 = blockIdx.x * SSB;
     int32_t pa = 0, pb = 0;
-    {
-        // eight independent loads per round keep the earlier counts streaming in
-        constexpr int UR = 8;
-        int32_t qa[UR] = {0, 0, 0, 0, 0, 0, 0, 0}, qb[UR] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int32_t kb = 0; kb < k0; kb += BIN_BLOCK * UR) {
 #pragma unroll
-            for (int u = 0; u < UR; ++u) {
-                const int32_t k = kb + u * BIN_BLOCK + threadIdx.x;
-                if (k < k0) {
-                    qa[u] += cnt[k];
-                    qb[u] += fcnt[k];
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < UR; ++u) {
-            pa += qa[u];
-            pb += qb[u];
+    for (int u = 0; u < SS_UR; ++u) {
+        const int32_t k = u * SSB + threadIdx.x;
+        if (k < k0) {
+            pa += cnt[k];
+            pb += fcnt[k];
         }
     }
     int32_t ta, tb, sa, sb;
-    (void)wg_excl_scan<BIN_BLOCK>(pa, sh, ta);
-    (void)wg_excl_scan<BIN_BLOCK>(pb, sh, tb);
+    (void)wg_excl_scan<SSB>(pa, sh, ta);
+    (void)wg_excl_scan<SSB>(pb, sh, tb);
     const int32_t k = k0 + threadIdx.x;
     const int32_t va = k < ncell ? cnt[k] : 0, vb = k < ncell ? fcnt[k] : 0;
-    const int32_t ea = wg_excl_scan<BIN_BLOCK>(va, sh, sa) + ta;
-    const int32_t eb = wg_excl_scan<BIN_BLOCK>(vb, sh, sb) + tb;
+    const int32_t ea = wg_excl_scan<SSB>(va, sh, sa) + ta;
+    const int32_t eb = wg_excl_scan<SSB>(vb, sh, sb) + tb;
     if (k < ncell) {
         offsets[k] = ea;
         foff[k] = eb;
@@ -583,12 +554,13 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_kernel(
     const int32_t* __restrict__ src_off, const int32_t* __restrict__ bend,
     const int32_t* __restrict__ bidx, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ foff, const int32_t* __restrict__ fkey,
-    const int32_t* __restrict__ fsrc, int32_t* __restrict__ fcnt, int32_t* __restrict__ fcur,
-    int32_t* __restrict__ farn, Rec<T> r) {
+    const int32_t* __restrict__ fsrc, int32_t* __restrict__ cnt, int32_t* __restrict__ fcnt,
+    int32_t* __restrict__ fcur, int32_t* __restrict__ farn, Rec<T> r) {
     constexpr int GROUPS = BIN_BLOCK / G;
     __shared__ int32_t s_run[GROUPS][9][3];   // bucket start in bidx, length, far arrivals before
     for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i <= ncell;
          i += (int64_t)gridDim.x * BIN_BLOCK) {
+        cnt[i] = 0;
         fcnt[i] = 0;
         fcur[i] = 0;
         if (i == 0) farn[0] = 0;
@@ -713,14 +685,14 @@ static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_
     const int64_t n = src->n, cap = c->cfg.capacity;
     const bool two_d = c->cfg.geometry != FP_COUETTE1D;
     const int32_t cblocks_count = (int32_t)(((int64_t)nc * G + BIN_BLOCK - 1) / BIN_BLOCK);
+    // cnt, ccnt (far counts), ccur and farn are zero on entry: the previous sort call left
+    // them so
     hipLaunchKernelGGL((rebin_count_kernel<G>), dim3(cblocks_count + FAR_BLOCKS), dim3(BIN_BLOCK), 0,
                        s, nc, nx, n, cap, cblocks_count, src_off, (const int32_t*)src->key, c->ncnt,
-                       c->bidx, c->ccnt, c->farn, c->cmask, c->errcount);
-    hipLaunchKernelGGL(rebin_dest_kernel, dim3((nc + BIN_BLOCK - 1) / BIN_BLOCK), dim3(BIN_BLOCK), 0,
-                       s, nc, nx, ny, (const int32_t*)c->ncnt, (const int32_t*)c->ccnt, c->cnt);
+                       c->bidx, c->cnt, c->ccnt, c->farn, c->cmask, c->errcount);
     if (nc <= SMALL_SCAN_CELLS) {
-        hipLaunchKernelGGL(rebin_small_scan_kernel, dim3((nc + BIN_BLOCK - 1) / BIN_BLOCK), dim3(BIN_BLOCK),
-                           0, s, nc, (const int32_t*)c->cnt, (const int32_t*)c->ccnt, offsets, c->coff);
+        hipLaunchKernelGGL(rebin_small_scan_kernel, dim3((nc + SSB - 1) / SSB), dim3(SSB), 0, s, nc,
+                           (const int32_t*)c->cnt, (const int32_t*)c->ccnt, offsets, c->coff);
     } else {
         const int32_t nblocks = (nc + SCAN_TILE - 1) / SCAN_TILE;
         hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt,
@@ -741,7 +713,8 @@ static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_
     hipLaunchKernelGGL((rebin_gather_kernel<T, G>), dim3(cblocks_gather + FAR_BLOCKS), dim3(BIN_BLOCK),
                        0, s, nc, nx, ny, n, cap, cblocks_gather, src_off, (const int32_t*)c->ncnt,
                        (const int32_t*)c->bidx, (const int32_t*)offsets, (const int32_t*)c->coff,
-                       (const int32_t*)c->cwave, (const int32_t*)c->gidx, c->ccnt, c->ccur, c->farn, r);
+                       (const int32_t*)c->cwave, (const int32_t*)c->gidx, c->cnt, c->ccnt, c->ccur,
+                       c->farn, r);
 }
 
 template <typename T>
