@@ -144,9 +144,11 @@ int fp_bin(fp_ctx* ctx, const fp_particles* src, fp_particles* dst, int32_t* off
  * per-cell direction counts, without global atomics; the others take a general path
  * that is slower per particle.  src_offsets and offsets must not alias (keep two
  * offsets arrays and alternate them); src_offsets must be non-decreasing with
- * src_offsets[0] >= 0 and src_offsets[ncell] <= src->n. */
+ * src_offsets[0] >= 0 and src_offsets[ncell] <= src->n.  mom (optional, may be NULL)
+ * receives the moment records of the sorted cells, as fp_moments of dst would compute
+ * them (up to the order of the sums), gathered in the same pass. */
 int fp_rebin(fp_ctx* ctx, const fp_particles* src, const int32_t* src_offsets,
-             fp_particles* dst, int32_t* offsets, int32_t* perm, hipStream_t s);
+             fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom, hipStream_t s);
 
 /* Central moments of every cell of particles sorted by cell (moments u^(p) entering
  * eq. system9x9 and Table matrix_system; layout mom above). */

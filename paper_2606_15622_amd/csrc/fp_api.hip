@@ -241,7 +241,8 @@ extern "C" int fp_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int
 }
 
 extern "C" int fp_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_offsets,
-                        fp_particles* dst, int32_t* offsets, int32_t* perm, hipStream_t s) {
+                        fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom,
+                        hipStream_t s) {
     if (!c || !offsets || !src_offsets || !particles_ok(c, src, true) || !dst)
         return set_err(c, FP_EINVAL, "fp_rebin: bad argument");
     if (src->n > 0 && (!dst->vx || !dst->vy || !dst->vz || !dst->pid || !dst->key || !dst->x ||
@@ -250,7 +251,7 @@ extern "C" int fp_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_o
     if (src->vx == dst->vx || src->x == dst->x || src->pid == dst->pid)
         return set_err(c, FP_EINVAL, "fp_rebin: src and dst alias");
     if (src_offsets == offsets) return set_err(c, FP_EINVAL, "fp_rebin: src_offsets and offsets alias");
-    return launch_rebin(c, src, src_offsets, dst, offsets, perm, s);
+    return launch_rebin(c, src, src_offsets, dst, offsets, perm, mom, s);
 }
 
 extern "C" int fp_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,

@@ -7,7 +7,7 @@
 // by source wave, which reproduces the order of a stable counting sort exactly,
 // expands them to source indices in LDS and gathers the particle records.  No float
 // atomics, no global radix passes; the result is deterministic.
-#include "fp_internal.h"
+#include "fp_mom_dev.h"
 
 namespace fpg {
 
@@ -678,9 +678,178 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_kernel(
     }
 }
 
+// The gather of one destination cell can also produce the cell's moments (the same
+// quantities fp_moments computes from the sorted particles): the group has just written
+// every particle of its cell.  In this form the group also places its own far arrivals
+// (no separate far blocks) and then reads its fresh slots back (L1/L2-resident) for the
+// two moment passes.
+constexpr int GM_U = 4;
+
+template <typename T, int G>
+__global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
+    int32_t ncell, int32_t nx, int32_t ny, int64_t n, int64_t cap,
+    const int32_t* __restrict__ src_off, const int32_t* __restrict__ bend,
+    const int32_t* __restrict__ bidx, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ foff, const int32_t* __restrict__ fsrc,
+    int32_t* __restrict__ cnt, int32_t* __restrict__ fcnt, int32_t* __restrict__ fcur,
+    int32_t* __restrict__ farn, Rec<T> r, double* __restrict__ mom) {
+    constexpr int GROUPS = BIN_BLOCK / G;
+    __shared__ int32_t s_run[GROUPS][9][3];
+    __shared__ int32_t s_pre[GROUPS][10];     // bucket starts in the cell's concatenation
+    __shared__ MomShared<BIN_BLOCK, G> sm;
+    for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i <= ncell;
+         i += (int64_t)gridDim.x * BIN_BLOCK) {
+        cnt[i] = 0;
+        fcnt[i] = 0;
+        fcur[i] = 0;
+        if (i == 0) farn[0] = 0;
+    }
+    const int64_t lim = min((int64_t)offsets[ncell], n);
+    const int32_t fend = (int32_t)min((int64_t)foff[ncell], cap);
+    const int grp = threadIdx.x / G, lg = threadIdx.x % G;
+    const int32_t k = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * GROUPS + grp;
+    const bool in = k < ncell;
+    int32_t kx = 0, ky = 0, base = 0, f0 = 0, f1 = 0;
+    if (in) {
+        ky = k / nx;
+        kx = k - ky * nx;
+        base = offsets[k];
+        f0 = min(foff[k], fend);
+        f1 = min(foff[k + 1], fend);
+    }
+    for (int q = lg; q < 9; q += G) {
+        int32_t st = 0, len = 0, fb = 0;
+        const int32_t sy = ky - 1 + q / 3, sx = kx - 1 + q % 3;
+        if (in && sx >= 0 && sx < nx && sy >= 0 && sy < ny) {
+            const int32_t c2 = sy * nx + sx;
+            const int d = (ky - sy + 1) * 3 + (kx - sx + 1);
+            const int32_t* e2 = bend + (int64_t)c2 * 9;
+            const int32_t b0 = d > 0 ? e2[d - 1] : 0;
+            const int32_t s0 = max(src_off[c2], 0);
+            st = s0 + b0;
+            len = e2[d] - b0;
+            for (int32_t f = f0; f < f1; ++f) fb += fsrc[f] < s0 ? 1 : 0;
+        }
+        s_run[grp][q][0] = st;
+        s_run[grp][q][1] = len;
+        s_run[grp][q][2] = fb;
+    }
+    __syncthreads();
+    if (lg == 0) {
+        int32_t acc = 0;
+        for (int q = 0; q < 9; ++q) {
+            s_pre[grp][q] = acc;
+            acc += s_run[grp][q][1];
+        }
+        s_pre[grp][9] = acc;
+    }
+    __syncthreads();
+    int32_t rs[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) rs[q] = s_pre[grp][q];
+    const int32_t nk = rs[9];
+    // bucket of position q: the number of bucket starts at or before q (the buckets are
+    // in order; empty ones share their start), its descriptor read back from LDS
+    auto lookup = [&](int32_t q, int32_t& j, int32_t& fb) __attribute__((always_inline)) {
+        int t = 0;
+#pragma unroll
+        for (int tt = 1; tt < 9; ++tt) t += q >= rs[tt] ? 1 : 0;
+        fb = s_run[grp][t][2];
+        j = bidx[s_run[grp][t][0] + q - s_pre[grp][t]];
+    };
+    // one round: U positions per lane, all loads first; velocities returned
+    auto round = [&](int32_t q0, T (&ox)[GM_U], T (&oy)[GM_U], T (&oz)[GM_U])
+                     __attribute__((always_inline)) {
+        int32_t src[GM_U], dst[GM_U];
+#pragma unroll
+        for (int u = 0; u < GM_U; ++u) {
+            const int32_t q = q0 + u * G + lg;
+            src[u] = -1;
+            dst[u] = -1;
+            if (q < nk) {
+                int32_t fb;
+                lookup(q, src[u], fb);
+                dst[u] = base + q + fb;
+            }
+        }
+        T rx[GM_U], ry[GM_U];
+        uint32_t rp[GM_U];
+#pragma unroll
+        for (int u = 0; u < GM_U; ++u) {
+            ox[u] = oy[u] = oz[u] = (T)0;
+            if (src[u] >= 0) {
+                const int32_t j = src[u];
+                rx[u] = r.sx[j];
+                ry[u] = r.sy ? r.sy[j] : (T)0;
+                ox[u] = r.svx[j];
+                oy[u] = r.svy[j];
+                oz[u] = r.svz[j];
+                rp[u] = r.spid[j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GM_U; ++u) {
+            const int32_t d = dst[u];
+            if (src[u] >= 0 && d >= 0 && d < lim) {
+                r.dx[d] = rx[u];
+                if (r.dy) r.dy[d] = ry[u];
+                r.dvx[d] = ox[u];
+                r.dvy[d] = oy[u];
+                r.dvz[d] = oz[u];
+                r.dpid[d] = rp[u];
+                r.dkey[d] = k;
+                if (r.perm) r.perm[d] = src[u];
+            }
+        }
+    };
+    for (int32_t q0 = 0; q0 < nk; q0 += G * GM_U) {
+        T tx[GM_U], ty[GM_U], tz[GM_U];
+        round(q0, tx, ty, tz);
+    }
+    // far arrivals of this cell, placed by counting
+    for (int32_t i = f0 + lg; i < f1; i += G) {
+        const int32_t p = fsrc[i];
+        if (p < 0 || p >= n) continue;   // only with bad src_off
+        int32_t slot = base;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int32_t sy = ky - 1 + q / 3, sx = kx - 1 + q % 3;
+            if (sx >= 0 && sx < nx && sy >= 0 && sy < ny && src_off[sy * nx + sx] < p)
+                slot += rs[q + 1] - rs[q];
+        }
+        for (int32_t f = f0; f < f1; ++f) slot += fsrc[f] < p ? 1 : 0;
+        if (slot >= 0 && slot < lim) r.copy(p, slot, k);
+    }
+    // moments of the cell from its sorted slots, in slot order per lane (deterministic:
+    // the far arrivals sit in the segment in arbitrary order, their slots do not); the
+    // barrier makes the group's writes visible to all of its lanes
+    __syncthreads();
+    const int32_t ncnt = in ? (int32_t)min((int64_t)nk + (f1 - f0), lim - base) : 0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int32_t q = lg; q < ncnt; q += G) {
+        s0 += (double)r.dvx[base + q];
+        s1 += (double)r.dvy[base + q];
+        s2 += (double)r.dvz[base + q];
+    }
+    s0 = group_sum<G>(s0);
+    s1 = group_sum<G>(s1);
+    s2 = group_sum<G>(s2);
+    const double inv_n = ncnt > 0 ? 1.0 / (double)ncnt : 0.0;
+    const double U0 = s0 * inv_n, U1 = s1 * inv_n, U2 = s2 * inv_n;
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int32_t q = lg; q < ncnt; q += G)
+        mom_accum((double)r.dvx[base + q] - U0, (double)r.dvy[base + q] - U1,
+                  (double)r.dvz[base + q] - U2, acc);
+    mom_finish<BIN_BLOCK, G>(sm, acc, grp, lg, in, ncnt, U0, U1, U2,
+                             mom + (int64_t)(in ? k : 0) * MOM);
+}
+
 template <typename T, int G>
 static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
-                         fp_particles* dst, int32_t* offsets, int32_t* perm, hipStream_t s) {
+                         fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom,
+                         hipStream_t s) {
     const int32_t nc = c->ncell, nx = c->cfg.nx, ny = c->cfg.ny;
     const int64_t n = src->n, cap = c->cfg.capacity;
     const bool two_d = c->cfg.geometry != FP_COUETTE1D;
@@ -710,6 +879,13 @@ static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_
              (T*)dst->vy,       (T*)dst->vz,                         dst->pid,
              dst->key,          perm};
     const int32_t cblocks_gather = (nc + BIN_BLOCK / G - 1) / (BIN_BLOCK / G);
+    if (mom) {
+        hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G>), dim3(cblocks_gather), dim3(BIN_BLOCK), 0, s,
+                           nc, nx, ny, n, cap, src_off, (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
+                           (const int32_t*)offsets, (const int32_t*)c->coff, (const int32_t*)c->gidx,
+                           c->cnt, c->ccnt, c->ccur, c->farn, r, mom);
+        return;
+    }
     hipLaunchKernelGGL((rebin_gather_kernel<T, G>), dim3(cblocks_gather + FAR_BLOCKS), dim3(BIN_BLOCK),
                        0, s, nc, nx, ny, n, cap, cblocks_gather, src_off, (const int32_t*)c->ncnt,
                        (const int32_t*)c->bidx, (const int32_t*)offsets, (const int32_t*)c->coff,
@@ -719,22 +895,23 @@ static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_
 
 template <typename T>
 static void rebin_dispatch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
-                           fp_particles* dst, int32_t* offsets, int32_t* perm, hipStream_t s) {
+                           fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom,
+                           hipStream_t s) {
     switch (lanes_per_cell(c, src->n, FILL_8)) {
-        case 4: rebin_launch<T, 4>(c, src, src_off, dst, offsets, perm, s); break;
-        case 8: rebin_launch<T, 8>(c, src, src_off, dst, offsets, perm, s); break;
-        case 16: rebin_launch<T, 16>(c, src, src_off, dst, offsets, perm, s); break;
-        case 32: rebin_launch<T, 32>(c, src, src_off, dst, offsets, perm, s); break;
-        default: rebin_launch<T, 64>(c, src, src_off, dst, offsets, perm, s); break;
+        case 4: rebin_launch<T, 4>(c, src, src_off, dst, offsets, perm, mom, s); break;
+        case 8: rebin_launch<T, 8>(c, src, src_off, dst, offsets, perm, mom, s); break;
+        case 16: rebin_launch<T, 16>(c, src, src_off, dst, offsets, perm, mom, s); break;
+        case 32: rebin_launch<T, 32>(c, src, src_off, dst, offsets, perm, mom, s); break;
+        default: rebin_launch<T, 64>(c, src, src_off, dst, offsets, perm, mom, s); break;
     }
 }
 
 int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_particles* dst,
-                 int32_t* offsets, int32_t* perm, hipStream_t s) {
+                 int32_t* offsets, int32_t* perm, double* mom, hipStream_t s) {
     if (c->cfg.precision == FP_F32)
-        rebin_dispatch<float>(c, src, src_off, dst, offsets, perm, s);
+        rebin_dispatch<float>(c, src, src_off, dst, offsets, perm, mom, s);
     else
-        rebin_dispatch<double>(c, src, src_off, dst, offsets, perm, s);
+        rebin_dispatch<double>(c, src, src_off, dst, offsets, perm, mom, s);
     return check_launch(c, "fp_rebin");
 }
 

@@ -182,7 +182,7 @@ constexpr int64_t FILL_4 = 1024 * 4 * 64, FILL_8 = 1024 * 8 * 64;
 int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* offsets,
                int32_t* perm, hipStream_t s);
 int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_particles* dst,
-                 int32_t* offsets, int32_t* perm, hipStream_t s);
+                 int32_t* offsets, int32_t* perm, double* mom, hipStream_t s);
 int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,
                    hipStream_t s);
 int launch_closure(fp_ctx* c, const double* mom, double* rec, int32_t* status, hipStream_t s);

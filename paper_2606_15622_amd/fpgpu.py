@@ -68,7 +68,7 @@ def load():
         L.fp_error_count.argtypes = [vp, vp]
         L.fp_error_count.restype = i64
         L.fp_bin.argtypes = [vp, P(FPParticles), P(FPParticles), vp, vp, vp]
-        L.fp_rebin.argtypes = [vp, P(FPParticles), vp, P(FPParticles), vp, vp, vp]
+        L.fp_rebin.argtypes = [vp, P(FPParticles), vp, P(FPParticles), vp, vp, vp, vp]
         L.fp_moments.argtypes = [vp, P(FPParticles), vp, vp, vp]
         L.fp_closure_solve.argtypes = [vp, vp, vp, vp, vp]
         L.fp_step.argtypes = [vp, P(FPParticles), vp, vp, vp, u64, u32, vp]
@@ -238,10 +238,11 @@ class Context:
         self._check(self.lib.fp_bin(self.h, C.byref(a), C.byref(b), _ptr(offsets), _ptr(perm),
                                     _stream(stream)), "fp_bin")
 
-    def rebin(self, src, src_offsets, dst, offsets, perm=None, stream=None):
+    def rebin(self, src, src_offsets, dst, offsets, perm=None, mom=None, stream=None):
         a, b = src.struct(), dst.struct()
         self._check(self.lib.fp_rebin(self.h, C.byref(a), _ptr(src_offsets), C.byref(b),
-                                      _ptr(offsets), _ptr(perm), _stream(stream)), "fp_rebin")
+                                      _ptr(offsets), _ptr(perm), _ptr(mom), _stream(stream)),
+                    "fp_rebin")
 
     def moments(self, p, offsets, mom, stream=None):
         a = p.struct()
@@ -385,20 +386,23 @@ class Simulation:
         """Cell start indices of the particles in a (after the last sort)."""
         return self.offs[0]
 
-    def sort(self, perm=None):
+    def sort(self, perm=None, mom=None):
         """a -> b sorted by key (fp_rebin from the previous grouping after the first
-        step, fp_bin before), then swap a and b; offsets describe the new a."""
+        step, fp_bin before), then swap a and b; offsets describe the new a.  With mom,
+        the moments of the sorted cells are written too (by the re-sort itself, or by
+        fp_moments after the first sort)."""
         if self.sorted:
-            self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1], perm)
+            self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1], perm, mom)
         else:
             self.ctx.bin(self.a, self.b, self.offs[1], perm)
         self.offs.reverse()
         self.a, self.b = self.b, self.a
+        if mom is not None and not self.sorted:
+            self.ctx.moments(self.a, self.offsets, mom)
         self.sorted = True
 
     def step(self, s, sample=False):
-        self.sort()
-        self.ctx.moments(self.a, self.offsets, self.mom)
+        self.sort(mom=self.mom)
         if sample:
             self.ctx.sample(self.mom, self.samp)
         self.ctx.closure_solve(self.mom, self.rec, self.status)
@@ -423,8 +427,7 @@ class GraphSimulation(Simulation):
 
     def _body(self, sample):
         for _ in range(2):
-            self.sort()
-            self.ctx.moments(self.a, self.offsets, self.mom)
+            self.sort(mom=self.mom)
             if sample:
                 self.ctx.sample(self.mom, self.samp)
             self.ctx.closure_solve(self.mom, self.rec, self.status)
@@ -490,8 +493,9 @@ class OpenSimulation:
         self.b.n = self.n_total
         # after the first step the live particles are grouped by their previous cells and
         # the injected ones follow them: the re-sort applies
+        fused = self.sorted
         if self.sorted:
-            self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1])
+            self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1], None, self.mom)
         else:
             self.ctx.bin(self.a, self.b, self.offs[1])
         self.offs.reverse()
@@ -499,7 +503,8 @@ class OpenSimulation:
         self.a, self.b = self.b, self.a
         live = int(self.offsets[-1])
         self.a.n = live
-        self.ctx.moments(self.a, self.offsets, self.mom)
+        if not fused:
+            self.ctx.moments(self.a, self.offsets, self.mom)
         if sample:
             self.ctx.sample(self.mom, self.samp)
         if closure is None:

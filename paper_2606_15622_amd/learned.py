@@ -144,8 +144,7 @@ class LearnedSimulation(F.Simulation):
         self.tol = (tol_abs, tol_rel)
 
     def step(self, s, sample=False):
-        self.sort()
-        self.ctx.moments(self.a, self.offsets, self.mom)
+        self.sort(mom=self.mom)
         if sample:
             self.ctx.sample(self.mom, self.samp)
         if self.net is not None:

@@ -7,12 +7,11 @@
         a plain device copy of 256 MiB (three times), the known-size reference for the
         FETCH_SIZE / WRITE_SIZE counters
     python -m paper_2606_15622_amd.prof_summary counters --fetch F.csv --write W.csv
-            --copy-fetch CF.csv --copy-write CW.csv --kernel REGEX --grid N
+            --copy-fetch CF.csv --copy-write CW.csv --match REGEX@GRID [--match ...]
             --source FILE [--source FILE ...] [--title T] [--command C]
-        HBM bytes per launch of the kernels matching REGEX at grid N (summed, e.g. the
-        two kernels of one entry point), each counter scaled by bytes / counter of the
-        reference copy; the listed sources are hashed so that a reader can tell whether
-        the kernel changed since
+        HBM bytes per launch of an entry point: the kernels matching each REGEX at its
+        grid, summed, each counter scaled by bytes / counter of the reference copy; the
+        listed sources are hashed so that a reader can tell whether a kernel changed since
 """
 import argparse
 import csv
@@ -100,15 +99,31 @@ def counters(a):
     out.append(f"copy_factor_fetch: {kf:.4f}")
     out.append(f"copy_factor_write: {kw:.4f}")
     tot = 0.0
-    names = sorted({k[0] for k in _counter(a.fetch, "FETCH_SIZE", a.kernel, a.grid)})
-    for name in names:
-        fv = [v for k, v in _counter(a.fetch, "FETCH_SIZE", a.kernel, a.grid).items() if k[0] == name]
-        wv = [v for k, v in _counter(a.write, "WRITE_SIZE", a.kernel, a.grid).items() if k[0] == name]
-        f = sum(fv) / len(fv) * 1024.0 * kf
-        w = sum(wv) / len(wv) * 1024.0 * kw if wv else 0.0
-        short = re.sub(r"\(.*$", "", name)
-        out.append(f"kernel: {short} grid {a.grid} dispatches {len(fv)} fetch_bytes {f:.0f} write_bytes {w:.0f}")
-        tot += f + w
+    pats = [(m.rsplit("@", 1)[0], int(m.rsplit("@", 1)[1])) for m in a.match]
+
+    def window(path, name):
+        # dispatches of one workload lie between the first dispatch of the first pattern
+        # and the last dispatch of the last one (other workloads may run the same kernels
+        # at the same grid, e.g. a grid-stride kernel)
+        lo = min(int(k[1]) for k in _counter(path, name, *pats[0]))
+        hi = max(int(k[1]) for k in _counter(path, name, *pats[-1]))
+        return lo, hi
+
+    fwin, wwin = window(a.fetch, "FETCH_SIZE"), window(a.write, "WRITE_SIZE")
+    for kre, grid in pats:
+        fd = {k: v for k, v in _counter(a.fetch, "FETCH_SIZE", kre, grid).items()
+              if fwin[0] <= int(k[1]) <= fwin[1]}
+        wd = {k: v for k, v in _counter(a.write, "WRITE_SIZE", kre, grid).items()
+              if wwin[0] <= int(k[1]) <= wwin[1]}
+        for name in sorted({k[0] for k in fd}):
+            fv = [v for k, v in fd.items() if k[0] == name]
+            wv = [v for k, v in wd.items() if k[0] == name]
+            f = sum(fv) / len(fv) * 1024.0 * kf
+            w = sum(wv) / len(wv) * 1024.0 * kw if wv else 0.0
+            short = re.sub(r"\(.*$", "", name)
+            out.append(f"kernel: {short} grid {grid} dispatches {len(fv)} fetch_bytes {f:.0f} "
+                       f"write_bytes {w:.0f}")
+            tot += f + w
     out.append(f"traffic_bytes_per_launch: {tot:.0f}")
     for src in a.source:
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -125,9 +140,10 @@ def main():
     t.add_argument("--command", default="")
     sub.add_parser("copy")
     c = sub.add_parser("counters")
-    for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--kernel"):
+    for k in ("--fetch", "--write", "--copy-fetch", "--copy-write"):
         c.add_argument(k, required=True)
-    c.add_argument("--grid", type=int, required=True)
+    c.add_argument("--match", action="append", required=True,
+                   help="REGEX@GRID: kernels of one launch of the entry point (repeatable)")
     c.add_argument("--source", action="append", default=[])
     c.add_argument("--title", default="")
     c.add_argument("--command", default="")

@@ -84,8 +84,7 @@ def _relaxation_rates(params=None, langevin=False, cells=4000, ppc=500, steps=12
         net.load(params)
     pxy, sx, taus = [], [], []
     for s in range(steps + 1):
-        sim.sort()
-        sim.ctx.moments(sim.a, sim.offsets, sim.mom)
+        sim.sort(mom=sim.mom)
         m = sim.mom
         th = m[:, 4]
         pxy.append(float((m[:, 6] / th).mean()))

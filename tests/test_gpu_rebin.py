@@ -34,7 +34,24 @@ def grouped_after_flight(w, state, step=3):
     return s, off0
 
 
+def moment_scale(o):
+    """Natural scale of every moment entry (theta^k for order 2k), as in the parity of
+    fp_moments."""
+    th = np.maximum(o[:, 4], 1e-300)
+    scale = np.ones(o.shape)
+    scale[:, 1:4] = np.sqrt(th)[:, None] + np.abs(o[:, 1:4])
+    scale[:, 4:11] = th[:, None]
+    scale[:, 11:21] = th[:, None] ** 1.5
+    scale[:, 21:27] = th[:, None] ** 2
+    scale[:, 27:30] = th[:, None] ** 2.5
+    scale[:, 30] = th ** 3
+    return scale
+
+
 def run_rebin(F, w, s, off0, expect_errors=0):
+    """fp_rebin twice without moments, then twice with the moment gather: the sort must
+    equal the oracle's bit for bit each time, and the moments match the oracle's moments
+    of the oracle-sorted cells (1e-10 of the natural scale, as for fp_moments)."""
     nc = I.ncells(w)
     n = s["x"].shape[0]
     ctx = F.Context(w, max(n, 1))
@@ -43,11 +60,14 @@ def run_rebin(F, w, s, off0, expect_errors=0):
     src_off = torch.from_numpy(np.ascontiguousarray(off0, dtype=np.int32)).cuda()
     off = torch.full((nc + 1,), -7, dtype=torch.int32, device="cuda")
     perm = torch.full((max(n, 1),), -7, dtype=torch.int32, device="cuda")
-    for rep in range(2):     # twice: the counters must be left clean by the first call
-        ctx.rebin(a, src_off, b, off, perm)
+    mom = torch.full((nc, 32), -7.0, dtype=torch.float64, device="cuda")
+    operm, ooff = O.bin_particles(nc, s["key"])
+    kept = int(ooff[-1])
+    srt = {k: np.asarray(s[k])[operm[:kept]] for k in s}
+    for rep in range(4):     # repeated: the counters must be left clean by every call
+        with_mom = rep >= 2
+        ctx.rebin(a, src_off, b, off, perm, mom if with_mom else None)
         torch.cuda.synchronize()
-        operm, ooff = O.bin_particles(nc, s["key"])
-        kept = int(ooff[-1])
         np.testing.assert_array_equal(off.cpu().numpy(), ooff)
         np.testing.assert_array_equal(perm.cpu().numpy()[:kept], operm[:kept])
         b.n = kept
@@ -55,9 +75,14 @@ def run_rebin(F, w, s, off0, expect_errors=0):
         for k in ("x", "y", "vx", "vy", "vz", "pid", "key"):
             if k == "y" and w["geometry"] == "couette1d":
                 continue
-            np.testing.assert_array_equal(out[k], np.asarray(s[k])[operm[:kept]], err_msg=k)
+            np.testing.assert_array_equal(out[k], srt[k], err_msg=k)
         b.n = n
-    assert ctx.error_count() == 2 * expect_errors
+        if with_mom and nc > 0:
+            o = O.moments(ooff, srt["vx"], srt["vy"], srt["vz"])
+            g = mom.cpu().numpy()
+            np.testing.assert_array_equal(g[:, 0], o[:, 0])
+            assert np.all(np.abs(g - o) <= 1e-10 * moment_scale(o))
+    assert ctx.error_count() == 4 * expect_errors
     return kept
 
 
