@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-scaled", action="store_true", help="skip the 2e7-particle cavity")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--scaled-steps", type=int, default=20)
+    ap.add_argument("--no-other", action="store_true", help="skip the Couette and cylinder lines")
+    ap.add_argument("--cylinder-steps", type=int, default=20)
     return ap.parse_args()
 
 
@@ -43,14 +45,14 @@ def parse():
 # operation must move at least, once each
 #   step (collide+move): read x y vx vy vz pid, write x y vx vy vz key = 48 B/particle;
 #                        per cell offsets 8 B, rec 128 B, U and T of mom 104 B
-#   moments:             read vx vy vz = 12 B/particle; per cell offsets 8 B + 256 B out
-#   sort:                read key x y vx vy vz pid 28 B, write the same 28 B = 56 B/particle;
-#                        per cell 8 B of old and 4 B of new offsets
+#   sort_moments:        the re-sort with the moment gather and the time-average sums in
+#                        the same pass: read key x y vx vy vz pid 28 B, write the same
+#                        28 B = 56 B/particle; per cell 8 B of old and 4 B of new offsets,
+#                        the 256 B moment record, 14 sums read and written (224 B)
 #   closure:             256 B in + 128 B + 4 B out per cell
-#   sample:              256 B of moments in, 128 B of sums read and written per cell
 def alg_bytes(kind, n, nc):
-    return {"step": 48 * n + 240 * nc, "moments": 12 * n + 264 * nc,
-            "sort": 56 * n + 12 * nc, "closure": 388 * nc, "sample": 512 * nc}[kind]
+    return {"step": 48 * n + 240 * nc, "sort_moments": 56 * n + 492 * nc,
+            "closure": 388 * nc}[kind]
 
 
 def gpu_hold(torch, ms):
@@ -66,19 +68,17 @@ def gpu_hold(torch, ms):
 
 
 def entry_times(torch, F, sim, s, steps=20):
-    """Per-entry-point durations inside the loop itself: `steps` eager steps (sort,
-    moments, sample, closure, collide + move, in the loop's order) are enqueued behind a
+    """Per-entry-point durations inside the loop itself: `steps` eager steps (re-sort with
+    moments and sums, closure, collide + move, in the loop's order) are enqueued behind a
     GPU hold, each entry point between two HIP events on the launch stream, so the events
     time back-to-back kernels with no host gaps.  Means in milliseconds."""
     ctx = sim.ctx
-    names = ("sort", "moments", "sample", "closure", "step")
+    names = ("sort_moments", "closure", "step")
     ev = {k: [] for k in names}
     torch.cuda.synchronize()
     gpu_hold(torch, 60.0)
     for i in range(steps):
-        calls = (("sort", lambda: sim.sort()),
-                 ("moments", lambda: ctx.moments(sim.a, sim.offsets, sim.mom)),
-                 ("sample", lambda: ctx.sample(sim.mom, sim.samp)),
+        calls = (("sort_moments", lambda: sim.sort(mom=sim.mom, samp=sim.samp)),
                  ("closure", lambda: ctx.closure_solve(sim.mom, sim.rec, sim.status)),
                  ("step", lambda: ctx.step(sim.a, sim.offsets, sim.mom, sim.rec, s + i,
                                            F.STEP_COLLIDE | F.STEP_MOVE)))
@@ -92,7 +92,7 @@ def entry_times(torch, F, sim, s, steps=20):
     return {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
 
 
-def run_workload(torch, F, I, w, steps, warmup, graph=True):
+def run_workload(torch, F, I, w, steps, warmup, graph=True, kernel_times=True):
     """Warm up eagerly, then time `steps` steps: replays of the step captured in a HIP
     graph (graph=True) or eager launches.  Returns timings and per-kernel durations."""
     state = I.maxwellian_state(w)
@@ -122,8 +122,8 @@ def run_workload(torch, F, I, w, steps, warmup, graph=True):
     t = time.perf_counter() - t0
     if graph:
         s = int(sim.step_ctr.cpu()[0])
-    # per-entry-point durations (graph-replayed repeats, HIP events)
-    ms = entry_times(torch, F, sim, s)
+    # per-entry-point durations (loop order, HIP events)
+    ms = entry_times(torch, F, sim, s) if kernel_times else {}
     kern = {}
     for k, v in ms.items():
         gbs = alg_bytes(k, n, nc) / (v * 1e-3) / 1e9
@@ -175,6 +175,42 @@ def cpu_baseline(I, w):
                       f"{platform.processor() or platform.machine()}, {t:.1f} s)"}
 
 
+def couette_line(torch, F, I, steps=1000):
+    """Configuration 1: the FP64 Couette channel, 100 cells x 100 particles, graph-replayed
+    steps (launch-bound at this size)."""
+    w = I.couette(kn=0.1, ncell=100, ppc=100, precision="f64")
+    res = run_workload(torch, F, I, w, steps, 20, graph=True, kernel_times=False)
+    return {"workload": "couette1d 100 cells x 100 particles, FP64, Kn 0.1",
+            "value": round(res["n"] * res["steps"] / res["t"], 1), "unit": "particle-steps/s",
+            "ms_per_step": round(res["t"] / res["steps"] * 1e3, 5),
+            "cell_closures_per_s": round(res["nc"] * res["steps"] / res["t"], 1)}
+
+
+def cylinder_line(torch, F, I, steps):
+    """Configuration 5: Mach 10 argon past the cylinder, 400 x 300 cut cells, about 1.8e7
+    particles, FP32, exact closure, open boundaries with inflow injection.  Eager steps
+    (the live particle count is read back once per step); warm-up steps first."""
+    w = I.cylinder(precision="f32", seed=3)
+    state = I.freestream_state(w)
+    sim = F.OpenSimulation(w, state)
+    del state
+    for s in range(10):
+        sim.step(s)
+    torch.cuda.synchronize()
+    n0 = sim.n_total
+    t0 = time.perf_counter()
+    live = 0
+    for s in range(10, 10 + steps):
+        sim.step(s, sample=True)
+        live += int(sim.offsets[-1])
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return {"workload": "cylinder2d 400x300 cut cells, Mach 10 argon, about 1.8e7 particles, FP32",
+            "value": round(live / t, 1), "unit": "particle-steps/s", "steps": steps,
+            "ms_per_step": round(t / steps * 1e3, 4), "particles_first": n0,
+            "cell_closures_per_s": round(sim.ctx.ncell * steps / t, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -190,13 +226,12 @@ def main():
 
     w = I.cavity(kn=args.kn, ncell=100, ppc=100, precision="f32", seed=1)
     res = run_workload(torch, F, I, w, args.steps, args.warmup, graph=True)
-    res_eager = run_workload(torch, F, I, w, min(args.steps, 50), 5, graph=False)
+    res_eager = run_workload(torch, F, I, w, min(args.steps, 50), 5, graph=False, kernel_times=False)
     n, nc = res["n"], res["nc"]
     ms_step = res["t"] / res["steps"] * 1e3
     pps = n * res["steps"] / res["t"]
     kern = res["kern"]
-    dominant = max((k for k in kern if k in ("step", "moments", "closure")),
-                   key=lambda k: kern[k]["ms"])   # single-kernel entry points
+    dominant = max(kern, key=lambda k: kern[k]["ms"])
     out = {
         "metric": "particle-steps/s (cubic-FP step, exact closure)",
         "value": round(pps, 1),
@@ -224,8 +259,12 @@ def main():
             "value": round(rs["n"] * rs["steps"] / rs["t"], 1), "unit": "particle-steps/s",
             "ms_per_step": round(rs["t"] / rs["steps"] * 1e3, 4), "kernels": rs["kern"],
             "roofline_step": roofline_of(rs, "step", "step_cavity448x448x100_counters.txt"),
-            "roofline_moments": roofline_of(rs, "moments", "moments_cavity448x448x100_counters.txt"),
+            "roofline_sort_moments": roofline_of(rs, "sort_moments",
+                                                 "sort_moments_cavity448x448x100_counters.txt"),
         }
+    if not args.no_other:
+        out["couette"] = couette_line(torch, F, I)
+        out["cylinder"] = cylinder_line(torch, F, I, args.cylinder_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(I, w)
     print(json.dumps(out))

@@ -68,6 +68,7 @@ enum fp_cell_status {
 #define FP_STEP_COLLIDE 1u   /* velocity update (eqs. update_vel, update_N) + conservation */
 #define FP_STEP_MOVE 2u      /* free flight (eq. update_pos), diffuse walls, new cell key */
 #define FP_STEP_KEYS 4u      /* only recompute cell keys from the stored positions */
+#define FP_STEP_ADVANCE 8u   /* fp_step_dev only: add 1 to *step_dev once the step is done */
 
 typedef struct fp_config {
     int32_t geometry;        /* fp_geometry */
@@ -146,9 +147,12 @@ int fp_bin(fp_ctx* ctx, const fp_particles* src, fp_particles* dst, int32_t* off
  * offsets arrays and alternate them); src_offsets must be non-decreasing with
  * src_offsets[0] >= 0 and src_offsets[ncell] <= src->n.  mom (optional, may be NULL)
  * receives the moment records of the sorted cells, as fp_moments of dst would compute
- * them (up to the order of the sums), gathered in the same pass. */
+ * them (up to the order of the sums), gathered in the same pass.  samp (optional, needs
+ * mom) then receives the time-average sums of those records exactly as fp_sample would
+ * add them. */
 int fp_rebin(fp_ctx* ctx, const fp_particles* src, const int32_t* src_offsets,
-             fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom, hipStream_t s);
+             fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom, double* samp,
+             hipStream_t s);
 
 /* Central moments of every cell of particles sorted by cell (moments u^(p) entering
  * eq. system9x9 and Table matrix_system; layout mom above). */
@@ -177,7 +181,10 @@ int fp_step(fp_ctx* ctx, fp_particles* p, const int32_t* offsets, const double* 
 
 /* fp_step with the step number read from device memory (*step_dev, one uint32) when the
  * kernels run, so that a whole step can be captured once in a HIP graph and replayed
- * for successive steps (advance the counter with fp_counter_add inside the graph). */
+ * for successive steps.  With FP_STEP_ADVANCE the step itself adds 1 to *step_dev after
+ * every kernel of the step has read it (with COLLIDE | MOVE the last kernel does it, so
+ * no launch is added); without it advance the counter with fp_counter_add.  step_dev
+ * must then be writable device memory that no other work uses during the step. */
 int fp_step_dev(fp_ctx* ctx, fp_particles* p, const int32_t* offsets, const double* mom,
                 const double* rec, const uint32_t* step_dev, uint32_t flags, hipStream_t s);
 /* *ctr += inc on the device, ordered on the stream (a kernel, no memset: capturable). */

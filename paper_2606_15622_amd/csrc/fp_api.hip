@@ -138,14 +138,15 @@ extern "C" int fp_init(const fp_config* cfg, fp_ctx** out) {
     bool ok = dalloc(&c->cnt, nc) && dalloc(&c->ccnt, nc) && dalloc(&c->coff, nc + 1) &&
               dalloc(&c->ccur, nc) && dalloc(&c->cwave, cap) && dalloc(&c->cmask, cap) &&
               dalloc(&c->gidx, cap) && dalloc(&c->blocksum, 2 * 8192) &&
-              dalloc(&c->errcount, 1) && dalloc(&c->ncnt, 9 * (nc - 1) + 1) && dalloc(&c->farn, 1) && dalloc(&c->bidx, cap) &&
-              dalloc(&c->pend, nc);
+              dalloc(&c->errcount, 1) && dalloc(&c->ncnt, 9 * (nc - 1) + 1) && dalloc(&c->farn, 1) &&
+              dalloc(&c->bidx, cap) && dalloc(&c->pend, nc) && dalloc(&c->stepc, 1);
     // the sort counters start at zero; every fp_bin / fp_rebin leaves them zero again
     if (ok) ok = hipMemset(c->errcount, 0, sizeof(unsigned long long)) == hipSuccess &&
                  hipMemset(c->cnt, 0, sizeof(int32_t) * nc) == hipSuccess &&
                  hipMemset(c->ccnt, 0, sizeof(int32_t) * nc) == hipSuccess &&
                  hipMemset(c->ccur, 0, sizeof(int32_t) * nc) == hipSuccess &&
-                 hipMemset(c->farn, 0, sizeof(int32_t)) == hipSuccess;
+                 hipMemset(c->farn, 0, sizeof(int32_t)) == hipSuccess &&
+                 hipMemset(c->stepc, 0, sizeof(uint32_t)) == hipSuccess;
     if (ok && cfg->geometry == FP_CYLINDER2D) {
         std::vector<double> vol, nvol;
         gas_volumes(*cfg, vol);
@@ -202,6 +203,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     (void)hipFree(c->ncnt);
     (void)hipFree(c->farn);
     (void)hipFree(c->pend);
+    (void)hipFree(c->stepc);
     (void)hipFree(c->bidx);
     (void)hipFree(c->vol);
     (void)hipFree(c->nvol);
@@ -242,16 +244,17 @@ extern "C" int fp_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int
 
 extern "C" int fp_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_offsets,
                         fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom,
-                        hipStream_t s) {
-    if (!c || !offsets || !src_offsets || !particles_ok(c, src, true) || !dst)
+                        double* samp, hipStream_t s) {
+    if (!c || !offsets || !src_offsets || !particles_ok(c, src, true) || !dst || (samp && !mom))
         return set_err(c, FP_EINVAL, "fp_rebin: bad argument");
+    if (samp && samp == mom) return set_err(c, FP_EINVAL, "fp_rebin: samp and mom alias");
     if (src->n > 0 && (!dst->vx || !dst->vy || !dst->vz || !dst->pid || !dst->key || !dst->x ||
                        (c->cfg.geometry != FP_COUETTE1D && !dst->y)))
         return set_err(c, FP_EINVAL, "fp_rebin: bad destination");
     if (src->vx == dst->vx || src->x == dst->x || src->pid == dst->pid)
         return set_err(c, FP_EINVAL, "fp_rebin: src and dst alias");
     if (src_offsets == offsets) return set_err(c, FP_EINVAL, "fp_rebin: src_offsets and offsets alias");
-    return launch_rebin(c, src, src_offsets, dst, offsets, perm, mom, s);
+    return launch_rebin(c, src, src_offsets, dst, offsets, perm, mom, samp, s);
 }
 
 extern "C" int fp_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,
@@ -283,7 +286,8 @@ extern "C" int fp_step(fp_ctx* c, fp_particles* p, const int32_t* offsets, const
 extern "C" int fp_step_dev(fp_ctx* c, fp_particles* p, const int32_t* offsets, const double* mom,
                            const double* rec, const uint32_t* step_dev, uint32_t flags,
                            hipStream_t s) {
-    if (!c || !step_dev || (flags & ~7u) || !flags) return set_err(c, FP_EINVAL, "fp_step_dev: bad argument");
+    if (!c || !step_dev || (flags & ~15u) || !(flags & 7u))
+        return set_err(c, FP_EINVAL, "fp_step_dev: bad argument");
     if (!particles_ok(c, p, (flags & (FP_STEP_MOVE | FP_STEP_KEYS)) != 0))
         return set_err(c, FP_EINVAL, "fp_step_dev: bad particles");
     if ((flags & FP_STEP_COLLIDE) && (!offsets || !mom || !rec))

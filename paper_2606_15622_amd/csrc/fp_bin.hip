@@ -8,6 +8,7 @@
 // expands them to source indices in LDS and gathers the particle records.  No float
 // atomics, no global radix passes; the result is deterministic.
 #include "fp_mom_dev.h"
+#include "fp_sample_dev.h"
 
 namespace fpg {
 
@@ -288,11 +289,33 @@ static void gather_dispatch(fp_ctx* c, const fp_particles* src, fp_particles* ds
 // whose old cell starts after it, and writes its slots contiguously (whole cache lines,
 // each written once).  The only global atomics are those of the far list.
 
-__device__ __forceinline__ int near_dir(int32_t k, int32_t cx, int32_t cy, int32_t nx) {
-    const int32_t ky = k / nx, kx = k - ky * nx;
-    const int32_t dx = kx - cx, dy = ky - cy;
-    if (dx < -1 || dx > 1 || dy < -1 || dy > 1) return -1;
+// direction 0..8 of key k among the 3 x 3 cells around the old cell (column cx, its row
+// starting at cell rs), -1 for any other cell; no division: k's row is told by comparing
+// k - rs with 0 and nx
+__device__ __forceinline__ int near_dir(int32_t k, int32_t rs, int32_t cx, int32_t nx) {
+    const int32_t rel = k - rs;
+    const int32_t dy = rel < 0 ? -1 : (rel >= nx ? 1 : 0);
+    const int32_t dx = rel - dy * nx - cx;
+    if (rel < -nx || rel >= 2 * nx || dx < -1 || dx > 1) return -1;
     return (dy + 1) * 3 + (dx + 1);
+}
+
+// inclusive prefix sum over the G consecutive lanes of a group (lane lg of it): steps
+// inside rows of 16 lanes by DPP row shifts (lanes before the row start read 0, lanes
+// before the group start are masked), then across rows by the row broadcasts
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, true);
+}
+template <int G>
+__device__ __forceinline__ uint32_t group_incl_scan(uint32_t x, int lg) {
+    if constexpr (G >= 2) { const uint32_t y = dpp_u<0x111>(x); x += (G >= 16 || lg >= 1) ? y : 0u; }
+    if constexpr (G >= 4) { const uint32_t y = dpp_u<0x112>(x); x += (G >= 16 || lg >= 2) ? y : 0u; }
+    if constexpr (G >= 8) { const uint32_t y = dpp_u<0x114>(x); x += (G >= 16 || lg >= 4) ? y : 0u; }
+    if constexpr (G >= 16) x += dpp_u<0x118>(x);
+    if constexpr (G >= 32) x += dpp_u<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    if constexpr (G >= 64) x += dpp_u<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
 }
 
 // exclusive prefix sum over a workgroup of BLOCK threads (wave shuffles, then the wave
@@ -342,6 +365,25 @@ __device__ __forceinline__ int32_t bucket_len(const int32_t* __restrict__ bend, 
 // (tail) on its length: a single counter hit once per particle would serialise.
 constexpr int FAR_BLOCKS = 64;
 
+// Order in which the gathers visit destination cells on a 2-D grid: column strips of
+// STRIP cells, each strip row by row (a narrower last strip takes the rest).  A
+// destination row reads the particles of the three source rows around it; in row-major
+// order those rows are a whole grid row apart and their cache lines are evicted from L2
+// between the reads, in strip order they are STRIP cells apart.  A bijection on
+// [0, nx*ny); the identity for grids no wider than one strip.
+constexpr int32_t STRIP = 32;
+__device__ __forceinline__ int32_t strip_cell(int32_t t, int32_t nx, int32_t ny) {
+    if (nx <= STRIP) return t;
+    const int32_t full = nx / STRIP, per = STRIP * ny;
+    const int32_t sidx = t / per;
+    if (sidx < full) {
+        const int32_t r = t - sidx * per;
+        return (r / STRIP) * nx + sidx * STRIP + r % STRIP;
+    }
+    const int32_t w = nx - full * STRIP, r = t - full * per;
+    return (r / w) * nx + full * STRIP + r % w;
+}
+
 template <int G>
 __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     int32_t ncell, int32_t nx, int64_t n, int64_t cap, int32_t cell_blocks,
@@ -351,7 +393,8 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     unsigned long long* __restrict__ errcount) {
     __shared__ int32_t sh[BIN_BLOCK / 64 + 1];
     __shared__ int32_t s_base;
-    const int lane = threadIdx.x & 63;
+    __shared__ int32_t s_next[BIN_BLOCK / G][9];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x / G;
     const uint64_t below = (1ull << lane) - 1ull;
     if ((int32_t)blockIdx.x >= cell_blocks) {
         // particles after the grouped range: all take the general path
@@ -381,13 +424,13 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     const int32_t cell = (int32_t)(gt / G);
     const int lg = (int)(gt % G);
     int c9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    int32_t nfar = 0, b = 0, e = 0, cx = 0, cy = 0;
+    int32_t nfar = 0, b = 0, e = 0, cx = 0, rs = 0;
     constexpr int KR = 4;
     if (cell < ncell) {
         b = max(src_off[cell], 0);
         e = (int32_t)min((int64_t)src_off[cell + 1], n);
-        cy = cell / nx;
-        cx = cell - cy * nx;
+        cx = cell % nx;
+        rs = cell - cx;
         for (int32_t j0 = b + lg; j0 < e; j0 += G * KR) {
             int32_t kk[KR];
 #pragma unroll
@@ -400,7 +443,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
                     atomicAdd(errcount, 1ull);
                     continue;
                 }
-                const int d = near_dir(k, cx, cy, nx);
+                const int d = near_dir(k, rs, cx, nx);
                 nfar += d < 0 ? 1 : 0;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) c9[i] += d == i ? 1 : 0;
@@ -423,17 +466,28 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
 #pragma unroll
             for (int i = 0; i < 9; ++i) bend[(int64_t)cell * 9 + i] = bst[i] + c9[i];
         }
-        // this cell's share of the destination counts (integer adds: order-free)
-        if (lg < 9 && c9[0] + c9[1] + c9[2] + c9[3] + c9[4] + c9[5] + c9[6] + c9[7] + c9[8] > 0) {
+        // this cell's share of the destination counts (integer adds: order-free); lane lg
+        // takes directions lg, lg + G, ... (groups may have fewer than 9 lanes)
+        for (int q = lg; q < 9; q += G) {
             int32_t cnt_d = 0;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) cnt_d = lg == i ? c9[i] : cnt_d;
-            if (cnt_d > 0) atomicAdd(&cnt[cell + (lg / 3 - 1) * nx + (lg % 3 - 1)], cnt_d);
+            for (int i = 0; i < 9; ++i) cnt_d = q == i ? c9[i] : cnt_d;
+            if (cnt_d > 0) atomicAdd(&cnt[cell + (q / 3 - 1) * nx + (q % 3 - 1)], cnt_d);
         }
-        // second pass: source indices into the buckets, in source order (ballot ranks)
-        const int gl = lane - lg;
-        const uint64_t gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << gl);
-        int32_t run[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        // second pass: source indices into the buckets, in source order.  Per round of
+        // G particles the rank of a particle among those of its direction is a group
+        // prefix sum of one-hot counters (three words of three 10-bit fields; at most
+        // G <= 64 per field); the next free position of each direction lives in LDS,
+        // advanced after every round by lane lg for directions lg, lg + G, ... (LDS
+        // operations of one wave are done in order, so the round's reads see the old
+        // value)
+        for (int q = lg; q < 9; q += G) {
+            int32_t bv = 0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) bv = q == i ? bst[i] : bv;
+            s_next[grp][q] = bv;
+        }
+        const int last = lane - lg + G - 1;
         for (int32_t j0 = b; j0 < e; j0 += G * KR) {
             int32_t kk[KR];
 #pragma unroll
@@ -443,17 +497,26 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
             }
 #pragma unroll
             for (int u = 0; u < KR; ++u) {
+                if (j0 + u * G >= e) break;   // group-uniform
                 const int32_t k = kk[u];
                 int d = -1;
-                if (k >= 0 && k < ncell) d = near_dir(k, cx, cy, nx);
-                int32_t pos = 0;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const uint64_t m = __ballot(d == i) & gmask;
-                    if (d == i) pos = bst[i] + run[i] + __popcll(m & below);
-                    run[i] += __popcll(m);
+                if (k >= 0 && k < ncell) d = near_dir(k, rs, cx, nx);
+                const int dw = d < 0 ? 3 : d / 3, dsh = 10 * (d - 3 * dw);
+                const uint32_t w0 = dw == 0 ? 1u << dsh : 0u, w1 = dw == 1 ? 1u << dsh : 0u,
+                               w2 = dw == 2 ? 1u << dsh : 0u;
+                const uint32_t i0 = group_incl_scan<G>(w0, lg), i1 = group_incl_scan<G>(w1, lg),
+                               i2 = group_incl_scan<G>(w2, lg);
+                if (d >= 0) {
+                    const uint32_t ex = dw == 0 ? i0 - w0 : (dw == 1 ? i1 - w1 : i2 - w2);
+                    bidx[b + s_next[grp][d] + (int32_t)((ex >> dsh) & 1023u)] = j0 + u * G + lg;
                 }
-                if (d >= 0) bidx[b + pos] = j0 + u * G + lg;
+                const uint32_t t0 = __shfl(i0, last, 64), t1 = __shfl(i1, last, 64),
+                               t2 = __shfl(i2, last, 64);
+                for (int q = lg; q < 9; q += G) {
+                    const int tw = q / 3;
+                    const uint32_t tv = tw == 0 ? t0 : (tw == 1 ? t1 : t2);
+                    s_next[grp][q] += (int32_t)((tv >> (10 * (q - 3 * tw))) & 1023u);
+                }
             }
         }
     }
@@ -466,7 +529,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     int64_t slot = (int64_t)s_base + pre;
     for (int32_t j = b + lg; j < e; j += G) {
         const int32_t k = key[j];
-        if (k < 0 || k >= ncell || near_dir(k, cx, cy, nx) >= 0) continue;
+        if (k < 0 || k >= ncell || near_dir(k, rs, cx, nx) >= 0) continue;
         far_put(k, j, slot++, cap, flist, cnt, fcnt);
     }
 }
@@ -477,10 +540,16 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
 constexpr int SSB = 1024, SS_UR = 16;
 constexpr int SMALL_SCAN_CELLS = SSB * SS_UR;
 
+// It also splits the far list into per-destination segments for its own cells (every
+// workgroup reads the whole list and keeps the entries bound for its range; the slot
+// inside a segment comes from an LDS counter, so the order inside a segment is
+// arbitrary): no separate far-placement launch on small grids.
 __global__ __launch_bounds__(SSB) void rebin_small_scan_kernel(
-    int32_t ncell, const int32_t* __restrict__ cnt, const int32_t* __restrict__ fcnt,
-    int32_t* __restrict__ offsets, int32_t* __restrict__ foff) {
+    int32_t ncell, int64_t cap, const int32_t* __restrict__ cnt, const int32_t* __restrict__ fcnt,
+    int32_t* __restrict__ offsets, int32_t* __restrict__ foff, const int32_t* __restrict__ farn,
+    const uint64_t* __restrict__ flist, int32_t* __restrict__ fkey, int32_t* __restrict__ fsrc) {
     __shared__ int32_t sh[SSB / 64 + 1];
+    __shared__ int32_t s_foff[SSB], s_cur[SSB];
     const int32_t k0 = blockIdx.x * SSB;
     int32_t pa = 0, pb = 0;
 #pragma unroll
@@ -505,6 +574,21 @@ __global__ __launch_bounds__(SSB) void rebin_small_scan_kernel(
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         offsets[ncell] = ta + sa;
         foff[ncell] = tb + sb;
+    }
+    if (sb == 0) return;    // no far arrivals in this range (block-uniform)
+    s_foff[threadIdx.x] = eb;
+    s_cur[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t nf = min((int64_t)farn[0], cap);
+    for (int64_t i = threadIdx.x; i < nf; i += SSB) {
+        const uint64_t v = flist[i];
+        const int32_t kf = (int32_t)(v >> 32) - k0;
+        if (kf < 0 || kf >= SSB) continue;
+        const int32_t slot = s_foff[kf] + atomicAdd(&s_cur[kf], 1);
+        if (slot < cap) {
+            fkey[slot] = kf + k0;
+            fsrc[slot] = (int32_t)(uint32_t)v;
+        }
     }
 }
 
@@ -588,8 +672,9 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_kernel(
         return;
     }
     const int grp = threadIdx.x / G, lg = threadIdx.x % G;
-    const int32_t k = xcd_block((int32_t)blockIdx.x, cell_blocks) * GROUPS + grp;
-    const bool in = k < ncell;
+    const int32_t ord = xcd_block((int32_t)blockIdx.x, cell_blocks) * GROUPS + grp;
+    const bool in = ord < ncell;
+    const int32_t k = in ? strip_cell(ord, nx, ny) : ord;
     int32_t kx = 0, ky = 0, base = 0;
     if (in) {
         ky = k / nx;
@@ -692,11 +777,18 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
     const int32_t* __restrict__ bidx, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ foff, const int32_t* __restrict__ fsrc,
     int32_t* __restrict__ cnt, int32_t* __restrict__ fcnt, int32_t* __restrict__ fcur,
-    int32_t* __restrict__ farn, Rec<T> r, double* __restrict__ mom) {
+    int32_t* __restrict__ farn, Rec<T> r, double* __restrict__ mom, double* __restrict__ samp) {
     constexpr int GROUPS = BIN_BLOCK / G;
-    __shared__ int32_t s_run[GROUPS][9][3];
+    __shared__ int32_t s_run[GROUPS][9][4];   // start in bidx, length, far before, range start
     __shared__ int32_t s_pre[GROUPS][10];     // bucket starts in the cell's concatenation
     __shared__ MomShared<BIN_BLOCK, G> sm;
+    // far arrivals of a cell staged in LDS, up to FCAP of them (their ranks compare every
+    // arrival with all others and with the nine source ranges), in the space of the
+    // moment reduction, which is used only after the gather's last barrier: the
+    // workgroup's LDS stays below 32 KB (five workgroups per CU)
+    constexpr int FCAP = 2048 / GROUPS;
+    static_assert(sizeof(int32_t) * GROUPS * FCAP <= sizeof(sm.red), "far staging space");
+    int32_t(*s_far)[FCAP] = reinterpret_cast<int32_t(*)[FCAP]>(&sm.red[0][0]);
     for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i <= ncell;
          i += (int64_t)gridDim.x * BIN_BLOCK) {
         cnt[i] = 0;
@@ -707,8 +799,9 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
     const int64_t lim = min((int64_t)offsets[ncell], n);
     const int32_t fend = (int32_t)min((int64_t)foff[ncell], cap);
     const int grp = threadIdx.x / G, lg = threadIdx.x % G;
-    const int32_t k = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * GROUPS + grp;
-    const bool in = k < ncell;
+    const int32_t ord = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * GROUPS + grp;
+    const bool in = ord < ncell;
+    const int32_t k = in ? strip_cell(ord, nx, ny) : ord;
     int32_t kx = 0, ky = 0, base = 0, f0 = 0, f1 = 0;
     if (in) {
         ky = k / nx;
@@ -717,22 +810,31 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
         f0 = min(foff[k], fend);
         f1 = min(foff[k + 1], fend);
     }
+    const int32_t nf = f1 - f0;
+    const bool far_lds = nf <= FCAP;   // group-uniform
+    if (far_lds)
+        for (int32_t t = lg; t < nf; t += G) s_far[grp][t] = fsrc[f0 + t];
+    __syncthreads();
+    auto far_at = [&](int32_t t) __attribute__((always_inline)) {
+        return far_lds ? s_far[grp][t] : fsrc[f0 + t];
+    };
     for (int q = lg; q < 9; q += G) {
-        int32_t st = 0, len = 0, fb = 0;
+        int32_t st = 0, len = 0, fb = 0, s0 = INT32_MAX;
         const int32_t sy = ky - 1 + q / 3, sx = kx - 1 + q % 3;
         if (in && sx >= 0 && sx < nx && sy >= 0 && sy < ny) {
             const int32_t c2 = sy * nx + sx;
             const int d = (ky - sy + 1) * 3 + (kx - sx + 1);
             const int32_t* e2 = bend + (int64_t)c2 * 9;
             const int32_t b0 = d > 0 ? e2[d - 1] : 0;
-            const int32_t s0 = max(src_off[c2], 0);
+            s0 = max(src_off[c2], 0);
             st = s0 + b0;
             len = e2[d] - b0;
-            for (int32_t f = f0; f < f1; ++f) fb += fsrc[f] < s0 ? 1 : 0;
+            for (int32_t f = 0; f < nf; ++f) fb += far_at(f) < s0 ? 1 : 0;
         }
         s_run[grp][q][0] = st;
         s_run[grp][q][1] = len;
         s_run[grp][q][2] = fb;
+        s_run[grp][q][3] = s0;   // INT32_MAX for a neighbour outside the grid
     }
     __syncthreads();
     if (lg == 0) {
@@ -806,18 +908,16 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
         T tx[GM_U], ty[GM_U], tz[GM_U];
         round(q0, tx, ty, tz);
     }
-    // far arrivals of this cell, placed by counting
-    for (int32_t i = f0 + lg; i < f1; i += G) {
-        const int32_t p = fsrc[i];
+    // far arrivals of this cell, placed by counting: after every bucket whose old cell
+    // starts before it and every arrival with a smaller source index
+    for (int32_t i = lg; i < nf; i += G) {
+        const int32_t p = far_at(i);
         if (p < 0 || p >= n) continue;   // only with bad src_off
         int32_t slot = base;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const int32_t sy = ky - 1 + q / 3, sx = kx - 1 + q % 3;
-            if (sx >= 0 && sx < nx && sy >= 0 && sy < ny && src_off[sy * nx + sx] < p)
-                slot += rs[q + 1] - rs[q];
-        }
-        for (int32_t f = f0; f < f1; ++f) slot += fsrc[f] < p ? 1 : 0;
+        for (int q = 0; q < 9; ++q)
+            if (s_run[grp][q][3] < p) slot += rs[q + 1] - rs[q];
+        for (int32_t f = 0; f < nf; ++f) slot += far_at(f) < p ? 1 : 0;
         if (slot >= 0 && slot < lim) r.copy(p, slot, k);
     }
     // moments of the cell from its sorted slots, in slot order per lane (deterministic:
@@ -844,24 +944,74 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
                   (double)r.dvz[base + q] - U2, acc);
     mom_finish<BIN_BLOCK, G>(sm, acc, grp, lg, in, ncnt, U0, U1, U2,
                              mom + (int64_t)(in ? k : 0) * MOM);
+    if (samp) {
+        // time-average sums from the record, once all of the group's lanes wrote it
+        __syncthreads();
+        if (in && lg == 0) sample_add(mom + (int64_t)k * MOM, samp + (int64_t)k * SAMP);
+    }
 }
 
+// pass 1 with G lanes per old cell
+template <int G>
+static void rebin_count_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
+                               hipStream_t s) {
+    const int32_t nc = c->ncell;
+    const int32_t cblocks = (int32_t)(((int64_t)nc * G + BIN_BLOCK - 1) / BIN_BLOCK);
+    // cnt, ccnt (far counts), ccur and farn are zero on entry: the previous sort call left
+    // them so
+    hipLaunchKernelGGL((rebin_count_kernel<G>), dim3(cblocks + FAR_BLOCKS), dim3(BIN_BLOCK), 0, s, nc,
+                       c->cfg.nx, src->n, c->cfg.capacity, cblocks, src_off, (const int32_t*)src->key,
+                       c->ncnt, c->bidx, c->cnt, c->ccnt, c->farn, c->cmask, c->errcount);
+}
+
+// pass 2 with G lanes per destination cell
 template <typename T, int G>
-static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
-                         fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom,
-                         hipStream_t s) {
+static void rebin_gather_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
+                                fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom,
+                                double* samp, hipStream_t s) {
     const int32_t nc = c->ncell, nx = c->cfg.nx, ny = c->cfg.ny;
     const int64_t n = src->n, cap = c->cfg.capacity;
     const bool two_d = c->cfg.geometry != FP_COUETTE1D;
-    const int32_t cblocks_count = (int32_t)(((int64_t)nc * G + BIN_BLOCK - 1) / BIN_BLOCK);
-    // cnt, ccnt (far counts), ccur and farn are zero on entry: the previous sort call left
-    // them so
-    hipLaunchKernelGGL((rebin_count_kernel<G>), dim3(cblocks_count + FAR_BLOCKS), dim3(BIN_BLOCK), 0,
-                       s, nc, nx, n, cap, cblocks_count, src_off, (const int32_t*)src->key, c->ncnt,
-                       c->bidx, c->cnt, c->ccnt, c->farn, c->cmask, c->errcount);
+    Rec<T> r{(const T*)src->x,  two_d ? (const T*)src->y : nullptr, (const T*)src->vx,
+             (const T*)src->vy, (const T*)src->vz,                   src->pid,
+             (T*)dst->x,        two_d ? (T*)dst->y : nullptr,        (T*)dst->vx,
+             (T*)dst->vy,       (T*)dst->vz,                         dst->pid,
+             dst->key,          perm};
+    const int32_t cblocks = (nc + BIN_BLOCK / G - 1) / (BIN_BLOCK / G);
+    if (mom) {
+        hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G>), dim3(cblocks), dim3(BIN_BLOCK), 0, s,
+                           nc, nx, ny, n, cap, src_off, (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
+                           (const int32_t*)offsets, (const int32_t*)c->coff, (const int32_t*)c->gidx,
+                           c->cnt, c->ccnt, c->ccur, c->farn, r, mom, samp);
+        return;
+    }
+    hipLaunchKernelGGL((rebin_gather_kernel<T, G>), dim3(cblocks + FAR_BLOCKS), dim3(BIN_BLOCK),
+                       0, s, nc, nx, ny, n, cap, cblocks, src_off, (const int32_t*)c->ncnt,
+                       (const int32_t*)c->bidx, (const int32_t*)offsets, (const int32_t*)c->coff,
+                       (const int32_t*)c->cwave, (const int32_t*)c->gidx, c->cnt, c->ccnt, c->ccur,
+                       c->farn, r);
+}
+
+template <typename T>
+static void rebin_typed(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
+                        fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom,
+                        double* samp, hipStream_t s) {
+    const int32_t nc = c->ncell;
+    // count: about 8 particles per lane (its work per particle is ALU); gather: about 4
+    // (its dependent load chains are short per lane), at most 32 (the moment reduction
+    // sums G partials per value)
+    switch (lanes_per_cell(c, src->n, FILL_4)) {
+        case 4: rebin_count_launch<4>(c, src, src_off, s); break;
+        case 8: rebin_count_launch<8>(c, src, src_off, s); break;
+        case 16: rebin_count_launch<16>(c, src, src_off, s); break;
+        case 32: rebin_count_launch<32>(c, src, src_off, s); break;
+        default: rebin_count_launch<64>(c, src, src_off, s); break;
+    }
     if (nc <= SMALL_SCAN_CELLS) {
         hipLaunchKernelGGL(rebin_small_scan_kernel, dim3((nc + SSB - 1) / SSB), dim3(SSB), 0, s, nc,
-                           (const int32_t*)c->cnt, (const int32_t*)c->ccnt, offsets, c->coff);
+                           (int64_t)c->cfg.capacity, (const int32_t*)c->cnt, (const int32_t*)c->ccnt,
+                           offsets, c->coff, (const int32_t*)c->farn, (const uint64_t*)c->cmask,
+                           c->cwave, c->gidx);
     } else {
         const int32_t nblocks = (nc + SCAN_TILE - 1) / SCAN_TILE;
         hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt,
@@ -869,49 +1019,27 @@ static void rebin_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_
         hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(SCAN_BLOCK), 0, s, c->blocksum, nblocks);
         hipLaunchKernelGGL(scan_final_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt, nc,
                            c->blocksum, nblocks, offsets, c->coff);
+        hipLaunchKernelGGL(rebin_far_place_kernel, dim3(FAR_BLOCKS), dim3(BIN_BLOCK), 0, s,
+                           (int64_t)c->cfg.capacity, (const int32_t*)c->farn, (const uint64_t*)c->cmask,
+                           (const int32_t*)c->coff, c->ccur, c->cwave, c->gidx);
     }
-    hipLaunchKernelGGL(rebin_far_place_kernel, dim3(FAR_BLOCKS), dim3(BIN_BLOCK), 0, s, cap,
-                       (const int32_t*)c->farn, (const uint64_t*)c->cmask, (const int32_t*)c->coff,
-                       c->ccur, c->cwave, c->gidx);
-    Rec<T> r{(const T*)src->x,  two_d ? (const T*)src->y : nullptr, (const T*)src->vx,
-             (const T*)src->vy, (const T*)src->vz,                   src->pid,
-             (T*)dst->x,        two_d ? (T*)dst->y : nullptr,        (T*)dst->vx,
-             (T*)dst->vy,       (T*)dst->vz,                         dst->pid,
-             dst->key,          perm};
-    const int32_t cblocks_gather = (nc + BIN_BLOCK / G - 1) / (BIN_BLOCK / G);
-    if (mom) {
-        hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G>), dim3(cblocks_gather), dim3(BIN_BLOCK), 0, s,
-                           nc, nx, ny, n, cap, src_off, (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
-                           (const int32_t*)offsets, (const int32_t*)c->coff, (const int32_t*)c->gidx,
-                           c->cnt, c->ccnt, c->ccur, c->farn, r, mom);
-        return;
-    }
-    hipLaunchKernelGGL((rebin_gather_kernel<T, G>), dim3(cblocks_gather + FAR_BLOCKS), dim3(BIN_BLOCK),
-                       0, s, nc, nx, ny, n, cap, cblocks_gather, src_off, (const int32_t*)c->ncnt,
-                       (const int32_t*)c->bidx, (const int32_t*)offsets, (const int32_t*)c->coff,
-                       (const int32_t*)c->cwave, (const int32_t*)c->gidx, c->cnt, c->ccnt, c->ccur,
-                       c->farn, r);
-}
-
-template <typename T>
-static void rebin_dispatch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
-                           fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom,
-                           hipStream_t s) {
-    switch (lanes_per_cell(c, src->n, FILL_8)) {
-        case 4: rebin_launch<T, 4>(c, src, src_off, dst, offsets, perm, mom, s); break;
-        case 8: rebin_launch<T, 8>(c, src, src_off, dst, offsets, perm, mom, s); break;
-        case 16: rebin_launch<T, 16>(c, src, src_off, dst, offsets, perm, mom, s); break;
-        case 32: rebin_launch<T, 32>(c, src, src_off, dst, offsets, perm, mom, s); break;
-        default: rebin_launch<T, 64>(c, src, src_off, dst, offsets, perm, mom, s); break;
+    int g = lanes_per_cell(c, src->n, FILL_4, 4);
+    if (c->cfg.lanes <= 0 && g > 32) g = 32;
+    switch (g) {
+        case 4: rebin_gather_launch<T, 4>(c, src, src_off, dst, offsets, perm, mom, samp, s); break;
+        case 8: rebin_gather_launch<T, 8>(c, src, src_off, dst, offsets, perm, mom, samp, s); break;
+        case 16: rebin_gather_launch<T, 16>(c, src, src_off, dst, offsets, perm, mom, samp, s); break;
+        case 32: rebin_gather_launch<T, 32>(c, src, src_off, dst, offsets, perm, mom, samp, s); break;
+        default: rebin_gather_launch<T, 64>(c, src, src_off, dst, offsets, perm, mom, samp, s); break;
     }
 }
 
 int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_particles* dst,
-                 int32_t* offsets, int32_t* perm, double* mom, hipStream_t s) {
+                 int32_t* offsets, int32_t* perm, double* mom, double* samp, hipStream_t s) {
     if (c->cfg.precision == FP_F32)
-        rebin_dispatch<float>(c, src, src_off, dst, offsets, perm, mom, s);
+        rebin_typed<float>(c, src, src_off, dst, offsets, perm, mom, samp, s);
     else
-        rebin_dispatch<double>(c, src, src_off, dst, offsets, perm, mom, s);
+        rebin_typed<double>(c, src, src_off, dst, offsets, perm, mom, samp, s);
     return check_launch(c, "fp_rebin");
 }
 

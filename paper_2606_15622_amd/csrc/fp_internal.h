@@ -36,6 +36,7 @@ struct fp_ctx {
                                  // step: per-cell lists of the flights left to flight_rest
     int32_t* farn = nullptr;     // [1] re-sort: length of the list of particles that moved far
     int32_t* pend = nullptr;     // [ncell] step: flights left for flight_rest_kernel per cell
+    uint32_t* stepc = nullptr;   // [1] step: the step number collide_kernel read, for flight_rest_kernel
     unsigned long long* errcount = nullptr;  // invalid keys
     // open cylinder domain
     double* vol = nullptr;       // [ncell] gas volume of every cell
@@ -163,14 +164,14 @@ __device__ __forceinline__ int group_sum_i(int v) {
 }
 
 // ---- host-side launch shape of the per-cell kernels -------------------------------------
-// Lanes per cell: about 8 particles per lane from the mean occupancy, and at least enough
-// lanes that the grid holds min_threads work-items (small grids would leave most SIMDs
-// idle); 4..64 lanes.  cfg.lanes > 0 overrides both.
-inline int lanes_per_cell(const fp_ctx* c, int64_t n, int64_t min_threads = 0) {
+// Lanes per cell: about ppl particles per lane from the mean occupancy, and at least
+// enough lanes that the grid holds min_threads work-items (small grids would leave most
+// SIMDs idle); 4..64 lanes.  cfg.lanes > 0 overrides both.
+inline int lanes_per_cell(const fp_ctx* c, int64_t n, int64_t min_threads = 0, int ppl = 8) {
     if (c->cfg.lanes > 0) return c->cfg.lanes;
     const double avg = c->ncell > 0 ? (double)n / (double)c->ncell : 0.0;
     int g = 4;
-    while (g < 64 && (double)g * 8.0 < avg * 1.25) g *= 2;
+    while (g < 64 && (double)g * ppl < avg * 1.25) g *= 2;
     while (g < 64 && (int64_t)c->ncell * g < min_threads) g *= 2;
     return g;
 }
@@ -182,7 +183,7 @@ constexpr int64_t FILL_4 = 1024 * 4 * 64, FILL_8 = 1024 * 8 * 64;
 int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* offsets,
                int32_t* perm, hipStream_t s);
 int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_particles* dst,
-                 int32_t* offsets, int32_t* perm, double* mom, hipStream_t s);
+                 int32_t* offsets, int32_t* perm, double* mom, double* samp, hipStream_t s);
 int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,
                    hipStream_t s);
 int launch_closure(fp_ctx* c, const double* mom, double* rec, int32_t* status, hipStream_t s);

@@ -112,40 +112,77 @@ __device__ __forceinline__ void cell_features(const double* m, double eps_hat, f
     for (int q = 27; q < 32; ++q) f[q] = 0.0f;
 }
 
+// the 16 features lane half h feeds into the first layer: f[q] = feature 8h + q (q < 8)
+// and 16 + 8h + (q - 8) (q >= 8); the same arithmetic as cell_features, with only the
+// moments that half needs loaded (17 of them for h = 0, 11 for h = 1)
+__device__ __forceinline__ void half_features(const double* __restrict__ m, int h, double eps_hat,
+                                              float f[16]) {
+    const double th = m[M_TH];
+    const double i1 = 1.0 / th, i15 = i1 / sqrt(th), i2 = i1 * i1, i25 = i2 / sqrt(th);
+    // feature K -> (moment index, scale: 0 = 1/th 1 = th^-1.5 2 = th^-2 3 = th^-2.5,
+    // offset), for K < 25
+    auto fea = [&](int K, bool hi) -> float {
+        if (K < 6) return (float)(m[M_P + K] * i1 - ((K == 0 || K == 3 || K == 5) ? 1.0 : 0.0));
+        if (K < 16) return (float)(m[M_T + K - 6] * i15);
+        if (K < 22) {
+            const int q = K - 16;
+            return (float)(m[M_R + q] * i2 - ((q == 0 || q == 3 || q == 5) ? 5.0 : 0.0));
+        }
+        if (K < 25) return (float)(m[M_W + K - 22] * i25);
+        if (K == 25) return (float)eps_hat;
+        if (K == 26) return hi ? (float)log10(m[M_N]) : 0.0f;
+        return 0.0f;
+    };
+    if (h == 0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) f[q] = fea(q < 8 ? q : 16 + q - 8, false);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) f[q] = fea(q < 8 ? 8 + q : 24 + q - 8, true);
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // fused inference: standardised outputs y_std[cell][16] (entries 9..15 zero)
-constexpr int NN_BLOCK = 256;
+// 16 waves per workgroup share one LDS copy of the weights (82 KB: one workgroup per
+// CU), i.e. 4 waves per SIMD, so that one wave's SiLU epilogue (VALU) overlaps another's
+// MFMAs; every wave keeps at most 128 registers (VGPRs and AGPRs together)
+constexpr int NN_BLOCK = 1024;
 
 template <int KS>
 __device__ __forceinline__ void nn_layer(const __bf16* __restrict__ img_l, const float* __restrict__ bias,
                                          const bf16x8 (&bin)[8], bf16x8 (&bout)[8], int lane) {
     const int h = lane >> 5;
-    // accumulators start from the bias: output row u = 32 mt + 8 (j / 4) + 4 h + j % 4,
-    // four consecutive rows per 16-byte LDS read
-    f32x16 acc[4];
+    // two of the four 32-row output tiles at a time (32 accumulator registers live)
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mp = 0; mp < 4; mp += 2) {
+        // accumulators start from the bias: output row u = 32 mt + 8 (j / 4) + 4 h + j % 4,
+        // four consecutive rows per 16-byte LDS read
+        f32x16 acc[2];
 #pragma unroll
-        for (int jq = 0; jq < 4; ++jq) {
-            const float4 bq = *(const float4*)(bias + mt * 32 + 8 * jq + 4 * h);
-            acc[mt][4 * jq + 0] = bq.x;
-            acc[mt][4 * jq + 1] = bq.y;
-            acc[mt][4 * jq + 2] = bq.z;
-            acc[mt][4 * jq + 3] = bq.w;
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int jq = 0; jq < 4; ++jq) {
+                const float4 bq = *(const float4*)(bias + (mp + t) * 32 + 8 * jq + 4 * h);
+                acc[t][4 * jq + 0] = bq.x;
+                acc[t][4 * jq + 1] = bq.y;
+                acc[t][4 * jq + 2] = bq.z;
+                acc[t][4 * jq + 3] = bq.w;
+            }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const bf16x8 a = *(const bf16x8*)(img_l + (((mp + t) * KS + s) * 64 + lane) * 8);
+                acc[t] = mfma32(a, bin[s], acc[t]);
+            }
         }
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const bf16x8 a = *(const bf16x8*)(img_l + ((mt * KS + s) * 64 + lane) * 8);
-            acc[mt] = mfma32(a, bin[s], acc[mt]);
-        }
+            for (int j = 0; j < 16; ++j)
+                bout[2 * (mp + t) + (j >> 3)][j & 7] = (__bf16)silu_fast(acc[t][j]);
     }
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-            bout[2 * mt + (j >> 3)][j & 7] = (__bf16)silu_fast(acc[mt][j]);
 }
 
 __global__ __launch_bounds__(NN_BLOCK) void nn_infer_kernel(int32_t ncell, const double* __restrict__ mom,
@@ -163,20 +200,17 @@ __global__ __launch_bounds__(NN_BLOCK) void nn_infer_kernel(int32_t ncell, const
     const int32_t ntiles = (ncell + 31) / 32;
     for (int32_t tile = blockIdx.x * (NN_BLOCK / 64) + wave; tile < ntiles;
          tile += gridDim.x * (NN_BLOCK / 64)) {
+        // the weight fragments are read from LDS inside every tile: keep the compiler from
+        // hoisting them out of the loop (80 fragments would not fit in the registers)
+        __asm__ volatile("" ::: "memory");
         const int32_t cell = tile * 32 + n;
         const bool valid = cell < ncell;
-        float f[32];
+        float f[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) f[q] = 0.0f;
         if (valid) {
-            double m[31];
-#pragma unroll
-            for (int i = 0; i < 31; ++i) m[i] = mom[(int64_t)cell * MOM + i];
-            if (m[M_N] > 1.0 && m[M_TH] > 0.0) cell_features(m, eps_hat, f);
-            else
-#pragma unroll
-                for (int q = 0; q < 32; ++q) f[q] = 0.0f;
-        } else {
-#pragma unroll
-            for (int q = 0; q < 32; ++q) f[q] = 0.0f;
+            const double* mr = mom + (int64_t)cell * MOM;
+            if (mr[M_N] > 1.0 && mr[M_TH] > 0.0) half_features(mr, h, eps_hat, f);
         }
         bf16x8 b0[8], b1[8];
 #pragma unroll
@@ -184,8 +218,7 @@ __global__ __launch_bounds__(NN_BLOCK) void nn_infer_kernel(int32_t ncell, const
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int K = 16 * s + 8 * h + i;
-                const float fk = h ? f[16 * s + 8 + i] : f[16 * s + i];
-                b0[s][i] = (__bf16)((fk - sec[SEC_XM + K]) / sec[SEC_XS + K]);
+                b0[s][i] = (__bf16)((f[8 * s + i] - sec[SEC_XM + K]) / sec[SEC_XS + K]);
             }
         nn_layer<2>(img + IMG_L1, sec + SEC_B1, b0, b1, lane);
         nn_layer<8>(img + IMG_L2, sec + SEC_B2, b1, b0, lane);
@@ -573,7 +606,7 @@ extern "C" int fp_closure_nn(fp_ctx* c, const fp_nn* n, const double* mom, doubl
         return set_err(c, FP_EINVAL, "fp_closure_nn: bad argument");
     const int32_t ntiles = (c->ncell + 31) / 32;
     int grid = (ntiles + NN_BLOCK / 64 - 1) / (NN_BLOCK / 64);
-    if (grid > 512) grid = 512;
+    if (grid > 256) grid = 256;   // one workgroup per CU, each loops over its tiles
     hipLaunchKernelGGL(nn_infer_kernel, dim3(grid), dim3(NN_BLOCK), 0, s, c->ncell, mom,
                        c->cfg.eps_hat, (const __bf16*)n->img, (const float*)n->sec, n->ybuf);
     int rc = check_launch(c, "fp_closure_nn (network)");

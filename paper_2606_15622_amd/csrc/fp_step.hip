@@ -273,8 +273,10 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
     const double* __restrict__ mom, const double* __restrict__ rec, T* __restrict__ px,
     T* __restrict__ py, T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
     const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step_arg, int move,
-    const uint32_t* __restrict__ stepp, int32_t* __restrict__ pend, int32_t* __restrict__ plist) {
+    const uint32_t* __restrict__ stepp, int32_t* __restrict__ pend, int32_t* __restrict__ plist,
+    uint32_t* __restrict__ stepc) {
     const uint32_t step = stepp ? stepp[0] : step_arg;
+    if (stepc && blockIdx.x == 0 && threadIdx.x == 0) stepc[0] = step;   // for flight_rest
     const int64_t gt = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
     const int32_t cell = (int32_t)(gt / G);
     const int lg = (int)(gt % G);
@@ -440,28 +442,50 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
 }
 
 // the flights collide_kernel left: the particles listed for cells with pend > 0 fly from
-// their stored position with their stored (new) velocity, through walls / past the body
-template <typename T, int G, int GEOM>
-__global__ __launch_bounds__(ST_BLOCK) void flight_rest_kernel(
+// their stored position with their stored (new) velocity, through walls / past the body.
+// One wave per FR cells: it reads their list lengths at once and spreads the listed
+// particles of all of them over its 64 lanes (only cells in reach of a wall or the body
+// have any, so most waves end after one load).  The flights of the cells along a wall
+// are the kernel's critical path: FR = 2 on small grids keeps them to one flight per
+// lane (a wave per 64 cells serialised whole wall rows), FR = 4 on large grids halves
+// the number of waves.  With adv non-null the step number is the one collide_kernel
+// saved in stepc, and one lane sets *adv (the caller's step counter, read by nothing else
+// in this kernel) to the next step number.
+constexpr int FR_BLOCK = 256;
+
+template <typename T, int GEOM, int FR>
+__global__ __launch_bounds__(FR_BLOCK) void flight_rest_kernel(
     fp_config g, int32_t ncell, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ pend, const int32_t* __restrict__ plist, T* __restrict__ px,
     T* __restrict__ py, T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
     const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step_arg,
-    const uint32_t* __restrict__ stepp) {
-    const int64_t gt = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
-    const int32_t cell = (int32_t)(gt / G);
-    const int lg = (int)(gt % G);
-    if (cell >= ncell) return;
-    const int32_t np = pend[cell];
-    if (lg >= np) return;
-    const uint32_t step = stepp ? stepp[0] : step_arg;
+    const uint32_t* stepp, uint32_t* adv, const uint32_t* __restrict__ stepc) {
+    constexpr int FR_CELLS = FR;
+    if (adv && blockIdx.x == 0 && threadIdx.x == 0) adv[0] = stepc[0] + 1u;
+    const int lane = threadIdx.x & 63;
+    const int32_t c0 = (int32_t)((blockIdx.x * (FR_BLOCK / 64) + (threadIdx.x >> 6)) * FR_CELLS);
+    int32_t np = 0, b = 0;
+    if (lane < FR_CELLS && c0 + lane < ncell) np = pend[c0 + lane];
+    if (__ballot(np > 0) == 0) return;
+    if (np > 0) b = offsets[c0 + lane];
+    int32_t pre[FR_CELLS + 1], bs[FR_CELLS];
+    pre[0] = 0;
+#pragma unroll
+    for (int c = 0; c < FR_CELLS; ++c) {
+        pre[c + 1] = pre[c] + __shfl(np, c, 64);
+        bs[c] = __shfl(b, c, 64);
+    }
+    const uint32_t step = adv ? stepc[0] : (stepp ? stepp[0] : step_arg);
     const bool f32 = sizeof(T) == 4;
     constexpr bool TWO_D = GEOM != FP_COUETTE1D;
     const Walls W = make_walls(g);
     const double inv_dx = 1.0 / g.dx, inv_dy = 1.0 / g.dy;
-    const int32_t b = offsets[cell];
-    for (int32_t i = lg; i < np; i += G) {
-        const int32_t p = plist[b + i];
+    for (int32_t i = lane; i < pre[FR_CELLS]; i += 64) {
+        int32_t at = bs[0] + i;
+#pragma unroll
+        for (int c = 1; c < FR_CELLS; ++c)
+            if (i >= pre[c]) at = bs[c] + (i - pre[c]);
+        const int32_t p = plist[at];
         double pos[2] = {(double)px[p], TWO_D ? (double)py[p] : 0.0};
         double v[3] = {(double)pvx[p], (double)pvy[p], (double)pvz[p]};
         bool gone = false;
@@ -515,29 +539,40 @@ __global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, 
 template <typename T, int G, int GEOM>
 static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
                            const double* rec, uint32_t step, int move, const uint32_t* stepp,
-                           hipStream_t s) {
+                           uint32_t* adv, hipStream_t s) {
     const int64_t threads = (int64_t)c->ncell * G;
     const unsigned grid = (unsigned)((threads + ST_BLOCK - 1) / ST_BLOCK);
     hipLaunchKernelGGL((collide_kernel<T, G, ST_K, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
                        c->cfg, c->ncell, off, mom, rec, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy,
-                       (T*)p->vz, p->pid, p->key, step, move, stepp, c->pend, c->bidx);
-    if (move)
-        hipLaunchKernelGGL((flight_rest_kernel<T, G, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
-                           c->cfg, c->ncell, off, (const int32_t*)c->pend, (const int32_t*)c->bidx,
-                           (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
-                           step, stepp);
+                       (T*)p->vz, p->pid, p->key, step, move, stepp, c->pend, c->bidx,
+                       adv ? c->stepc : nullptr);
+    if (move) {
+        const int fr = c->ncell <= 65536 ? 2 : 4;
+        const int32_t per_block = FR_BLOCK / 64 * fr;
+        const dim3 fgrid((c->ncell + per_block - 1) / per_block);
+        if (fr == 2)
+            hipLaunchKernelGGL((flight_rest_kernel<T, GEOM, 2>), fgrid, dim3(FR_BLOCK), 0, s, c->cfg,
+                               c->ncell, off, (const int32_t*)c->pend, (const int32_t*)c->bidx, (T*)p->x,
+                               (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key, step, stepp,
+                               adv, (const uint32_t*)c->stepc);
+        else
+            hipLaunchKernelGGL((flight_rest_kernel<T, GEOM, 4>), fgrid, dim3(FR_BLOCK), 0, s, c->cfg,
+                               c->ncell, off, (const int32_t*)c->pend, (const int32_t*)c->bidx, (T*)p->x,
+                               (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key, step, stepp,
+                               adv, (const uint32_t*)c->stepc);
+    }
 }
 
 template <typename T, int GEOM>
 static void collide_dispatch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
                              const double* rec, uint32_t step, int move, const uint32_t* sp,
-                             hipStream_t s) {
+                             uint32_t* adv, hipStream_t s) {
     switch (lanes_per_cell(c, p->n, FILL_4)) {
-        case 4: collide_launch<T, 4, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
-        case 8: collide_launch<T, 8, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
-        case 16: collide_launch<T, 16, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
-        case 32: collide_launch<T, 32, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
-        default: collide_launch<T, 64, GEOM>(c, p, off, mom, rec, step, move, sp, s); break;
+        case 4: collide_launch<T, 4, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;
+        case 8: collide_launch<T, 8, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;
+        case 16: collide_launch<T, 16, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;
+        case 32: collide_launch<T, 32, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;
+        default: collide_launch<T, 64, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;
     }
 }
 
@@ -547,11 +582,26 @@ static void step_typed(fp_ctx* c, fp_particles* p, const int32_t* off, const dou
                        hipStream_t s) {
     const int geom = c->cfg.geometry;
     const int move = (flags & FP_STEP_MOVE) ? 1 : 0;
-    if (flags & FP_STEP_COLLIDE) {
-        if (geom == FP_CAVITY2D) collide_dispatch<T, FP_CAVITY2D>(c, p, off, mom, rec, step, move, sp, s);
+    if ((flags & FP_STEP_COLLIDE) && move) {
+        // the counter advance rides on the last kernel of the step
+        uint32_t* adv = (flags & FP_STEP_ADVANCE) ? const_cast<uint32_t*>(sp) : nullptr;
+        if (geom == FP_CAVITY2D) collide_dispatch<T, FP_CAVITY2D>(c, p, off, mom, rec, step, move, sp, adv, s);
         else if (geom == FP_CYLINDER2D)
-            collide_dispatch<T, FP_CYLINDER2D>(c, p, off, mom, rec, step, move, sp, s);
-        else collide_dispatch<T, FP_COUETTE1D>(c, p, off, mom, rec, step, move, sp, s);
+            collide_dispatch<T, FP_CYLINDER2D>(c, p, off, mom, rec, step, move, sp, adv, s);
+        else collide_dispatch<T, FP_COUETTE1D>(c, p, off, mom, rec, step, move, sp, adv, s);
+        return;
+    }
+    if (flags & FP_STEP_ADVANCE) {
+        // the other forms end with a kernel of their own for it
+        step_typed<T>(c, p, off, mom, rec, step, flags & ~FP_STEP_ADVANCE, sp, s);
+        launch_counter_add(c, const_cast<uint32_t*>(sp), 1u, s);
+        return;
+    }
+    if (flags & FP_STEP_COLLIDE) {
+        if (geom == FP_CAVITY2D) collide_dispatch<T, FP_CAVITY2D>(c, p, off, mom, rec, step, 0, sp, nullptr, s);
+        else if (geom == FP_CYLINDER2D)
+            collide_dispatch<T, FP_CYLINDER2D>(c, p, off, mom, rec, step, 0, sp, nullptr, s);
+        else collide_dispatch<T, FP_COUETTE1D>(c, p, off, mom, rec, step, 0, sp, nullptr, s);
         return;
     }
     if (p->n == 0) return;

@@ -20,7 +20,7 @@ FP_F32, FP_F64 = 0, 1
 FP_EXACT, FP_PAPER = 0, 1
 (CELL_OK, CELL_EMPTY, CELL_FEW, CELL_SINGULAR, CELL_NONFINITE, CELL_NN,
  CELL_NN_FALLBACK) = range(7)
-STEP_COLLIDE, STEP_MOVE, STEP_KEYS = 1, 2, 4
+STEP_COLLIDE, STEP_MOVE, STEP_KEYS, STEP_ADVANCE = 1, 2, 4, 8
 MOM_STRIDE, REC_STRIDE, SAMP_STRIDE = 32, 16, 16
 NN_PARAMS, NN_TRAIN, NN_FEATURES, NN_OUTPUTS = 39408, 39312, 32, 16
 LOSS_MSE, LOSS_RESIDUAL = 0, 1
@@ -68,7 +68,7 @@ def load():
         L.fp_error_count.argtypes = [vp, vp]
         L.fp_error_count.restype = i64
         L.fp_bin.argtypes = [vp, P(FPParticles), P(FPParticles), vp, vp, vp]
-        L.fp_rebin.argtypes = [vp, P(FPParticles), vp, P(FPParticles), vp, vp, vp, vp]
+        L.fp_rebin.argtypes = [vp, P(FPParticles), vp, P(FPParticles), vp, vp, vp, vp, vp]
         L.fp_moments.argtypes = [vp, P(FPParticles), vp, vp, vp]
         L.fp_closure_solve.argtypes = [vp, vp, vp, vp, vp]
         L.fp_step.argtypes = [vp, P(FPParticles), vp, vp, vp, u64, u32, vp]
@@ -238,11 +238,11 @@ class Context:
         self._check(self.lib.fp_bin(self.h, C.byref(a), C.byref(b), _ptr(offsets), _ptr(perm),
                                     _stream(stream)), "fp_bin")
 
-    def rebin(self, src, src_offsets, dst, offsets, perm=None, mom=None, stream=None):
+    def rebin(self, src, src_offsets, dst, offsets, perm=None, mom=None, samp=None, stream=None):
         a, b = src.struct(), dst.struct()
         self._check(self.lib.fp_rebin(self.h, C.byref(a), _ptr(src_offsets), C.byref(b),
-                                      _ptr(offsets), _ptr(perm), _ptr(mom), _stream(stream)),
-                    "fp_rebin")
+                                      _ptr(offsets), _ptr(perm), _ptr(mom), _ptr(samp),
+                                      _stream(stream)), "fp_rebin")
 
     def moments(self, p, offsets, mom, stream=None):
         a = p.struct()
@@ -386,25 +386,26 @@ class Simulation:
         """Cell start indices of the particles in a (after the last sort)."""
         return self.offs[0]
 
-    def sort(self, perm=None, mom=None):
+    def sort(self, perm=None, mom=None, samp=None):
         """a -> b sorted by key (fp_rebin from the previous grouping after the first
         step, fp_bin before), then swap a and b; offsets describe the new a.  With mom,
-        the moments of the sorted cells are written too (by the re-sort itself, or by
-        fp_moments after the first sort)."""
+        the moments of the sorted cells are written too, and with samp their time-average
+        sums are added (by the re-sort itself, or by fp_moments and fp_sample after the
+        first sort)."""
         if self.sorted:
-            self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1], perm, mom)
+            self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1], perm, mom, samp)
         else:
             self.ctx.bin(self.a, self.b, self.offs[1], perm)
         self.offs.reverse()
         self.a, self.b = self.b, self.a
         if mom is not None and not self.sorted:
             self.ctx.moments(self.a, self.offsets, mom)
+            if samp is not None:
+                self.ctx.sample(mom, samp)
         self.sorted = True
 
     def step(self, s, sample=False):
-        self.sort(mom=self.mom)
-        if sample:
-            self.ctx.sample(self.mom, self.samp)
+        self.sort(mom=self.mom, samp=self.samp if sample else None)
         self.ctx.closure_solve(self.mom, self.rec, self.status)
         self.ctx.step(self.a, self.offsets, self.mom, self.rec, s, STEP_COLLIDE | STEP_MOVE)
 
@@ -427,13 +428,10 @@ class GraphSimulation(Simulation):
 
     def _body(self, sample):
         for _ in range(2):
-            self.sort(mom=self.mom)
-            if sample:
-                self.ctx.sample(self.mom, self.samp)
+            self.sort(mom=self.mom, samp=self.samp if sample else None)
             self.ctx.closure_solve(self.mom, self.rec, self.status)
             self.ctx.step_dev(self.a, self.offsets, self.mom, self.rec, self.step_ctr,
-                              STEP_COLLIDE | STEP_MOVE)
-            self.ctx.counter_add(self.step_ctr, 1)
+                              STEP_COLLIDE | STEP_MOVE | STEP_ADVANCE)
 
     def _graph(self, sample):
         if sample not in self.graphs:
@@ -495,7 +493,8 @@ class OpenSimulation:
         # the injected ones follow them: the re-sort applies
         fused = self.sorted
         if self.sorted:
-            self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1], None, self.mom)
+            self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1], None, self.mom,
+                           self.samp if sample else None)
         else:
             self.ctx.bin(self.a, self.b, self.offs[1])
         self.offs.reverse()
@@ -505,8 +504,8 @@ class OpenSimulation:
         self.a.n = live
         if not fused:
             self.ctx.moments(self.a, self.offsets, self.mom)
-        if sample:
-            self.ctx.sample(self.mom, self.samp)
+            if sample:
+                self.ctx.sample(self.mom, self.samp)
         if closure is None:
             self.ctx.closure_solve(self.mom, self.rec, self.status)
         else:

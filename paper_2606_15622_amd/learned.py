@@ -144,9 +144,7 @@ class LearnedSimulation(F.Simulation):
         self.tol = (tol_abs, tol_rel)
 
     def step(self, s, sample=False):
-        self.sort(mom=self.mom)
-        if sample:
-            self.ctx.sample(self.mom, self.samp)
+        self.sort(mom=self.mom, samp=self.samp if sample else None)
         if self.net is not None:
             self.net.closure(self.mom, self.rec, self.status, *self.tol)
         else:

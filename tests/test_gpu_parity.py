@@ -410,3 +410,32 @@ def test_graph_replay_matches_eager_bitwise():
         assert torch.equal(graph.mom, eager.mom)
         assert int(graph.step_ctr.cpu()[0]) == step
         del junk
+
+
+def test_step_dev_advance_matches_host_step_number():
+    """fp_step_dev with FP_STEP_ADVANCE: the step reads *step_dev, then adds 1 to it (in
+    the last kernel for COLLIDE | MOVE, in a kernel of its own for the other forms); the
+    particles equal those of fp_step with the host step number."""
+    F = fp()
+    w = I.cavity(kn=1.0, ncell=30, ppc=80, precision="f32", seed=12)
+    s = I.maxwellian_state(w)
+    host, devs = F.Simulation(w, s), F.Simulation(w, s)
+    for k in range(2):
+        host.step(k)
+        devs.step(k)
+    ctr = torch.zeros(1, dtype=torch.int32, device="cuda")
+    step = 2
+    for flags in (F.STEP_COLLIDE | F.STEP_MOVE, F.STEP_MOVE, F.STEP_COLLIDE,
+                  F.STEP_COLLIDE | F.STEP_MOVE):
+        ctr.fill_(step)
+        for sim in (host, devs):
+            sim.sort(mom=sim.mom)
+            sim.ctx.closure_solve(sim.mom, sim.rec, sim.status)
+        host.ctx.step(host.a, host.offsets, host.mom, host.rec, step, flags)
+        devs.ctx.step_dev(devs.a, devs.offsets, devs.mom, devs.rec, ctr, flags | F.STEP_ADVANCE)
+        torch.cuda.synchronize()
+        assert int(ctr.cpu()[0]) == step + 1, flags
+        ha, da = host.a.numpy(), devs.a.numpy()
+        for k in ha:
+            np.testing.assert_array_equal(da[k], ha[k], err_msg=f"flags {flags} {k}")
+        step += 1

@@ -49,9 +49,11 @@ def moment_scale(o):
 
 
 def run_rebin(F, w, s, off0, expect_errors=0):
-    """fp_rebin twice without moments, then twice with the moment gather: the sort must
-    equal the oracle's bit for bit each time, and the moments match the oracle's moments
-    of the oracle-sorted cells (1e-10 of the natural scale, as for fp_moments)."""
+    """fp_rebin twice without moments, then with the moment gather, then with moments and
+    time-average sums: the sort must equal the oracle's bit for bit each time, the
+    moments match the oracle's moments of the oracle-sorted cells (1e-10 of the natural
+    scale, as for fp_moments), the sums the oracle's sums (as for fp_sample) and, bit for
+    bit, what fp_sample adds from the gathered moments."""
     nc = I.ncells(w)
     n = s["x"].shape[0]
     ctx = F.Context(w, max(n, 1))
@@ -64,9 +66,13 @@ def run_rebin(F, w, s, off0, expect_errors=0):
     operm, ooff = O.bin_particles(nc, s["key"])
     kept = int(ooff[-1])
     srt = {k: np.asarray(s[k])[operm[:kept]] for k in s}
+    samp0 = np.random.default_rng(9).uniform(0.0, 1e3, (nc, 16))
+    samp = torch.from_numpy(samp0).cuda()
     for rep in range(4):     # repeated: the counters must be left clean by every call
         with_mom = rep >= 2
-        ctx.rebin(a, src_off, b, off, perm, mom if with_mom else None)
+        with_samp = rep == 3
+        ctx.rebin(a, src_off, b, off, perm, mom if with_mom else None,
+                  samp if with_samp else None)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(off.cpu().numpy(), ooff)
         np.testing.assert_array_equal(perm.cpu().numpy()[:kept], operm[:kept])
@@ -82,6 +88,14 @@ def run_rebin(F, w, s, off0, expect_errors=0):
             g = mom.cpu().numpy()
             np.testing.assert_array_equal(g[:, 0], o[:, 0])
             assert np.all(np.abs(g - o) <= 1e-10 * moment_scale(o))
+        if with_samp and nc > 0:
+            gs = samp.cpu().numpy()
+            osamp = O.sample(ooff, srt["vx"], srt["vy"], srt["vz"], samp0.copy())
+            scale = np.abs(osamp) + np.repeat(np.maximum(osamp[:, :1], 1), 16, 1) * 1e6
+            assert np.all(np.abs(gs - osamp) <= 1e-10 * scale)
+            ref = torch.from_numpy(samp0).cuda()
+            ctx.sample(mom, ref)
+            np.testing.assert_array_equal(gs, ref.cpu().numpy())
     assert ctx.error_count() == 4 * expect_errors
     return kept
 
@@ -169,6 +183,20 @@ def test_channel_1d_and_empty():
     run_rebin(F, w, s, off0)
     e = {k: v[:0] for k, v in s.items()}
     run_rebin(F, w, e, np.zeros(101, dtype=np.int32))
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
+def test_every_group_width(lanes):
+    """Every lanes-per-cell width of the count and gather kernels (their group prefix
+    sums and reductions), on a grid wider than the gather's column strips (70 = 32 + 32
+    + a ragged 6), with 1 % far movers."""
+    F = fp()
+    w = dict(I.cavity(ncell=70, ppc=90, precision="f32", kn=1.0), lanes=lanes)
+    s, off0 = grouped_after_flight(w, I.maxwellian_state(w, seed=11))
+    rng = np.random.default_rng(11)
+    far = rng.random(s["x"].shape[0]) < 0.01
+    s["key"][far] = rng.integers(0, I.ncells(w), far.sum())
+    run_rebin(F, w, s, off0)
 
 
 def test_full_size_cavity():
