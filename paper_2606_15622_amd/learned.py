@@ -181,12 +181,12 @@ def couette_dataset(kns=(0.1, 0.5), n_transient=500, n_samples=5000, seed=1, dev
     return torch.cat(moms, 0)
 
 
-def closure_timings(w, params, ncells=1_000_000, reps=20, seed=0, device="cuda"):
-    """Kernel times of the exact and learned closure on a synthetic batch of cells with
-    the moment records of a Couette harvest (HIP events on the launch stream)."""
-    from . import inputs as I
-    mom = couette_dataset(kns=(0.5,), n_transient=50, n_samples=max(ncells // 100, 1),
-                          seed=seed)[:ncells].contiguous()
+def closure_timings(w, params, ncells=1_000_000, reps=20, seed=0, device="cuda", harvest=1000):
+    """Kernel times of the exact and learned closure on a batch of ncells moment records
+    of a Couette harvest (harvest steps of 100 cells, repeated up to ncells), by HIP
+    events on the launch stream."""
+    mom = couette_dataset(kns=(0.5,), n_transient=50, n_samples=harvest, seed=seed)
+    mom = mom.repeat(ncells // mom.shape[0] + 1, 1)[:ncells].contiguous()
     n = mom.shape[0]
     wd = dict(w, geometry="couette1d", nx=n, ny=1, lx=float(w["dx"]) * n, ly=1.0, dy=1.0)
     ctx = F.Context(wd, 1)
@@ -256,7 +256,14 @@ def main(argv=None):
     ap.add_argument("--save", default=None, help="write the trained parameters (.npy)")
     ap.add_argument("--finetune", type=int, default=10,
                     help="epochs of closure-residual fine-tuning on cavity cells (0: none)")
+    ap.add_argument("--timing", default=None, metavar="PARAMS.npy",
+                    help="only time the exact and learned closures on 1e6 cells with these "
+                         "parameters (a file written by --save)")
     a = ap.parse_args(argv)
+    if a.timing:
+        p = torch.from_numpy(np.load(a.timing)).to("cuda")
+        print(json.dumps(closure_timings(I.cavity(kn=1.0, ncell=100, ppc=100), p, reps=5)))
+        return
     res = {}
     t0 = time.time()
     mom = couette_dataset(n_samples=a.samples)
