@@ -79,6 +79,12 @@ typedef struct fp_config {
     int32_t max_bounces;     /* wall interactions per particle and step */
     int32_t lanes;           /* lanes per cell of the per-cell kernels: 4, 8, 16, 32 or 64;
                                 0 = chosen from the particle and cell counts */
+    int32_t moment_order;    /* 5 (or 0): moment records through fifth order (the exact
+                                closure needs them); 3: only N, U, theta, P and T are
+                                gathered (R, W, H written as 0), for a closure from
+                                low-order moments (fp_closure_nn unchecked); fp_closure_solve
+                                and the checked fp_closure_nn then refuse the records */
+    int32_t reserved0;       /* 0 */
     int64_t capacity;        /* largest particle count any call will see */
     double x0, y0;           /* domain origin [m] */
     double lx, ly;           /* domain extent [m] */
@@ -247,10 +253,17 @@ int fp_nn_load(fp_ctx* ctx, fp_nn* net, const float* params, hipStream_t s);
  * outputs de-standardised, then checked against the cell's own normalised 9x9 system;
  * accepted if |A y - b| <= tol_abs + tol_rel |b| (status FP_CELL_NN), otherwise solved
  * exactly (FP_CELL_NN_FALLBACK).  tol_abs = +infinity skips the check (and the assembly
- * of the system): every finite output is accepted, non-finite ones fall back.  Cells that
- * are EMPTY/NONFINITE/FEW are treated as in fp_closure_solve.  Same rec layout. */
+ * of the system): every finite output is accepted, non-finite ones fall back (on a
+ * context with moment_order 3, which has no system to solve, they take the Langevin drift:
+ * FP_CELL_SINGULAR; such a context accepts only tol_abs = +infinity).  relax in (0, 1]:
+ * accepted coefficients are blended with the cell's previous ones in rec, C = relax C_net
+ * + (1 - relax) C_prev, the same for Gamma, when that record carries coefficients (the
+ * temporal under-relaxation of the cylinder deployment, Sec. "Extension to External
+ * Aerodynamics"); 1
+ * takes the network's values.  Cells that are EMPTY/NONFINITE/FEW are treated as in
+ * fp_closure_solve.  Same rec layout. */
 int fp_closure_nn(fp_ctx* ctx, const fp_nn* net, const double* mom, double* rec,
-                  int32_t* status, double tol_abs, double tol_rel, hipStream_t s);
+                  int32_t* status, double tol_abs, double tol_rel, double relax, hipStream_t s);
 /* Copy the standardised network outputs of the last fp_closure_nn ([ncell][16]). */
 int fp_nn_outputs(fp_ctx* ctx, const fp_nn* net, float* y, hipStream_t s);
 /* Raw (unstandardised) features of n moment records: feats[n][32] floats. */

@@ -39,6 +39,8 @@ static int validate(const fp_config* g, std::string& why) {
     if (g->lanes != 0 && g->lanes != 4 && g->lanes != 8 && g->lanes != 16 && g->lanes != 32 &&
         g->lanes != 64)
         return why = "lanes", 0;
+    if ((g->moment_order != 0 && g->moment_order != 3 && g->moment_order != 5) || g->reserved0 != 0)
+        return why = "moment_order", 0;
     if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->lx) || !finite_pos(g->ly) ||
         !finite_pos(g->dt) || !finite_pos(g->kB) || !finite_pos(g->mass) ||
         !finite_pos(g->mu_ref) || !finite_pos(g->T_ref) || !finite_pos(g->fnum_over_vol))
@@ -267,6 +269,8 @@ extern "C" int fp_moments(fp_ctx* c, const fp_particles* p, const int32_t* offse
 extern "C" int fp_closure_solve(fp_ctx* c, const double* mom, double* rec, int32_t* status,
                                 hipStream_t s) {
     if (!c || !mom || !rec || !status) return set_err(c, FP_EINVAL, "fp_closure_solve: bad argument");
+    if (c->cfg.moment_order == 3)
+        return set_err(c, FP_EINVAL, "fp_closure_solve: the context gathers moments through third order only");
     return launch_closure(c, mom, rec, status, s);
 }
 

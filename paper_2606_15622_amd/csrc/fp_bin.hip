@@ -426,29 +426,41 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
     int c9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     int32_t nfar = 0, b = 0, e = 0, cx = 0, rs = 0;
     constexpr int KR = 4;
+    int32_t kfirst[KR];   // the keys of the first round, kept for the second pass
+#pragma unroll
+    for (int u = 0; u < KR; ++u) kfirst[u] = ncell;
     if (cell < ncell) {
         b = max(src_off[cell], 0);
         e = (int32_t)min((int64_t)src_off[cell + 1], n);
         cx = cell % nx;
         rs = cell - cx;
+        // branch-free: per round of KR particles the directions are counted in three words
+        // of three 10-bit fields (at most KR per field), unpacked once per round
+        int32_t nbad = 0;
         for (int32_t j0 = b + lg; j0 < e; j0 += G * KR) {
             int32_t kk[KR];
 #pragma unroll
             for (int u = 0; u < KR; ++u) kk[u] = j0 + u * G < e ? key[j0 + u * G] : ncell;
+            if (j0 == b + lg)
+#pragma unroll
+                for (int u = 0; u < KR; ++u) kfirst[u] = kk[u];
+            uint32_t w[3] = {0u, 0u, 0u};
 #pragma unroll
             for (int u = 0; u < KR; ++u) {
                 const int32_t k = kk[u];
-                if (k == ncell) continue;
-                if (k < 0 || k > ncell) {
-                    atomicAdd(errcount, 1ull);
-                    continue;
-                }
-                const int d = near_dir(k, rs, cx, nx);
-                nfar += d < 0 ? 1 : 0;
+                const bool valid = k >= 0 && k < ncell;
+                nbad += (!valid && k != ncell) ? 1 : 0;
+                const int d = valid ? near_dir(k, rs, cx, nx) : -1;
+                nfar += (valid && d < 0) ? 1 : 0;
+                const int dw = d < 0 ? 3 : d / 3;
+                const uint32_t one = 1u << (10 * (d - 3 * dw));
 #pragma unroll
-                for (int i = 0; i < 9; ++i) c9[i] += d == i ? 1 : 0;
+                for (int q = 0; q < 3; ++q) w[q] += dw == q ? one : 0u;
             }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) c9[i] += (int)((w[i / 3] >> (10 * (i % 3))) & 1023u);
         }
+        if (nbad) atomicAdd(errcount, (unsigned long long)nbad);
     }
     // bucket starts inside the cell's range (prefix over directions), same in every lane
     int32_t bst[9];
@@ -490,10 +502,15 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
         const int last = lane - lg + G - 1;
         for (int32_t j0 = b; j0 < e; j0 += G * KR) {
             int32_t kk[KR];
+            if (j0 == b) {
 #pragma unroll
-            for (int u = 0; u < KR; ++u) {
-                const int32_t j = j0 + u * G + lg;
-                kk[u] = j < e ? key[j] : -1;
+                for (int u = 0; u < KR; ++u) kk[u] = kfirst[u];   // ncell beyond e: no direction
+            } else {
+#pragma unroll
+                for (int u = 0; u < KR; ++u) {
+                    const int32_t j = j0 + u * G + lg;
+                    kk[u] = j < e ? key[j] : -1;
+                }
             }
 #pragma unroll
             for (int u = 0; u < KR; ++u) {
@@ -770,7 +787,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_kernel(
 // two moment passes.
 constexpr int GM_U = 4;
 
-template <typename T, int G>
+template <typename T, int G, int NVX>
 __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
     int32_t ncell, int32_t nx, int32_t ny, int64_t n, int64_t cap,
     const int32_t* __restrict__ src_off, const int32_t* __restrict__ bend,
@@ -936,13 +953,13 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
     s2 = group_sum<G>(s2);
     const double inv_n = ncnt > 0 ? 1.0 / (double)ncnt : 0.0;
     const double U0 = s0 * inv_n, U1 = s1 * inv_n, U2 = s2 * inv_n;
-    double acc[NV];
+    double acc[NVX];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int i = 0; i < NVX; ++i) acc[i] = 0.0;
     for (int32_t q = lg; q < ncnt; q += G)
-        mom_accum((double)r.dvx[base + q] - U0, (double)r.dvy[base + q] - U1,
-                  (double)r.dvz[base + q] - U2, acc);
-    mom_finish<BIN_BLOCK, G>(sm, acc, grp, lg, in, ncnt, U0, U1, U2,
+        mom_accum<NVX>((double)r.dvx[base + q] - U0, (double)r.dvy[base + q] - U1,
+                       (double)r.dvz[base + q] - U2, acc);
+    mom_finish<BIN_BLOCK, G, NVX>(sm, acc, grp, lg, in, ncnt, U0, U1, U2,
                              mom + (int64_t)(in ? k : 0) * MOM);
     if (samp) {
         // time-average sums from the record, once all of the group's lanes wrote it
@@ -979,10 +996,16 @@ static void rebin_gather_launch(fp_ctx* c, const fp_particles* src, const int32_
              dst->key,          perm};
     const int32_t cblocks = (nc + BIN_BLOCK / G - 1) / (BIN_BLOCK / G);
     if (mom) {
-        hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G>), dim3(cblocks), dim3(BIN_BLOCK), 0, s,
-                           nc, nx, ny, n, cap, src_off, (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
-                           (const int32_t*)offsets, (const int32_t*)c->coff, (const int32_t*)c->gidx,
-                           c->cnt, c->ccnt, c->ccur, c->farn, r, mom, samp);
+        if (c->cfg.moment_order == 3)
+            hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G, NV_LOW>), dim3(cblocks), dim3(BIN_BLOCK), 0, s,
+                               nc, nx, ny, n, cap, src_off, (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
+                               (const int32_t*)offsets, (const int32_t*)c->coff, (const int32_t*)c->gidx,
+                               c->cnt, c->ccnt, c->ccur, c->farn, r, mom, samp);
+        else
+            hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G, NV>), dim3(cblocks), dim3(BIN_BLOCK), 0, s,
+                               nc, nx, ny, n, cap, src_off, (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
+                               (const int32_t*)offsets, (const int32_t*)c->coff, (const int32_t*)c->gidx,
+                               c->cnt, c->ccnt, c->ccur, c->farn, r, mom, samp);
         return;
     }
     hipLaunchKernelGGL((rebin_gather_kernel<T, G>), dim3(cblocks + FAR_BLOCKS), dim3(BIN_BLOCK),

@@ -12,7 +12,12 @@ constexpr int CL_BLOCK = 64;
 // NN = false: exact solve.  NN = true: the network's standardised outputs ynn[cell][16]
 // are de-standardised (ysec = y_mean[16], y_std[16]) into normalised coefficients and
 // accepted if the residual of the normalised system satisfies
-// |A y - b| <= tol_abs + tol_rel |b|; otherwise the cell is solved exactly.
+// |A y - b| <= tol_abs + tol_rel |b|; otherwise the cell is solved exactly.  With
+// tol_abs = +inf every finite output is accepted; a non-finite one is solved exactly, or,
+// when the records hold moments through third order only (low), takes the Langevin drift
+// (status SINGULAR).  relax < 1 blends the accepted coefficients with the cell's previous
+// ones: C = relax C_net + (1 - relax) C_prev (the same for Gamma), where the previous
+// record carries coefficients.
 template <bool NN>
 __global__ __launch_bounds__(CL_BLOCK) void closure_kernel(fp_config g, int32_t ncell,
                                                             const double* __restrict__ mom,
@@ -21,7 +26,8 @@ __global__ __launch_bounds__(CL_BLOCK) void closure_kernel(fp_config g, int32_t 
                                                             const float* __restrict__ ynn,
                                                             const float* __restrict__ ysec,
                                                             double tol_abs, double tol_rel,
-                                                            const double* __restrict__ nvol) {
+                                                            const double* __restrict__ nvol,
+                                                            double relax) {
     const int32_t cell = blockIdx.x * CL_BLOCK + threadIdx.x;
     if (cell >= ncell) return;
     double m[31];
@@ -67,7 +73,9 @@ __global__ __launch_bounds__(CL_BLOCK) void closure_kernel(fp_config g, int32_t 
                     for (int i = 0; i < 9; ++i) accepted = accepted && isfinite(y[i]);
                 }
             }
-            if (!accepted) {
+            if (!accepted && NN && unchecked && g.moment_order == 3) {
+                st = FP_CELL_SINGULAR;   // no system to fall back on: Langevin drift
+            } else if (!accepted) {
                 CellSystem s;
                 build_system(m, g.eps_hat, s);
                 if (NN && !unchecked) {
@@ -103,6 +111,15 @@ __global__ __launch_bounds__(CL_BLOCK) void closure_kernel(fp_config g, int32_t 
 #pragma unroll
             for (int i = 0; i < 3; ++i) out[R_G + i] = y[6 + i] * ig;
             out[R_EPS2] = eps2;
+            if (NN && st == FP_CELL_NN && relax < 1.0) {
+                const double* prev = rec + (int64_t)cell * REC;
+                const int pst = (int)prev[R_ST];
+                if (pst == FP_CELL_OK || pst == FP_CELL_NN || pst == FP_CELL_NN_FALLBACK) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        out[R_C + i] = relax * out[R_C + i] + (1.0 - relax) * prev[R_C + i];
+                }
+            }
         }
         out[R_TAU] = tau;
         out[R_TH] = theta;
@@ -120,16 +137,16 @@ int launch_closure(fp_ctx* c, const double* mom, double* rec, int32_t* status, h
     const int grid = (c->ncell + CL_BLOCK - 1) / CL_BLOCK;
     hipLaunchKernelGGL(closure_kernel<false>, dim3(grid), dim3(CL_BLOCK), 0, s, c->cfg, c->ncell,
                        mom, rec, status, (const float*)nullptr, (const float*)nullptr, 0.0, 0.0,
-                       (const double*)c->nvol);
+                       (const double*)c->nvol, 1.0);
     return check_launch(c, "fp_closure_solve");
 }
 
 int launch_closure_nn(fp_ctx* c, const float* ynn, const float* ysec, double tol_abs,
-                      double tol_rel, const double* mom, double* rec, int32_t* status,
+                      double tol_rel, double relax, const double* mom, double* rec, int32_t* status,
                       hipStream_t s) {
     const int grid = (c->ncell + CL_BLOCK - 1) / CL_BLOCK;
     hipLaunchKernelGGL(closure_kernel<true>, dim3(grid), dim3(CL_BLOCK), 0, s, c->cfg, c->ncell,
-                       mom, rec, status, ynn, ysec, tol_abs, tol_rel, (const double*)c->nvol);
+                       mom, rec, status, ynn, ysec, tol_abs, tol_rel, (const double*)c->nvol, relax);
     return check_launch(c, "fp_closure_nn (check)");
 }
 

@@ -15,7 +15,7 @@ namespace fpg {
 constexpr int MOM_BLOCK = 256;
 constexpr int MOM_K = 8;
 
-template <typename T, int G, int K>
+template <typename T, int G, int K, int NVX>
 __global__ __launch_bounds__(MOM_BLOCK) void moments_kernel(
     int32_t ncell, const int32_t* __restrict__ offsets, const T* __restrict__ vx,
     const T* __restrict__ vy, const T* __restrict__ vz, double* __restrict__ mom) {
@@ -53,18 +53,18 @@ __global__ __launch_bounds__(MOM_BLOCK) void moments_kernel(
     const double inv_n = n > 0 ? 1.0 / (double)n : 0.0;
     const double U0 = s0 * inv_n, U1 = s1 * inv_n, U2 = s2 * inv_n;
 
-    double acc[NV];
+    double acc[NVX];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int i = 0; i < NVX; ++i) acc[i] = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int32_t j = lg + k * G;
-        if (j < n) mom_accum((double)cx[k] - U0, (double)cy[k] - U1, (double)cz[k] - U2, acc);
+        if (j < n) mom_accum<NVX>((double)cx[k] - U0, (double)cy[k] - U1, (double)cz[k] - U2, acc);
     }
     for (int32_t j = lg + K * G; j < n; j += G)
-        mom_accum((double)vx[b + j] - U0, (double)vy[b + j] - U1, (double)vz[b + j] - U2, acc);
+        mom_accum<NVX>((double)vx[b + j] - U0, (double)vy[b + j] - U1, (double)vz[b + j] - U2, acc);
     __shared__ MomShared<MOM_BLOCK, G> sm;
-    mom_finish<MOM_BLOCK, G>(sm, acc, (int)(threadIdx.x / G), lg, in, n, U0, U1, U2,
+    mom_finish<MOM_BLOCK, G, NVX>(sm, acc, (int)(threadIdx.x / G), lg, in, n, U0, U1, U2,
                              mom + (int64_t)(in ? cell : 0) * MOM);
 }
 
@@ -73,8 +73,12 @@ static void mom_launch(fp_ctx* c, const fp_particles* p, const int32_t* off, dou
                        hipStream_t s) {
     const int64_t threads = (int64_t)c->ncell * G;
     const unsigned grid = (unsigned)((threads + MOM_BLOCK - 1) / MOM_BLOCK);
-    hipLaunchKernelGGL((moments_kernel<T, G, MOM_K>), dim3(grid), dim3(MOM_BLOCK), 0, s,
-                       c->ncell, off, (const T*)p->vx, (const T*)p->vy, (const T*)p->vz, mom);
+    if (c->cfg.moment_order == 3)
+        hipLaunchKernelGGL((moments_kernel<T, G, MOM_K, NV_LOW>), dim3(grid), dim3(MOM_BLOCK), 0, s,
+                           c->ncell, off, (const T*)p->vx, (const T*)p->vy, (const T*)p->vz, mom);
+    else
+        hipLaunchKernelGGL((moments_kernel<T, G, MOM_K, NV>), dim3(grid), dim3(MOM_BLOCK), 0, s,
+                           c->ncell, off, (const T*)p->vx, (const T*)p->vy, (const T*)p->vz, mom);
 }
 
 template <typename T>

@@ -597,13 +597,18 @@ extern "C" int fp_nn_load(fp_ctx* c, fp_nn* n, const float* params, hipStream_t 
 
 namespace fpg {
 int launch_closure_nn(fp_ctx* c, const float* ynn, const float* ysec, double tol_abs,
-                      double tol_rel, const double* mom, double* rec, int32_t* status, hipStream_t s);
+                      double tol_rel, double relax, const double* mom, double* rec, int32_t* status,
+                      hipStream_t s);
 }
 
 extern "C" int fp_closure_nn(fp_ctx* c, const fp_nn* n, const double* mom, double* rec,
-                             int32_t* status, double tol_abs, double tol_rel, hipStream_t s) {
-    if (!c || !n || !mom || !rec || !status || n->ctx != c || !(tol_abs >= 0) || !(tol_rel >= 0))
+                             int32_t* status, double tol_abs, double tol_rel, double relax,
+                             hipStream_t s) {
+    if (!c || !n || !mom || !rec || !status || n->ctx != c || !(tol_abs >= 0) || !(tol_rel >= 0) ||
+        !(relax > 0.0 && relax <= 1.0))
         return set_err(c, FP_EINVAL, "fp_closure_nn: bad argument");
+    if (c->cfg.moment_order == 3 && tol_abs != INFINITY)
+        return set_err(c, FP_EINVAL, "fp_closure_nn: the check needs moments through fifth order");
     const int32_t ntiles = (c->ncell + 31) / 32;
     int grid = (ntiles + NN_BLOCK / 64 - 1) / (NN_BLOCK / 64);
     if (grid > 256) grid = 256;   // one workgroup per CU, each loops over its tiles
@@ -611,7 +616,7 @@ extern "C" int fp_closure_nn(fp_ctx* c, const fp_nn* n, const double* mom, doubl
                        c->cfg.eps_hat, (const __bf16*)n->img, (const float*)n->sec, n->ybuf);
     int rc = check_launch(c, "fp_closure_nn (network)");
     if (rc) return rc;
-    return launch_closure_nn(c, n->ybuf, n->sec + SEC_YM, tol_abs, tol_rel, mom, rec, status, s);
+    return launch_closure_nn(c, n->ybuf, n->sec + SEC_YM, tol_abs, tol_rel, relax, mom, rec, status, s);
 }
 
 extern "C" int fp_nn_outputs(fp_ctx* c, const fp_nn* n, float* y, hipStream_t s) {

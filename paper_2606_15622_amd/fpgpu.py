@@ -30,7 +30,8 @@ class FPConfig(C.Structure):
     _fields_ = [
         ("geometry", C.c_int32), ("precision", C.c_int32), ("conserve", C.c_int32),
         ("nx", C.c_int32), ("ny", C.c_int32), ("n_min", C.c_int32), ("max_bounces", C.c_int32),
-        ("lanes", C.c_int32), ("capacity", C.c_int64),
+        ("lanes", C.c_int32), ("moment_order", C.c_int32), ("reserved0", C.c_int32),
+        ("capacity", C.c_int64),
         ("x0", C.c_double), ("y0", C.c_double), ("lx", C.c_double), ("ly", C.c_double),
         ("dx", C.c_double), ("dy", C.c_double), ("dt", C.c_double),
         ("kB", C.c_double), ("mass", C.c_double),
@@ -82,7 +83,7 @@ def load():
         L.fp_nn_create.argtypes = [vp, i64, P(vp)]
         L.fp_nn_destroy.argtypes = [vp]
         L.fp_nn_load.argtypes = [vp, vp, vp, vp]
-        L.fp_closure_nn.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, vp]
+        L.fp_closure_nn.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
         L.fp_nn_outputs.argtypes = [vp, vp, vp, vp]
         L.fp_nn_features.argtypes = [vp, vp, i64, vp, vp]
         L.fp_closure_build.argtypes = [vp, vp, i64, vp, vp]
@@ -120,6 +121,7 @@ def make_config(w: dict, capacity: int) -> FPConfig:
     c.n_min = int(w.get("n_min", 4))
     c.max_bounces = int(w.get("max_bounces", 8))
     c.lanes = int(w.get("lanes", 0))
+    c.moment_order = int(w.get("moment_order", 5))
     c.capacity = int(capacity)
     c.x0, c.y0, c.lx, c.ly = float(w["x0"]), float(w["y0"]), float(w["lx"]), float(w["ly"])
     c.dx, c.dy, c.dt = float(w["dx"]), float(w["dy"]), float(w["dt"])
@@ -337,10 +339,10 @@ class Network:
         c = self.ctx
         c._check(c.lib.fp_nn_load(c.h, self.h, _ptr(params), _stream(stream)), "fp_nn_load")
 
-    def closure(self, mom, rec, status, tol_abs, tol_rel, stream=None):
+    def closure(self, mom, rec, status, tol_abs, tol_rel, relax=1.0, stream=None):
         c = self.ctx
         c._check(c.lib.fp_closure_nn(c.h, self.h, _ptr(mom), _ptr(rec), _ptr(status), float(tol_abs),
-                                     float(tol_rel), _stream(stream)), "fp_closure_nn")
+                                     float(tol_rel), float(relax), _stream(stream)), "fp_closure_nn")
 
     def outputs(self, y, stream=None):
         c = self.ctx

@@ -1,5 +1,10 @@
 """Learned closure pipeline on one GPU (the surrogate of Secs. "Phase 0"-"Phase 3").
 
+LITE (Sec. "Phase 3", step 2): moments through third order only, the network
+unchecked (LearnedSimulation(lite=True)), optionally the Gamma block weighted in the
+loss (fit_scalers(gamma_weight); Sec. "Case Study 2: 2D Lid-Driven Cavity") and the
+coefficients under-relaxed in time (relax; Sec. "Extension to External Aerodynamics").
+
 harvest()      runs the exact-closure loop and keeps the moment records of solved cells
                (the paper's Phase 0 saves the physics solver's inputs and outputs);
 dataset()      features, targets and normalised systems by the library's kernels;
@@ -21,6 +26,7 @@ import torch
 from . import fpgpu as F
 
 NF, NO = F.NN_FEATURES, F.NN_OUTPUTS
+LOW_END = 21   # moment record entries of a third-order gather: N, U, theta, P, T
 
 
 def harvest(w, state, n_transient, n_samples, every=1, seed_offset=0):
@@ -40,8 +46,17 @@ def harvest(w, state, n_transient, n_samples, every=1, seed_offset=0):
     return torch.cat(keep, 0)
 
 
-def dataset(w, mom):
-    """(feats [n][32] f32, targets [n][16] f32, sys [n][90] f64) of moment records."""
+def low_order(mom):
+    """The moment records a context with moment_order 3 gathers: R, W and H zeroed."""
+    m = mom.clone()
+    m[:, LOW_END:] = 0.0
+    return m
+
+
+def dataset(w, mom, lite=False):
+    """(feats [n][32] f32, targets [n][16] f32, sys [n][90] f64) of moment records; with
+    lite, the features are those of the low-order records (targets and systems from the
+    full ones)."""
     n = mom.shape[0]
     wd = dict(w)
     wd.update(geometry="couette1d", nx=n, ny=1, lx=float(w["dx"]) * n, ly=1.0, dy=1.0)
@@ -52,20 +67,25 @@ def dataset(w, mom):
     feats = torch.zeros((n, NF), dtype=torch.float32, device=mom.device)
     tg = torch.zeros((n, NO), dtype=torch.float32, device=mom.device)
     sys = torch.zeros((n, 90), dtype=torch.float64, device=mom.device)
-    ctx.nn_features(mom, n, feats)
+    ctx.nn_features(low_order(mom) if lite else mom, n, feats)
     ctx.nn_targets(rec, n, tg)
     ctx.closure_build(mom, n, sys)
     ok = st == F.CELL_OK
     return feats[ok].contiguous(), tg[ok].contiguous(), sys[ok].contiguous()
 
 
-def fit_scalers(feats, tg):
+def fit_scalers(feats, tg, gamma_weight=1.0):
+    """Standardising scalers.  gamma_weight > 1 gives the heat-flux block Gamma that
+    weight in the MSE of standardised targets (the q-weighted loss): dividing its target
+    scale by sqrt(gamma_weight) multiplies its standardised errors by that factor, for
+    every batch and with no change to the loss kernels."""
     xm = feats.double().mean(0)
     xs = feats.double().std(0)
     ym = tg.double().mean(0)
     ys = tg.double().std(0)
     xs = torch.where(xs > 1e-6, xs, torch.ones_like(xs))
     ys = torch.where(ys > 1e-9, ys, torch.ones_like(ys))
+    ys[6:9] = ys[6:9] / math.sqrt(gamma_weight)
     ym[9:] = 0.0
     ys[9:] = 1.0
     return xm.float(), xs.float(), ym.float(), ys.float()
@@ -133,15 +153,22 @@ class LearnedSimulation(F.Simulation):
     langevin is set), everything else as in Simulation."""
 
     def __init__(self, w, state, params=None, tol_abs=0.05, tol_rel=0.05, langevin=False,
-                 device="cuda"):
+                 lite=False, relax=1.0, device="cuda"):
+        """lite: moments through third order only (the high-order gather skipped) and the
+        network unchecked (there is no system to check against); relax: temporal
+        under-relaxation of the network's coefficients."""
         if langevin:
             w = dict(w, n_min=1 << 30)
+        if lite:
+            w = dict(w, moment_order=3)
+            tol_abs, tol_rel = math.inf, 0.0
         super().__init__(w, state, device)
         self.net = None
         if params is not None:
             self.net = F.Network(self.ctx, 0)
             self.net.load(params)
-        self.tol = (tol_abs, tol_rel)
+        self.tol = (tol_abs, tol_rel, relax)
+        self.rec[:, 14] = float(F.CELL_EMPTY)   # no previous coefficients to relax towards
 
     def step(self, s, sample=False):
         self.sort(mom=self.mom, samp=self.samp if sample else None)
@@ -216,6 +243,30 @@ def closure_timings(w, params, ncells=1_000_000, reps=20, seed=0, device="cuda",
             "learned_fallback_fraction": fb}
 
 
+def sort_moments_times(w, reps=20):
+    """Mean time (ms, HIP events) of the loop's re-sort with the moment gather and sums,
+    with moments through fifth order and through third order only (LITE), on the cavity's
+    initial state (re-sorts of a static state: the same work for both)."""
+    from . import inputs as I
+    out = {}
+    for name, order in (("full", 5), ("low", 3)):
+        ww = dict(w, moment_order=order)
+        sim = F.Simulation(ww, I.maxwellian_state(ww))
+        for _ in range(3):
+            sim.sort(mom=sim.mom, samp=sim.samp)
+        torch.cuda.synchronize()
+        ev = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sim.sort(mom=sim.mom, samp=sim.samp)
+            e1.record()
+            ev.append((e0, e1))
+        torch.cuda.synchronize()
+        out[name] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    return out
+
+
 def cavity_cells(kns=(0.1, 0.5, 1.0), ncell=100, n_transient=300, n_samples=200, every=10,
                  seed=7):
     """Moment records of solved cavity cells (snapshots every `every` steps after a
@@ -228,10 +279,10 @@ def cavity_cells(kns=(0.1, 0.5, 1.0), ncell=100, n_transient=300, n_samples=200,
     return torch.cat(moms, 0)
 
 
-def finetune(w, params, mom, batch=200_000, epochs=20, lr=1e-4, seed=0, log=None):
+def finetune(w, params, mom, batch=200_000, epochs=20, lr=1e-4, seed=0, log=None, lite=False):
     """Fine-tune on the closure residual |A y - b|^2 of the cells' own normalised systems
     (no targets needed), batches of `batch` cells; returns (params, history)."""
-    feats, tg, sys = dataset(w, mom)
+    feats, tg, sys = dataset(w, mom, lite=lite)
     return train(w, params, feats, tg, sys=sys, loss_kind=F.LOSS_RESIDUAL, epochs=epochs,
                  batch=batch, lr=lr, patience=epochs, seed=seed, log=log)
 
@@ -256,6 +307,11 @@ def main(argv=None):
     ap.add_argument("--save", default=None, help="write the trained parameters (.npy)")
     ap.add_argument("--finetune", type=int, default=10,
                     help="epochs of closure-residual fine-tuning on cavity cells (0: none)")
+    ap.add_argument("--lite", type=int, default=1,
+                    help="also train and run the LITE surrogate (moments through third order, "
+                         "unchecked network; 0: skip)")
+    ap.add_argument("--gamma-weight", type=float, default=4.0,
+                    help="weight of the Gamma block in the LITE network's MSE (q-weighted loss)")
     ap.add_argument("--timing", default=None, metavar="PARAMS.npy",
                     help="only time the exact and learned closures on 1e6 cells with these "
                          "parameters (a file written by --save)")
@@ -290,6 +346,21 @@ def main(argv=None):
         res["finetune_s"] = time.time() - t2
     else:
         params_ft = None
+    params_lite = None
+    if a.lite:
+        # LITE: features of the third-order records, Gamma block weighted in the MSE
+        t3 = time.time()
+        lfeats, ltg, _ = dataset(I.couette(), mom, lite=True)
+        lsc = fit_scalers(lfeats, ltg, gamma_weight=a.gamma_weight)
+        params_lite, hist_lite = train(I.couette(), init_params(lsc, seed=1), lfeats, ltg,
+                                       epochs=a.epochs, lr=a.lr, patience=10,
+                                       log=lambda s: print("lite", s, flush=True))
+        res["lite_val_loss"] = hist_lite
+        if a.finetune:
+            params_lite, _ = finetune(I.couette(), params_lite, cmom, epochs=a.finetune,
+                                      lite=True, log=lambda s: print("lite finetune", s, flush=True))
+        torch.cuda.synchronize()
+        res["lite_train_s"] = time.time() - t3
     w = I.cavity(kn=1.0, ncell=100, ppc=100, precision="f32", n_steps=a.steps,
                  n_skip=a.steps - a.avg)
     runs = {}
@@ -298,6 +369,8 @@ def main(argv=None):
              ("langevin", 1, {"langevin": True})]
     if params_ft is not None:
         cases.append(("learned_ft", 1, {"params": params_ft, "tol_abs": a.tol, "tol_rel": a.tol}))
+    if params_lite is not None:
+        cases.append(("lite", 1, {"params": params_lite, "lite": True}))
     for name, seed, kw in cases:
         ww = dict(w, seed=seed)
         sim = LearnedSimulation(ww, I.maxwellian_state(ww), **kw)
@@ -306,7 +379,7 @@ def main(argv=None):
         t = time.time()
         for s in range(a.steps):
             sim.step(s, sample=s >= w["n_skip"])
-            if name.startswith("learned") and s % 50 == 0:
+            if (name.startswith("learned") or name == "lite") and s % 50 == 0:
                 nn_cells += int((sim.status == F.CELL_NN).sum())
                 fb_cells += int((sim.status == F.CELL_NN_FALLBACK).sum())
         torch.cuda.synchronize()
@@ -315,10 +388,13 @@ def main(argv=None):
         res[f"{name}_particle_steps_per_s"] = 1e6 * a.steps / el
         if name.startswith("learned"):
             res[f"{name}_fallback_fraction"] = fb_cells / max(nn_cells + fb_cells, 1)
+        if name == "lite":
+            res["lite_langevin_fraction"] = float((sim.status == F.CELL_SINGULAR).sum()) / sim.ctx.ncell
     for name in [c[0] for c in cases if c[0] != "exact"]:
         res[f"relL2_{name}_vs_exact"] = {k: rel_l2(runs[name][k], runs["exact"][k])
                                          for k in ("U", "T", "rho", "p")}
     res["closure_timing"] = closure_timings(w, params)
+    res["sort_moments_ms"] = sort_moments_times(w)
     print(json.dumps(res))
     if a.out:
         with open(a.out, "w") as f:
