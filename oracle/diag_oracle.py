@@ -1,0 +1,60 @@
+"""Plain FP64 NumPy oracle of the post-processing diagnostics of the sampled fields.
+
+TEST INFRASTRUCTURE ONLY.  From the cumulative time-average sums of a cell (sample
+layout: sum N, sum v_i, sum v_i v_j (11 12 13 22 23 33), sum v_i |v|^2, number of samples)
+it forms the averaged state and the covariance-based entropy proxies of Sec. "Covariance-
+based entropy-proxy audit on the stagnation line and cylinder surface":
+  Theta_ij = <c_i c_j>, theta = tr(Theta) / 3                         (eq. cyl_theta_def)
+  ds_eq    = 3/2 log(theta / theta_inf) - log(n / n_inf)              (eq. cyl_entropy_eq)
+  D_G      = -1/2 log det(Theta / theta)                              (eq. cyl_DG)
+  ds_kinG  = ds_eq - (D_G - D_G,inf)                                  (eq. cyl_entropy_kinG)
+  D_q      = |q^|^2 / 5,  q^_i = <c_i |c|^2> / (2 theta^(3/2))
+and the normalised stress Theta_ij / theta - delta_ij.  The averages are ratios of the
+cumulative sums (the state of the time-averaged particle ensemble); with v = U + c,
+<c_i |c|^2> = <v_i |v|^2> - U_i |U|^2 - 3 theta U_i - 2 Theta_ik U_k.
+
+Output per cell, 24 entries: 0 particles per sample, 1 number density, 2-4 U, 5 theta,
+6 T, 7-12 normalised stress, 13-15 q^, 16 ds_eq, 17 D_G, 18 ds_kinG, 19 D_q, 20-23 zero.
+Cells without particles, or with theta <= 0, get NaN in 2-19.
+"""
+import numpy as np
+
+S2 = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+
+
+def diagnostics(samp, dens_factor, mass_over_kB, theta_inf, n_inf, dg_inf):
+    """samp [ncell][16] cumulative sums; dens_factor [ncell] (real molecules per particle
+    / gas volume of the cell); returns [ncell][24]."""
+    samp = np.asarray(samp, dtype=np.float64)
+    ncell = samp.shape[0]
+    out = np.full((ncell, 24), np.nan)
+    out[:, 20:] = 0.0
+    for k in range(ncell):
+        sN, nsamp = samp[k, 0], samp[k, 13]
+        out[k, 0] = sN / nsamp if nsamp > 0 else 0.0
+        out[k, 1] = out[k, 0] * dens_factor[k]
+        if not (sN > 0):
+            continue
+        U = samp[k, 1:4] / sN
+        Th = np.zeros((3, 3))
+        for q, (i, j) in enumerate(S2):
+            Th[i, j] = Th[j, i] = samp[k, 4 + q] / sN - U[i] * U[j]
+        theta = np.trace(Th) / 3.0
+        if not (theta > 0):
+            continue
+        vv = samp[k, 10:13] / sN
+        ccc = vv - U * (U @ U) - 3.0 * theta * U - 2.0 * (Th @ U)
+        qh = ccc / (2.0 * theta ** 1.5)
+        out[k, 2:5] = U
+        out[k, 5] = theta
+        out[k, 6] = theta * mass_over_kB
+        for q, (i, j) in enumerate(S2):
+            out[k, 7 + q] = Th[i, j] / theta - (1.0 if i == j else 0.0)
+        out[k, 13:16] = qh
+        ds_eq = 1.5 * np.log(theta / theta_inf) - np.log(out[k, 1] / n_inf)
+        dg = -0.5 * np.log(np.linalg.det(Th / theta))
+        out[k, 16] = ds_eq
+        out[k, 17] = dg
+        out[k, 18] = ds_eq - (dg - dg_inf)
+        out[k, 19] = (qh @ qh) / 5.0
+    return out
