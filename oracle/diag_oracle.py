@@ -15,11 +15,14 @@ cumulative sums (the state of the time-averaged particle ensemble); with v = U +
 
 Output per cell, 24 entries: 0 particles per sample, 1 number density, 2-4 U, 5 theta,
 6 T, 7-12 normalised stress, 13-15 q^, 16 ds_eq, 17 D_G, 18 ds_kinG, 19 D_q, 20-23 zero.
-Cells without particles, or with theta <= 0, get NaN in 2-19.
+Cells without particles, or with theta <= 0, get NaN in 2-19; a covariance that is not
+positive definite (det(Theta/theta) <= DET_MIN = 1e-12, as for fewer than four particles,
+where rounding decides the sign of a zero determinant) gets NaN in D_G and ds_kinG.
 """
 import numpy as np
 
 S2 = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+DET_MIN = 1e-12
 
 
 def diagnostics(samp, dens_factor, mass_over_kB, theta_inf, n_inf, dg_inf):
@@ -52,7 +55,8 @@ def diagnostics(samp, dens_factor, mass_over_kB, theta_inf, n_inf, dg_inf):
             out[k, 7 + q] = Th[i, j] / theta - (1.0 if i == j else 0.0)
         out[k, 13:16] = qh
         ds_eq = 1.5 * np.log(theta / theta_inf) - np.log(out[k, 1] / n_inf)
-        dg = -0.5 * np.log(np.linalg.det(Th / theta))
+        det = np.linalg.det(Th / theta)
+        dg = -0.5 * np.log(det) if det > DET_MIN else np.nan   # positive-definite Theta only
         out[k, 16] = ds_eq
         out[k, 17] = dg
         out[k, 18] = ds_eq - (dg - dg_inf)

@@ -80,3 +80,11 @@ def test_equilibrium_entropy_reference_and_empty_cells():
     assert abs(out[0, 16]) < 1e-14
     np.testing.assert_allclose(out[1, 16], 1.5 * np.log(2.0), rtol=1e-14)
     assert out[2, 0] == 0.0 and np.isnan(out[2, 2:20]).all() and (out[2, 20:] == 0).all()
+
+
+def test_singular_covariance_has_no_entropy_deficit():
+    """Two particles span one direction: det(Theta/theta) = 0 exactly, D_G undefined."""
+    v = np.array([[300.0, 100.0, -50.0], [-100.0, 20.0, 70.0]])
+    out = D.diagnostics(sums_of(v)[None], np.array([1.0]), 1.0, 1.0, 1.0, 0.0)[0]
+    assert np.isfinite(out[5]) and out[5] > 0
+    assert np.isnan(out[17]) and np.isnan(out[18]) and np.isfinite(out[16])
