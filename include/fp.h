@@ -220,6 +220,24 @@ int fp_cell_volumes(fp_ctx* ctx, double* vol, hipStream_t s);
  * reconstructed from mom, to samp (layout samp above). */
 int fp_sample(fp_ctx* ctx, const double* mom, double* samp, hipStream_t s);
 
+/* Diagnostics of the time-averaged fields in samp (after the loop): the averaged state
+ * (ratios of the cumulative sums), the normalised stress Theta_ij / theta - delta_ij, the
+ * normalised heat flux q^_i = <c_i |c|^2> / (2 theta^1.5), and the covariance-based
+ * entropy proxies of Sec. "Covariance-based entropy-proxy audit on the stagnation line and
+ * cylinder surface" (eqs. cyl_theta_def, cyl_entropy_eq, cyl_DG, cyl_entropy_kinG):
+ * ds_eq = 3/2 log(theta/theta_inf) - log(n/n_inf), D_G = -1/2 log det(Theta/theta),
+ * ds_kinG = ds_eq - (D_G - dg_inf), D_q = |q^|^2 / 5.  theta_inf [m^2/s^2] and n_inf
+ * [1/m^3] are the caller's reference state (e.g. the free stream), dg_inf its D_G.
+ * diag[ncell][FP_DIAG_STRIDE] doubles: 0 particles per sample, 1 number density [1/m^3]
+ * (cut-cell gas volume on the cylinder), 2-4 U [m/s], 5 theta, 6 T [K], 7-12 stress
+ * (11 12 13 22 23 33), 13-15 q^, 16 ds_eq, 17 D_G, 18 ds_kinG, 19 D_q, 20-23 zero;
+ * entries 2-19 are NaN for cells without particles or with theta <= 0, D_G and ds_kinG
+ * also where det(Theta/theta) <= 1e-12 (a singular sample covariance: fewer than four
+ * particles, say). */
+#define FP_DIAG_STRIDE 24
+int fp_diagnostics(fp_ctx* ctx, const double* samp, double theta_inf, double n_inf,
+                   double dg_inf, double* diag, hipStream_t s);
+
 
 /* ---- learned closure (project extension) -------------------------------------------
  * The paper replaces the closure build and solve by a dense network evaluated on the GPU
@@ -264,6 +282,19 @@ int fp_nn_load(fp_ctx* ctx, fp_nn* net, const float* params, hipStream_t s);
  * fp_closure_solve.  Same rec layout. */
 int fp_closure_nn(fp_ctx* ctx, const fp_nn* net, const double* mom, double* rec,
                   int32_t* status, double tol_abs, double tol_rel, double relax, hipStream_t s);
+/* Coefficient-sensitivity probe (Sec. "Heuristic coefficient-sensitivity probe"): npass
+ * >= 1 forward passes of the network on every cell's moments (mom [ncell][32], device)
+ * with inference-time dropout of rate p in [0, 1) on the three hidden layers (inverted:
+ * kept activations scaled by 1/(1-p); hidden unit u of layer l is dropped in pass k of
+ * cell c when word u % 4 of Philox4x32-10 with key (seed low, seed high) and counter
+ * (c, k, 6, 32 (l-1) + u / 4) is below floor(p 2^32)).  Per cell the standard deviation
+ * (1/npass) over the passes of each de-standardised normalised coefficient (the targets
+ * above), and sens[c] = (sigma_Stress, sigma_Heat), the Euclidean norms over the six
+ * stress and the three heat-flux coefficients (device, [ncell][2] doubles, caller-owned);
+ * cells with N <= 1 or theta <= 0 get zeros.  Not a deployment path: the closure itself
+ * never drops units.  FP_EINVAL for a bad argument. */
+int fp_nn_sensitivity(fp_ctx* ctx, const fp_nn* net, const double* mom, int32_t npass,
+                      double p, uint64_t seed, double* sens, hipStream_t s);
 /* Copy the standardised network outputs of the last fp_closure_nn ([ncell][16]). */
 int fp_nn_outputs(fp_ctx* ctx, const fp_nn* net, float* y, hipStream_t s);
 /* Raw (unstandardised) features of n moment records: feats[n][32] floats. */

@@ -146,3 +146,75 @@ def grads_flat(g):
             out[o:o + n] = g[name].ravel()
         o += n
     return out
+
+
+# ---------------------------------------------------------------------------------------
+# Coefficient-sensitivity probe (Sec. "Heuristic coefficient-sensitivity probe"): npass
+# forward passes with an inference-time dropout mask of rate p on the hidden activations;
+# per coefficient the standard deviation over the passes (1/N, about the mean of the
+# passes), and per cell the Euclidean norms of the deviations of the stress block and of
+# the heat-flux block.
+#
+# Readings: the perturbed outputs are the de-standardised normalised coefficients
+# [tau Ct - 5 eps_hat I (6), tau sqrt(th) Gamma (3)]; dropout is inverted (kept
+# activations scaled by 1/(1-p)) and acts after the SiLU of each of the three hidden
+# layers, not on the input or the output; the masks come from Philox4x32-10 (Salmon et
+# al., SC'11) keyed by the seed (low word, high word) with counter (cell, pass, 6,
+# 32 (layer-1) + unit // 4), word unit % 4 deciding hidden unit `unit`; a unit is dropped
+# when that word is below floor(p 2^32).  Cells without features (N <= 1 or theta <= 0)
+# report zero.
+
+PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+PURPOSE_DROPOUT = 6
+
+
+def philox(c0, c1, c2, c3, k0, k1):
+    """Philox4x32-10 on arrays of counters (uint64 arrays holding 32-bit words)."""
+    m32 = np.uint64(0xFFFFFFFF)
+    x = [np.asarray(v, dtype=np.uint64) & m32 for v in (c0, c1, c2, c3)]
+    k = [np.uint64(int(k0) & 0xFFFFFFFF), np.uint64(int(k1) & 0xFFFFFFFF)]
+    for r in range(10):
+        if r:
+            k = [(k[0] + np.uint64(PHILOX_W[0])) & m32, (k[1] + np.uint64(PHILOX_W[1])) & m32]
+        p0 = np.uint64(PHILOX_M[0]) * x[0]
+        p1 = np.uint64(PHILOX_M[1]) * x[2]
+        x = [(p1 >> np.uint64(32)) ^ x[1] ^ k[0], p1 & m32, (p0 >> np.uint64(32)) ^ x[3] ^ k[1],
+             p0 & m32]
+    return x
+
+
+def dropout_keep(seed, ncell, npass, p):
+    """keep[cell][pass][layer-1][unit] of the three hidden layers (bool)."""
+    cell, pss, sub = np.meshgrid(np.arange(ncell), np.arange(npass), np.arange(3 * NH // 4),
+                                 indexing="ij")
+    w = philox(cell, pss, np.full_like(cell, PURPOSE_DROPOUT), sub, seed & 0xFFFFFFFF, seed >> 32)
+    words = np.stack(w, axis=-1).reshape(ncell, npass, 3, NH)
+    return words >= np.uint64(int(np.floor(p * 2.0**32)))
+
+
+def dropout_sensitivity(p_flat, mom, eps_hat, npass, p, seed, emulate_bf16=True):
+    """sens[n][2] = (sigma_Stress, sigma_Heat) of moment records mom[n][32]."""
+    P = unpack(p_flat)
+    mom = np.asarray(mom, dtype=np.float64)
+    n = mom.shape[0]
+    valid = (mom[:, 0] > 1.0) & (mom[:, 4] > 0.0)
+    f = np.zeros((n, NF))
+    if valid.any():
+        f[valid] = features(mom[valid], eps_hat)
+    xs = (f - P["x_mean"]) / P["x_std"]
+    keep = dropout_keep(seed, n, npass, p)
+    scale = 1.0 / (1.0 - p)
+    q = (lambda a: bf16(a)) if emulate_bf16 else (lambda a: a)
+    ys = np.zeros((npass, n, 9))
+    for k in range(npass):
+        h = q(xs)
+        for l in (1, 2, 3):
+            a = silu(h @ q(P[f"W{l}"]).T + P[f"b{l}"])
+            h = q(np.where(keep[:, k, l - 1, :], a * scale, 0.0))
+        y = h @ q(P["W4"]).T + P["b4"]
+        ys[k] = (y * P["y_std"] + P["y_mean"])[:, :9]
+    sigma = ys.std(axis=0)
+    sens = np.stack([np.sqrt((sigma[:, :6] ** 2).sum(1)), np.sqrt((sigma[:, 6:] ** 2).sum(1))], 1)
+    sens[~valid] = 0.0
+    return sens

@@ -306,6 +306,13 @@ extern "C" int fp_counter_add(fp_ctx* c, uint32_t* ctr, uint32_t inc, hipStream_
     return launch_counter_add(c, ctr, inc, s);
 }
 
+extern "C" int fp_diagnostics(fp_ctx* c, const double* samp, double theta_inf, double n_inf,
+                              double dg_inf, double* diag, hipStream_t s) {
+    if (!c || !samp || !diag || !(theta_inf > 0.0) || !(n_inf > 0.0) || !std::isfinite(dg_inf))
+        return set_err(c, FP_EINVAL, "fp_diagnostics: bad argument");
+    return launch_diagnostics(c, samp, theta_inf, n_inf, dg_inf, diag, s);
+}
+
 extern "C" int fp_sample(fp_ctx* c, const double* mom, double* samp, hipStream_t s) {
     if (!c || !mom || !samp) return set_err(c, FP_EINVAL, "fp_sample: bad argument");
     return launch_sample(c, mom, samp, s);

@@ -9,10 +9,10 @@
 namespace fpg {
 
 // ---- record layouts (see include/fp.h) -------------------------------------------------
-constexpr int MOM = 32, REC = 16, SAMP = 16;
+constexpr int MOM = 32, REC = 16, SAMP = 16, DIAG = 24;
 enum { M_N = 0, M_U = 1, M_TH = 4, M_P = 5, M_T = 11, M_R = 21, M_W = 27, M_H = 30 };
 enum { R_C = 0, R_G = 6, R_TAU = 9, R_TH = 10, R_E = 11, R_EPS2 = 12, R_SIG = 13, R_ST = 14 };
-enum { PURPOSE_COLLISION = 3, PURPOSE_WALL = 4, PURPOSE_INJECT = 5 };
+enum { PURPOSE_COLLISION = 3, PURPOSE_WALL = 4, PURPOSE_INJECT = 5, PURPOSE_DROPOUT = 6 };
 
 constexpr double TWO_PI = 6.283185307179586;
 
@@ -93,13 +93,15 @@ __device__ __forceinline__ void normals3d(uint4 r, double& z0, double& z1, doubl
     z2 = r1 * cos(TWO_PI * u3);
 }
 
-// single precision: hardware log2 and sin/cos of revolutions (v_sin/v_cos take x in
-// units of 2 pi, so sin(2 pi u) is one instruction for u in (0, 1])
+// single precision: hardware log2, square root (about 1 ulp; the correctly rounded
+// expansion costs a dozen instructions more) and sin/cos of revolutions (v_sin/v_cos take
+// x in units of 2 pi, so sin(2 pi u) is one instruction for u in (0, 1]); the argument of
+// the root is 0 or at least 2e-10, never denormal
 __device__ __forceinline__ void normals3f(uint4 r, float& z0, float& z1, float& z2) {
     const float u0 = u01f(r.x), u1 = u01f(r.y), u2 = u01f(r.z), u3 = u01f(r.w);
     constexpr float M2LN2 = -1.3862943611198906f;  // -2 ln 2
-    const float r0 = __builtin_sqrtf(M2LN2 * __builtin_amdgcn_logf(u0));
-    const float r1 = __builtin_sqrtf(M2LN2 * __builtin_amdgcn_logf(u2));
+    const float r0 = __builtin_amdgcn_sqrtf(M2LN2 * __builtin_amdgcn_logf(u0));
+    const float r1 = __builtin_amdgcn_sqrtf(M2LN2 * __builtin_amdgcn_logf(u2));
     z0 = r0 * __builtin_amdgcn_cosf(u1);
     z1 = r0 * __builtin_amdgcn_sinf(u1);
     z2 = r1 * __builtin_amdgcn_cosf(u3);
@@ -182,6 +184,8 @@ constexpr int64_t FILL_4 = 1024 * 4 * 64, FILL_8 = 1024 * 8 * 64;
 // ---- launchers implemented in the kernel files -------------------------------------------
 int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* offsets,
                int32_t* perm, hipStream_t s);
+int launch_diagnostics(fp_ctx* c, const double* samp, double theta_inf, double n_inf,
+                       double dg_inf, double* diag, hipStream_t s);
 int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_particles* dst,
                  int32_t* offsets, int32_t* perm, double* mom, double* samp, hipStream_t s);
 int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,

@@ -149,9 +149,16 @@ __device__ __forceinline__ void half_features(const double* __restrict__ m, int 
 // MFMAs; every wave keeps at most 128 registers (VGPRs and AGPRs together)
 constexpr int NN_BLOCK = 1024;
 
-template <int KS>
+// Inverted dropout of the hidden activations for the sensitivity probe: activation row u
+// of cell k in pass t is kept if word u % 4 of Philox4x32-10 at counter
+// (k, t, PURPOSE_DROPOUT, 32 (layer - 1) + u / 4) is at least keep_min (= floor(p 2^32)),
+// and then scaled by 1 / (1 - p); no dropout when drop is null.
+// DROP: inverted dropout after the SiLU; bit 16 mt + 4 jq + i of keep set <=> the lane's
+// output row 32 mt + 8 jq + 4 h + i is kept (and scaled)
+template <int KS, bool DROP = false>
 __device__ __forceinline__ void nn_layer(const __bf16* __restrict__ img_l, const float* __restrict__ bias,
-                                         const bf16x8 (&bin)[8], bf16x8 (&bout)[8], int lane) {
+                                         const bf16x8 (&bin)[8], bf16x8 (&bout)[8], int lane,
+                                         uint64_t keep = 0, float scale = 1.0f) {
     const int h = lane >> 5;
     // two of the four 32-row output tiles at a time (32 accumulator registers live)
 #pragma unroll
@@ -178,10 +185,20 @@ __device__ __forceinline__ void nn_layer(const __bf16* __restrict__ img_l, const
             }
         }
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < 2; ++t) {
+            if constexpr (DROP) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                bout[2 * (mp + t) + (j >> 3)][j & 7] = (__bf16)silu_fast(acc[t][j]);
+                for (int j = 0; j < 16; ++j) {
+                    const float a = silu_fast(acc[t][j]);
+                    bout[2 * (mp + t) + (j >> 3)][j & 7] =
+                        (__bf16)(((keep >> (16 * (mp + t) + j)) & 1) ? a * scale : 0.0f);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    bout[2 * (mp + t) + (j >> 3)][j & 7] = (__bf16)silu_fast(acc[t][j]);
+            }
+        }
     }
 }
 
@@ -245,6 +262,119 @@ __global__ __launch_bounds__(NN_BLOCK) void nn_infer_kernel(int32_t ncell, const
             for (int q = 0; q < 9; ++q) dst[q] = o[q] + sec[SEC_B4 + q];
 #pragma unroll
             for (int q = 9; q < 16; ++q) dst[q] = 0.0f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// coefficient-sensitivity probe (Sec. "Heuristic coefficient-sensitivity probe"): npass
+// forward passes with inverted dropout on the three hidden layers; per cell the standard
+// deviation (1/npass) over the passes of each de-standardised normalised coefficient, and
+// sens[cell] = (|sigma_C| over the six stress coefficients, |sigma_Gamma| over the three
+// heat-flux ones); cells without features (N <= 1 or theta <= 0) get zeros.  Each wave
+// keeps its 32 cells' inputs and runs every pass; the sums of the deviations from the
+// first pass are FP64 (no cancellation).
+constexpr int SENS_BLOCK = 512;
+
+__global__ __launch_bounds__(SENS_BLOCK) void nn_sense_kernel(int32_t ncell, const double* __restrict__ mom,
+                                                              double eps_hat, const __bf16* __restrict__ gimg,
+                                                              const float* __restrict__ gsec, int32_t npass,
+                                                              uint64_t seed, uint32_t keep_min, float scale,
+                                                              double* __restrict__ sens) {
+    __shared__ __attribute__((aligned(16))) __bf16 img[IMG_BF];
+    __shared__ __attribute__((aligned(16))) float sec[SEC_N];
+    for (int t = threadIdx.x; t < IMG_BF / 8; t += SENS_BLOCK)
+        ((bf16x8*)img)[t] = ((const bf16x8*)gimg)[t];
+    for (int t = threadIdx.x; t < SEC_N; t += SENS_BLOCK) sec[t] = gsec[t];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, n = lane & 31;
+    const int32_t ntiles = (ncell + 31) / 32;
+    for (int32_t tile = blockIdx.x * (SENS_BLOCK / 64) + wave; tile < ntiles;
+         tile += gridDim.x * (SENS_BLOCK / 64)) {
+        __asm__ volatile("" ::: "memory");
+        const int32_t cell = tile * 32 + n;
+        const bool valid = cell < ncell;
+        float f[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) f[q] = 0.0f;
+        bool feat = false;
+        if (valid) {
+            const double* mr = mom + (int64_t)cell * MOM;
+            feat = mr[M_N] > 1.0 && mr[M_TH] > 0.0;
+            if (feat) half_features(mr, h, eps_hat, f);
+        }
+        bf16x8 bin[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int K = 16 * s + 8 * h + i;
+                bin[s][i] = (__bf16)((f[8 * s + i] - sec[SEC_XM + K]) / sec[SEC_XS + K]);
+            }
+        double y0[9], s1[9], s2[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) y0[q] = s1[q] = s2[q] = 0.0;
+        for (int32_t t = 0; t < npass; ++t) {
+            __asm__ volatile("" ::: "memory");  // keeps the weight reads inside the pass
+            bf16x8 b0[8], b1[8];
+            b0[0] = bin[0];
+            b0[1] = bin[1];
+            // masks of the lane's 64 rows of each hidden layer: row 32 mt + 8 jq + 4 h + i
+            // of layer l is decided by word i of the draw with sub 32 (l-1) + 8 mt + 2 jq + h
+            uint64_t km[3];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                uint64_t m = 0;
+#pragma unroll 1
+                for (int g = 0; g < 16; ++g) {
+                    const uint4 r = draw(seed, (uint32_t)cell, (uint32_t)t, PURPOSE_DROPOUT,
+                                         32u * (uint32_t)l + 2u * (uint32_t)g + (uint32_t)h);
+                    const uint64_t b = (uint64_t)(r.x >= keep_min) | ((uint64_t)(r.y >= keep_min) << 1) |
+                                       ((uint64_t)(r.z >= keep_min) << 2) |
+                                       ((uint64_t)(r.w >= keep_min) << 3);
+                    m |= b << (4 * g);
+                }
+                km[l] = m;
+            }
+            nn_layer<2, true>(img + IMG_L1, sec + SEC_B1, b0, b1, lane, km[0], scale);
+            nn_layer<8, true>(img + IMG_L2, sec + SEC_B2, b1, b0, lane, km[1], scale);
+            nn_layer<8, true>(img + IMG_L3, sec + SEC_B3, b0, b1, lane, km[2], scale);
+            f32x16 acc = f32x16{};
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const bf16x8 a = *(const bf16x8*)(img + IMG_L4 + (s * 64 + lane) * 8);
+                acc = mfma32(a, b1[s], acc);
+            }
+            float o[9];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float mine = acc[j];
+                const float other = __shfl_xor(mine, 32, 64);
+                o[j] = mine;
+                o[4 + j] = other;
+            }
+            o[8] = acc[4];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const double y = (double)(o[q] + sec[SEC_B4 + q]) * (double)sec[SEC_YS + q] +
+                                 (double)sec[SEC_YM + q];
+                if (t == 0) y0[q] = y;
+                const double dy = y - y0[q];
+                s1[q] += dy;
+                s2[q] += dy * dy;
+            }
+        }
+        if (valid && h == 0) {
+            double vc = 0.0, vg = 0.0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const double m = s1[q] / (double)npass;
+                const double var = fmax(s2[q] / (double)npass - m * m, 0.0);
+                if (q < 6) vc += var;
+                else vg += var;
+            }
+            sens[(int64_t)cell * 2] = feat ? sqrt(vc) : 0.0;
+            sens[(int64_t)cell * 2 + 1] = feat ? sqrt(vg) : 0.0;
         }
     }
 }
@@ -617,6 +747,20 @@ extern "C" int fp_closure_nn(fp_ctx* c, const fp_nn* n, const double* mom, doubl
     int rc = check_launch(c, "fp_closure_nn (network)");
     if (rc) return rc;
     return launch_closure_nn(c, n->ybuf, n->sec + SEC_YM, tol_abs, tol_rel, relax, mom, rec, status, s);
+}
+
+extern "C" int fp_nn_sensitivity(fp_ctx* c, const fp_nn* n, const double* mom, int32_t npass,
+                                 double p, uint64_t seed, double* sens, hipStream_t s) {
+    if (!c || !n || !mom || !sens || n->ctx != c || npass < 1 || !(p >= 0.0 && p < 1.0))
+        return set_err(c, FP_EINVAL, "fp_nn_sensitivity: bad argument");
+    const int32_t ntiles = (c->ncell + 31) / 32;
+    int grid = (ntiles + SENS_BLOCK / 64 - 1) / (SENS_BLOCK / 64);
+    if (grid > 512) grid = 512;
+    const uint32_t keep_min = (uint32_t)std::floor(p * 4294967296.0);
+    hipLaunchKernelGGL(nn_sense_kernel, dim3(grid), dim3(SENS_BLOCK), 0, s, c->ncell, mom,
+                       c->cfg.eps_hat, (const __bf16*)n->img, (const float*)n->sec, npass, seed,
+                       keep_min, (float)(1.0 / (1.0 - p)), sens);
+    return check_launch(c, "fp_nn_sensitivity");
 }
 
 extern "C" int fp_nn_outputs(fp_ctx* c, const fp_nn* n, float* y, hipStream_t s) {

@@ -52,6 +52,77 @@ __global__ __launch_bounds__(SA_BLOCK) void sample_kernel(int32_t ncell, const d
     }
 }
 
+// Diagnostics of the time-averaged fields, one lane per cell, FP64: the averaged state
+// (ratios of the cumulative sums), normalised stress Theta_ij / theta - delta_ij, heat flux
+// q^_i = <c_i |c|^2> / (2 theta^1.5) with <c_i |c|^2> = <v_i |v|^2> - U_i |U|^2
+// - 3 theta U_i - 2 Theta_ik U_k, and the covariance entropy proxies of the cylinder audit
+// (eqs. cyl_theta_def, cyl_entropy_eq, cyl_DG, cyl_entropy_kinG; D_q = |q^|^2 / 5).
+// Layout of diag[ncell][24]: 0 particles per sample, 1 number density, 2-4 U, 5 theta,
+// 6 T, 7-12 stress (11 12 13 22 23 33), 13-15 q^, 16 ds_eq, 17 D_G, 18 ds_kinG, 19 D_q,
+// 20-23 zero; 2-19 NaN without particles or with theta <= 0, D_G and ds_kinG NaN unless
+// det(Theta / theta) > 1e-12.
+__global__ __launch_bounds__(256) void diag_kernel(int32_t ncell, const double* __restrict__ samp,
+                                                   const double* __restrict__ nvol, double dens,
+                                                   double m_over_kB, double theta_inf, double n_inf,
+                                                   double dg_inf, double* __restrict__ diag) {
+    const int32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= ncell) return;
+    const double* sm = samp + (int64_t)k * SAMP;
+    double o[DIAG];
+    const double qnan = __builtin_nan("");
+#pragma unroll
+    for (int i = 0; i < DIAG; ++i) o[i] = i < 20 ? qnan : 0.0;
+    const double sN = sm[0], ns = sm[13];
+    o[0] = ns > 0.0 ? sN / ns : 0.0;
+    o[1] = o[0] * (nvol ? nvol[k] : dens);
+    if (sN > 0.0) {
+        const double U[3] = {sm[1] / sN, sm[2] / sN, sm[3] / sN};
+        double Th[3][3];
+        const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) Th[ii[q]][jj[q]] = Th[jj[q]][ii[q]] = sm[4 + q] / sN - U[ii[q]] * U[jj[q]];
+        const double theta = (Th[0][0] + Th[1][1] + Th[2][2]) / 3.0;
+        if (theta > 0.0) {
+            const double UU = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+            double qh[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double TU = Th[i][0] * U[0] + Th[i][1] * U[1] + Th[i][2] * U[2];
+                qh[i] = (sm[10 + i] / sN - U[i] * UU - 3.0 * theta * U[i] - 2.0 * TU) /
+                        (2.0 * theta * sqrt(theta));
+            }
+            o[2] = U[0]; o[3] = U[1]; o[4] = U[2];
+            o[5] = theta;
+            o[6] = theta * m_over_kB;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) o[7 + q] = Th[ii[q]][jj[q]] / theta - (ii[q] == jj[q] ? 1.0 : 0.0);
+            o[13] = qh[0]; o[14] = qh[1]; o[15] = qh[2];
+            const double a = Th[0][0] / theta, b = Th[0][1] / theta, cc = Th[0][2] / theta;
+            const double d = Th[1][1] / theta, e = Th[1][2] / theta, f = Th[2][2] / theta;
+            const double det = a * (d * f - e * e) - b * (b * f - e * cc) + cc * (b * e - d * cc);
+            const double ds_eq = 1.5 * log(theta / theta_inf) - log(o[1] / n_inf);
+            // positive-definite Theta only (a singular sample covariance, e.g. of fewer than
+            // four particles, has a zero determinant whose sign rounding decides)
+            const double dg = det > 1e-12 ? -0.5 * log(det) : qnan;
+            o[16] = ds_eq;
+            o[17] = dg;
+            o[18] = ds_eq - (dg - dg_inf);
+            o[19] = (qh[0] * qh[0] + qh[1] * qh[1] + qh[2] * qh[2]) / 5.0;
+        }
+    }
+    double* dst = diag + (int64_t)k * DIAG;
+#pragma unroll
+    for (int i = 0; i < DIAG; ++i) dst[i] = o[i];
+}
+
+int launch_diagnostics(fp_ctx* c, const double* samp, double theta_inf, double n_inf,
+                       double dg_inf, double* diag, hipStream_t s) {
+    hipLaunchKernelGGL(diag_kernel, dim3((c->ncell + 255) / 256), dim3(256), 0, s, c->ncell, samp,
+                       (const double*)c->nvol, c->cfg.fnum_over_vol, c->cfg.mass / c->cfg.kB,
+                       theta_inf, n_inf, dg_inf, diag);
+    return check_launch(c, "fp_diagnostics");
+}
+
 int launch_sample(fp_ctx* c, const double* mom, double* samp, hipStream_t s) {
     hipLaunchKernelGGL(sample_kernel, dim3((c->ncell + SA_CELLS - 1) / SA_CELLS), dim3(SA_BLOCK), 0, s,
                        c->ncell, mom, samp);

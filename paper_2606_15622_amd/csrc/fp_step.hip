@@ -542,7 +542,10 @@ static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const
                            uint32_t* adv, hipStream_t s) {
     const int64_t threads = (int64_t)c->ncell * G;
     const unsigned grid = (unsigned)((threads + ST_BLOCK - 1) / ST_BLOCK);
-    hipLaunchKernelGGL((collide_kernel<T, G, ST_K, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
+    // register cache of c*: 8 particles per lane, 4 with 32 or more lanes per cell (about
+    // 3 particles per lane there; fewer registers, more resident waves)
+    constexpr int K = G >= 32 ? ST_K / 2 : ST_K;
+    hipLaunchKernelGGL((collide_kernel<T, G, K, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
                        c->cfg, c->ncell, off, mom, rec, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy,
                        (T*)p->vz, p->pid, p->key, step, move, stepp, c->pend, c->bidx,
                        adv ? c->stepc : nullptr);
@@ -567,7 +570,9 @@ template <typename T, int GEOM>
 static void collide_dispatch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
                              const double* rec, uint32_t step, int move, const uint32_t* sp,
                              uint32_t* adv, hipStream_t s) {
-    switch (lanes_per_cell(c, p->n, FILL_4)) {
+    // about four particles per lane: the per-particle work (three Philox draws, the
+    // update, the flight) is long enough that wider groups beat the shorter group sums
+    switch (lanes_per_cell(c, p->n, FILL_4, 4)) {
         case 4: collide_launch<T, 4, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;
         case 8: collide_launch<T, 8, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;
         case 16: collide_launch<T, 16, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;

@@ -21,7 +21,7 @@ FP_EXACT, FP_PAPER = 0, 1
 (CELL_OK, CELL_EMPTY, CELL_FEW, CELL_SINGULAR, CELL_NONFINITE, CELL_NN,
  CELL_NN_FALLBACK) = range(7)
 STEP_COLLIDE, STEP_MOVE, STEP_KEYS, STEP_ADVANCE = 1, 2, 4, 8
-MOM_STRIDE, REC_STRIDE, SAMP_STRIDE = 32, 16, 16
+MOM_STRIDE, REC_STRIDE, SAMP_STRIDE, DIAG_STRIDE = 32, 16, 16, 24
 NN_PARAMS, NN_TRAIN, NN_FEATURES, NN_OUTPUTS = 39408, 39312, 32, 16
 LOSS_MSE, LOSS_RESIDUAL = 0, 1
 
@@ -76,6 +76,7 @@ def load():
         L.fp_sample.argtypes = [vp, vp, vp, vp]
         L.fp_step_dev.argtypes = [vp, P(FPParticles), vp, vp, vp, vp, u32, vp]
         L.fp_counter_add.argtypes = [vp, vp, u32, vp]
+        L.fp_diagnostics.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, vp, vp]
         L.fp_inject.argtypes = [vp, P(FPParticles), i64, vp, u64, vp]
         L.fp_inject_slots.argtypes = [vp]
         L.fp_inject_slots.restype = i64
@@ -85,6 +86,7 @@ def load():
         L.fp_nn_load.argtypes = [vp, vp, vp, vp]
         L.fp_closure_nn.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
         L.fp_nn_outputs.argtypes = [vp, vp, vp, vp]
+        L.fp_nn_sensitivity.argtypes = [vp, vp, vp, i32, C.c_double, u64, vp, vp]
         L.fp_nn_features.argtypes = [vp, vp, i64, vp, vp]
         L.fp_closure_build.argtypes = [vp, vp, i64, vp, vp]
         L.fp_nn_grad.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp, vp, vp]
@@ -95,10 +97,10 @@ def load():
         L.fp_closure_solve_backward.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fp_moments_backward.argtypes = [vp, P(FPParticles), vp, vp, vp, vp, vp, vp, vp]
         for f in ("fp_bin", "fp_rebin", "fp_moments", "fp_closure_solve", "fp_step", "fp_sample", "fp_nn_create",
-                  "fp_nn_load", "fp_closure_nn", "fp_nn_outputs", "fp_nn_features",
+                  "fp_nn_load", "fp_closure_nn", "fp_nn_outputs", "fp_nn_sensitivity", "fp_nn_features",
                   "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
                   "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
-                  "fp_inject", "fp_cell_volumes", "fp_step_dev", "fp_counter_add"):
+                  "fp_inject", "fp_cell_volumes", "fp_step_dev", "fp_counter_add", "fp_diagnostics"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -268,6 +270,11 @@ class Context:
         self._check(self.lib.fp_step_dev(self.h, C.byref(a), _ptr(offsets), _ptr(mom), _ptr(rec),
                                          _ptr(step_dev), int(flags), _stream(stream)), "fp_step_dev")
 
+    def diagnostics(self, samp, theta_inf, n_inf, dg_inf, diag, stream=None):
+        self._check(self.lib.fp_diagnostics(self.h, _ptr(samp), float(theta_inf), float(n_inf),
+                                            float(dg_inf), _ptr(diag), _stream(stream)),
+                    "fp_diagnostics")
+
     def counter_add(self, ctr, inc, stream=None):
         self._check(self.lib.fp_counter_add(self.h, _ptr(ctr), int(inc), _stream(stream)),
                     "fp_counter_add")
@@ -343,6 +350,11 @@ class Network:
         c = self.ctx
         c._check(c.lib.fp_closure_nn(c.h, self.h, _ptr(mom), _ptr(rec), _ptr(status), float(tol_abs),
                                      float(tol_rel), float(relax), _stream(stream)), "fp_closure_nn")
+
+    def sensitivity(self, mom, npass, p, seed, sens, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_nn_sensitivity(c.h, self.h, _ptr(mom), int(npass), float(p), int(seed),
+                                         _ptr(sens), _stream(stream)), "fp_nn_sensitivity")
 
     def outputs(self, y, stream=None):
         c = self.ctx
