@@ -12,7 +12,7 @@ steps (2000).
 
 Readings (the paper is silent on these):
   * the fields are averages over the steps since the last adaptation (sampling sums of
-    the leaves: sum N, sum v, sum v v, number of samples), rho = (sum N / samples) fnum /
+    the leaves: sum N, sum v, sum v v, number of samples in entry 13), rho = (sum N / samples) fnum /
     V (gas volume), U = sum v / sum N, theta = (sum |v|^2 / sum N - |U|^2) / 3 (the
     temperature up to the factor m/k_B, which cancels in the deviation), P = rho m theta;
   * a parent's sums are the sums of its four children (the merged population), its
@@ -129,7 +129,7 @@ def node_sums(tree, acc, vol):
     for i, (l, ix, iy) in enumerate(tree.leaves()):
         a = acc[i]
         s2 = (a[4] + a[7]) + a[9]
-        sums[l][iy, ix] = [a[0], a[1], a[2], a[3], s2, vol[i], a[14]]
+        sums[l][iy, ix] = [a[0], a[1], a[2], a[3], s2, vol[i], a[13]]
     for l in range(L - 1, -1, -1):
         for iy in range(tree.nby << l):
             for ix in range(tree.nbx << l):
@@ -260,14 +260,14 @@ def remap_samp(old, new, samp_old, vol_old, vol_new):
             out[i] = samp_old[o]
         elif olev[o] < l:
             r = vol_new[i] / vol_old[o]
-            out[i, :14] = samp_old[o, :14] * r
-            out[i, 14:] = samp_old[o, 14:]
+            out[i, :13] = samp_old[o, :13] * r
+            out[i, 13:] = samp_old[o, 13:]
         else:
             kids = [(l + 1, 2 * ix + (c & 1), 2 * iy + (c >> 1)) for c in range(4)]
             ids = [omap[new.fine_cells(*k)[0]] for k in kids]
             s = samp_old[ids[0]].copy()
             for k in ids[1:]:
-                s[:14] = s[:14] + samp_old[k, :14]
+                s[:13] = s[:13] + samp_old[k, :13]
             out[i] = s
     return out
 
@@ -279,3 +279,62 @@ def map_keys(leafmap, fine_key, nfine, nleaf):
     live = (k >= 0) & (k < nfine)
     out[live] = leafmap[k[live]]
     return out
+
+
+def run_open_amr(w, state, pid_next, step0, nsteps, max_level, prm, adapt_every, fine_vol,
+                 n_skip=0):
+    """The open cylinder loop on the tree, composed from the oracle's steps: every
+    adapt_every steps an adaptation on the sums since the last one (keys of the particles
+    from their positions, sampling sums carried over), then sort, moments, sums, closure
+    (density from the leaf gas volumes), velocity update, flight, injection.  fine_vol:
+    gas volumes of the fine cells.  Returns (state, pid_next, tree, mom, rec, status,
+    samp, vol) after the last step."""
+    from oracle import oracle as O
+    nx, ny = int(w["nx"]), int(w["ny"])
+    nfine = nx * ny
+    L = int(max_level)
+    fnum, mass = float(w["fnum"]), float(w["mass"])
+    full_fine = (float(w["dx"]) * float(w["dy"])) * float(w["depth"])
+    tree = Tree(nx >> L, ny >> L, L)
+    vol, nvol = leaf_volumes(tree, fine_vol, fnum, full_fine)
+    lm = tree.leaf_map()
+    nleaf = len(vol)
+    s = {k: np.asarray(state[k], dtype=np.float64).copy() for k in ("x", "y", "vx", "vy", "vz")}
+    s["pid"] = np.asarray(state["pid"], dtype=np.uint32).copy()
+    key = map_keys(lm, O.keys(w, s["x"], s["y"]), nfine, nleaf)
+    acc = np.zeros((nleaf, SAMP))
+    samp = np.zeros((nleaf, SAMP))
+    since = step0
+    mom = rec = st = None
+    for step in range(step0, step0 + nsteps):
+        if adapt_every > 0 and step - since >= adapt_every:
+            new, _, _ = adapt(tree, acc, vol, prm, step - since, fnum, mass)
+            vol2, nvol2 = leaf_volumes(new, fine_vol, fnum, full_fine)
+            samp = remap_samp(tree, new, samp, vol, vol2)
+            lm2 = new.leaf_map()
+            nleaf2 = len(vol2)
+            live = (key >= 0) & (key < nleaf)
+            fk = O.keys(w, s["x"], s["y"])
+            key = np.where(live, lm2[fk], nleaf2).astype(np.int32)
+            tree, vol, nvol, lm, nleaf = new, vol2, nvol2, lm2, nleaf2
+            acc = np.zeros((nleaf, SAMP))
+            since = step
+        perm, off = O.bin_particles(nleaf, key)
+        perm = perm[:off[-1]]
+        for k in s:
+            s[k] = s[k][perm]
+        mom = O.moments(off, s["vx"], s["vy"], s["vz"])
+        acc = O.sample(off, s["vx"], s["vy"], s["vz"], acc)
+        if step >= n_skip:
+            samp = O.sample(off, s["vx"], s["vy"], s["vz"], samp)
+        rec, st = O.closure(w, mom, nvol)
+        s["vx"], s["vy"], s["vz"] = O.update(w, off, s["vx"], s["vy"], s["vz"], s["pid"], mom, rec, step)
+        s["x"], s["y"], s["vx"], s["vy"], s["vz"], fk = O.move(w, s["x"], s["y"], s["vx"], s["vy"],
+                                                               s["vz"], s["pid"], step)
+        key = map_keys(lm, fk, nfine, nleaf)
+        inj, pid_next = O.inject(w, step, pid_next)
+        for k in ("x", "y", "vx", "vy", "vz", "pid"):
+            s[k] = np.concatenate([s[k], inj[k].astype(s[k].dtype)])
+        key = np.concatenate([key, map_keys(lm, inj["key"], nfine, nleaf)])
+    s["key"] = key
+    return s, pid_next, tree, mom, rec, st, samp, vol

@@ -22,7 +22,7 @@ def acc_row(nbar, ns, U, th):
     r[1:4] = S * np.asarray(U)
     vv = np.outer(U, U) + th * np.eye(3)
     r[4:10] = S * vv[[0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
-    r[14] = ns
+    r[13] = ns
     return r
 
 
@@ -86,7 +86,7 @@ def test_parent_sums_are_the_merged_population():
         acc[i, 1:4] = v.sum(0)
         vv = np.einsum("pi,pj->ij", v, v)
         acc[i, 4:10] = vv[[0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
-        acc[i, 14] = 1
+        acc[i, 13] = 1
     vol = np.array([1.0, 2.0, 3.0, 4.0])
     sums = A.node_sums(t, acc, vol)
     allv = np.concatenate(pops)
@@ -182,7 +182,7 @@ def test_empty_and_solid_leaves():
         t.age[1][c >> 1, c & 1] = 500
     acc = np.array([acc_row(100, 4, (0, 0, 0), 1.0), np.zeros(A.SAMP), np.zeros(A.SAMP),
                     acc_row(100, 4, (0, 0, 0), 1.0)])
-    acc[1, 14] = acc[2, 14] = 4
+    acc[1, 13] = acc[2, 13] = 4
     vol = np.array([1.0, 0.0, 1.0, 1.0])
     t2, ref, mer = A.adapt(t, acc, vol, dict(PRM), 5, FNUM, MASS)
     # the empty children take no criterion; children 0 and 3 deviate from the parent
@@ -191,7 +191,7 @@ def test_empty_and_solid_leaves():
     prm = dict(PRM)
     prm["n_max"] = 10
     acc0 = np.zeros((4, A.SAMP))
-    acc0[:, 14] = 4
+    acc0[:, 13] = 4
     acc0[1, 0] = 4 * 50
     _, ref, _ = A.adapt(t, acc0, vol, prm, 5, FNUM, MASS)
     assert ref == set()                 # the only crowded leaf has no gas volume
@@ -214,13 +214,13 @@ def test_sampling_sums_survive_adaptation():
     vol2, _ = A.leaf_volumes(t2, fine, FNUM, 1.0)
     s2 = A.remap_samp(t, t2, samp, vol, vol2)
     assert s2[:, 0].sum() == pytest.approx(samp[:, 0].sum(), rel=1e-14)
-    assert s2[:, 1:14].sum(0) == pytest.approx(samp[:, 1:14].sum(0), rel=1e-12)
+    assert s2[:, 1:13].sum(0) == pytest.approx(samp[:, 1:13].sum(0), rel=1e-12)
     # a split child keeps its parent's averaged velocity; the merged cell is the sum
     parent = samp[4]
     for i in range(1, 5):
         np.testing.assert_allclose(s2[i, 1:4] / s2[i, 0], parent[1:4] / parent[0], rtol=1e-14)
-        assert s2[i, 14] == parent[14]
-    np.testing.assert_allclose(s2[0, :14], samp[:4, :14].sum(0), rtol=1e-14)
+        assert s2[i, 13] == parent[13]
+    np.testing.assert_allclose(s2[0, :13], samp[:4, :13].sum(0), rtol=1e-14)
 
 
 def test_map_keys():
@@ -228,3 +228,27 @@ def test_map_keys():
     m = t.leaf_map()
     k = A.map_keys(m, np.array([0, 3, 8, 7, 8]), 8, 5)
     assert list(k) == [m[0], m[3], 5, m[7], 5]
+
+
+def test_level0_loop_is_the_uniform_oracle_loop():
+    """The tree loop composed in Python, with no level below the base grid and no
+    adaptation, against the oracle's own C loop of the open domain: the same numbers."""
+    from oracle import oracle as O
+    from paper_2606_15622_amd import inputs as I
+    w = I.cylinder(cell=2e-2, nx=40, ny=30, fnum=1e15, precision="f64")
+    s = I.freestream_state(w, seed=5)
+    s["key"] = O.keys(w, s["x"], s["y"])
+    n0 = s["x"].shape[0]
+    fine = O.cell_volumes(w)
+    a, apn, tree, amom, arec, ast, asamp, avol = A.run_open_amr(w, s, n0, 0, 3, 0, PRM, 0, fine)
+    o, opn, omom, orec, ost, osamp = O.run_open(w, s, n0, 0, 3, capacity=4 * n0, n_skip=0)
+    nc = w["nx"] * w["ny"]
+    keep = o["key"] < nc
+    o = {k: v[keep] for k, v in o.items()}
+    live = a["key"] < nc
+    assert apn == opn and len(tree.leaves()) == nc
+    for k in ("x", "y", "vx", "vy", "vz", "pid", "key"):
+        np.testing.assert_array_equal(a[k][live], o[k], err_msg=k)
+    np.testing.assert_array_equal(ast, ost)
+    np.testing.assert_array_equal(asamp, osamp)
+    np.testing.assert_array_equal(avol, fine)
