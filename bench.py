@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--scaled-steps", type=int, default=20)
     ap.add_argument("--no-other", action="store_true", help="skip the Couette and cylinder lines")
     ap.add_argument("--cylinder-steps", type=int, default=20)
+    ap.add_argument("--amr-steps", type=int, default=100)
     return ap.parse_args()
 
 
@@ -211,6 +212,47 @@ def cylinder_line(torch, F, I, steps):
             "cell_closures_per_s": round(sim.ctx.ncell * steps / t, 1)}
 
 
+def cylinder_amr_line(torch, F, I, steps, warm=300, every=100):
+    """The cylinder on the adaptive quadtree: base grid 400 x 300 cells of 2 mm, two levels
+    below it (finest 0.5 mm, 1600 x 1200 fine cells), the same free stream and about 1.8e7
+    particles, FP32, exact closure; an adaptation every `every` steps on the sums since the
+    last one (criteria thresholds of the paper, N_max = 4x the free-stream particles of a
+    base cell).  Warm-up steps let the bow shock form and the tree follow it."""
+    w = I.cylinder(cell=0.5e-3, nx=1600, ny=1200, precision="f32", seed=3)
+    ppc_base = w["n_inf"] * (2e-3) ** 2 * w["depth"] / w["fnum"]
+    prm = dict(tau_grad=0.10, tau_coarse=0.05, shock_factor=1.2,
+               p_inf=w["n_inf"] * I.KB * w["T_inf"], n_max=4.0 * ppc_base, n_grad=200.0,
+               eps=1e-300, age_min=2000)
+    state = I.freestream_state(w)
+    sim = F.AMRSimulation(w, state, 2, prm, every)
+    del state
+    for s in range(warm):
+        sim.step(s)
+    torch.cuda.synchronize()
+    leaves0 = sim.ncell
+    t0 = time.perf_counter()
+    live = 0
+    t_adapt = 0.0
+    for s in range(warm, warm + steps):
+        if s - sim.since >= every:
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            sim.adapt(s - sim.since)
+            sim.since = s
+            t_adapt += time.perf_counter() - ta
+        sim.step(s, sample=True)
+        live += int(sim.offsets[-1])
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return {"workload": "cylinder2d on a quadtree: base 400x300 cells of 2 mm, 2 levels "
+                        "(1600x1200 fine), Mach 10 argon, about 1.8e7 particles, FP32",
+            "value": round(live / t, 1), "unit": "particle-steps/s", "steps": steps,
+            "ms_per_step": round(t / steps * 1e3, 4), "adapt_every": every,
+            "adapt_ms": round(t_adapt * 1e3 / max(1, steps // every), 3),
+            "leaves_before": leaves0, "leaves_after": sim.ncell,
+            "cell_closures_per_s": round(sim.ncell * steps / t, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -265,6 +307,7 @@ def main():
     if not args.no_other:
         out["couette"] = couette_line(torch, F, I)
         out["cylinder"] = cylinder_line(torch, F, I, args.cylinder_steps)
+        out["cylinder_amr"] = cylinder_amr_line(torch, F, I, args.amr_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(I, w)
     print(json.dumps(out))

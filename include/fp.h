@@ -216,6 +216,59 @@ int64_t fp_inject_slots(const fp_ctx* ctx);
  * area count as solid, volume 0); box geometries dx dy (1 m depth). */
 int fp_cell_volumes(fp_ctx* ctx, double* vol, hipStream_t s);
 
+/* ---- adaptive quadtree of the cylinder domain -----------------------------------------
+ * Sec. "Extension to External Aerodynamics", Problem Description: hierarchical Cartesian
+ * quadtree, cells split on the normalised deviation |phi - phi_parent| / (|phi| + eps)
+ * of density, temperature and pressure from the parent (tau_grad), on a particle-count
+ * limit (N_max) and on shock pressure (P > factor p_inf); four sibling leaves merge when
+ * all deviations are below tau_coarse, the merged count is low and every sibling has been
+ * unchanged for age_min steps.  The grid of the context (nx, ny) is the finest level; the
+ * base grid has (nx >> max_level) x (ny >> max_level) cells.  With a tree, "cell" in every
+ * other entry point means leaf: ncell = fp_ncell(ctx) leaves, numbered depth first (base
+ * cells row-major, children (0,0) (1,0) (0,1) (1,1)); keys computed from positions
+ * (fp_step, fp_inject) are leaf ids; fp_cell_volumes gives leaf gas volumes; fp_rebin
+ * is refused (its neighbour structure is that of the uniform grid), fp_bin sorts. */
+typedef struct fp_amr_params {
+    double tau_grad;      /* split: largest deviation from the parent above this (0.10) */
+    double tau_coarse;    /* merge: every sibling's deviation below this (0.05) */
+    double shock_factor;  /* split: pressure above shock_factor p_inf (1.2) */
+    double p_inf;         /* free-stream pressure [Pa] */
+    double n_max;         /* split: mean particles per sampled step above this; merge: the
+                             merged cell's mean at most this */
+    double n_grad;        /* fewer sampled particles: no gradient or shock test (a sibling
+                             with fewer counts as no deviation) */
+    double eps;           /* regularisation of the deviation */
+    int32_t age_min;      /* steps unchanged before a leaf may merge (2000) */
+    int32_t reserved;     /* must be 0 */
+} fp_amr_params;
+
+/* Give a FP_CYLINDER2D context a tree of base cells only (all leaves at level 0,
+ * ages 0), 0 <= max_level <= 4, nx and ny multiples of 2^max_level.  Synchronous. */
+int fp_amr_init(fp_ctx* ctx, int32_t max_level);
+/* One adaptation (synchronous on s: returns once the new leaf count is known).  acc
+ * [ncell][16] (device) holds the sampling sums (layout of samp, e.g. from fp_sample) of
+ * the current leaves over the steps since the last adaptation; the fields behind the
+ * criteria are rho = (sum N / samples) fnum / V, U = sum v / sum N, theta = (sum |v|^2 /
+ * sum N - |U|^2) / 3, P = rho m theta, a parent's from the sums of its children.  One
+ * level per call: flagged leaves split, flagged parents of four leaves merge; ages of
+ * unchanged leaves advance by steps.  Afterwards acc is zeroed for the new leaves; samp
+ * (optional) is carried over (a new child takes its parent's sums scaled by its share of
+ * the parent's gas volume, a merged cell the sum of its children's, the sample count
+ * kept); p (optional, its n slots) gets the keys of the new leaves from the positions,
+ * and key = ncell for slots whose key was not a cell (deleted, unused).  FP_EINVAL
+ * without a tree. */
+int fp_amr_adapt(fp_ctx* ctx, const fp_amr_params* prm, double* acc, double* samp,
+                 fp_particles* p, int32_t steps, hipStream_t s);
+/* Number of cells (leaves with a tree, else nx ny). */
+int32_t fp_ncell(const fp_ctx* ctx);
+/* Number of tree nodes (all levels; 0 without a tree). */
+int64_t fp_amr_nodes(const fp_ctx* ctx);
+/* Copies of the tree (device buffers, each optional): state[nodes] (0 absent, 1 leaf,
+ * 2 refined; level-major, row-major in a level), age[nodes], leafmap[nx ny] (leaf of
+ * every fine cell), leaf_node[ncell] (node of every leaf). */
+int fp_amr_tree(fp_ctx* ctx, int8_t* state, int32_t* age, int32_t* leafmap, int32_t* leaf_node,
+                hipStream_t s);
+
 /* Time averaging (the "average_results" step): adds the raw sums of every cell,
  * reconstructed from mom, to samp (layout samp above). */
 int fp_sample(fp_ctx* ctx, const double* mom, double* samp, hipStream_t s);

@@ -209,6 +209,11 @@ extern "C" void fp_destroy(fp_ctx* c) {
     (void)hipFree(c->bidx);
     (void)hipFree(c->vol);
     (void)hipFree(c->nvol);
+    for (void* q : {(void*)c->amr_state, (void*)c->amr_flag, (void*)c->amr_age, (void*)c->amr_sum,
+                    (void*)c->leafmap, (void*)c->leafmap_old, (void*)c->leaf_node, (void*)c->leaf_node_old,
+                    (void*)c->amr_first, (void*)c->amr_part, (void*)c->fine_vol, (void*)c->vol_old,
+                    (void*)c->samp_old})
+        (void)hipFree(q);
     (void)hipFree(c->inj);
     delete c;
 }
@@ -250,6 +255,8 @@ extern "C" int fp_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_o
     if (!c || !offsets || !src_offsets || !particles_ok(c, src, true) || !dst || (samp && !mom))
         return set_err(c, FP_EINVAL, "fp_rebin: bad argument");
     if (samp && samp == mom) return set_err(c, FP_EINVAL, "fp_rebin: samp and mom alias");
+    if (c->amr_L >= 0)
+        return set_err(c, FP_EINVAL, "fp_rebin: the re-sort needs the uniform grid (adaptive tree: fp_bin)");
     if (src->n > 0 && (!dst->vx || !dst->vy || !dst->vz || !dst->pid || !dst->key || !dst->x ||
                        (c->cfg.geometry != FP_COUETTE1D && !dst->y)))
         return set_err(c, FP_EINVAL, "fp_rebin: bad destination");

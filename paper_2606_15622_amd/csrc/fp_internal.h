@@ -10,6 +10,7 @@ namespace fpg {
 
 // ---- record layouts (see include/fp.h) -------------------------------------------------
 constexpr int MOM = 32, REC = 16, SAMP = 16, DIAG = 24;
+constexpr int AMR_MAX_LEVEL = 4;
 enum { M_N = 0, M_U = 1, M_TH = 4, M_P = 5, M_T = 11, M_R = 21, M_W = 27, M_H = 30 };
 enum { R_C = 0, R_G = 6, R_TAU = 9, R_TH = 10, R_E = 11, R_EPS2 = 12, R_SIG = 13, R_ST = 14 };
 enum { PURPOSE_COLLISION = 3, PURPOSE_WALL = 4, PURPOSE_INJECT = 5, PURPOSE_DROPOUT = 6 };
@@ -45,6 +46,23 @@ struct fp_ctx {
     double inj_rect[4][4] = {};  // x_a, x_b, y_a, y_b of the four inflow rectangles
     double inj_lambda[4] = {};   // expected candidates per rectangle and step
     int32_t inj_slot0[5] = {};   // slot prefix: floor(lambda_r) + 1 slots per rectangle
+    // adaptive quadtree (fp_amr_init; the grid of cfg is the finest level): ncell is then
+    // the number of leaves and every key is looked up in leafmap
+    int32_t amr_L = -1;          // levels below the base grid, -1: no tree
+    int32_t amr_nbx = 0, amr_nby = 0;
+    int8_t* amr_state = nullptr; // [nodes] absent / leaf / refined, level-major
+    int8_t* amr_flag = nullptr;  // [nodes] 1 split, 2 merge (one adaptation)
+    int32_t* amr_age = nullptr;  // [nodes] steps unchanged
+    double* amr_sum = nullptr;   // [nodes][8] sums behind the criteria
+    int32_t* leafmap = nullptr;  // [nx*ny] leaf of every fine cell
+    int32_t* leafmap_old = nullptr;
+    int32_t* leaf_node = nullptr;      // [leaves] node of every leaf
+    int32_t* leaf_node_old = nullptr;
+    int32_t* amr_first = nullptr;      // [nx*ny+1] leaf starts in depth-first order, scanned
+    int32_t* amr_part = nullptr;       // scan partials
+    double* fine_vol = nullptr;        // [nx*ny] gas volume of the fine cells
+    double* vol_old = nullptr;         // [leaves] before the last adaptation
+    double* samp_old = nullptr;        // [leaves][16]
     std::string err;
 };
 

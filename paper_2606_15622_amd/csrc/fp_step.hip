@@ -192,12 +192,14 @@ __device__ __forceinline__ bool fly_open(const fp_config& g, double pos[2], doub
     return pos[0] < g.x0 || pos[0] > x1 || pos[1] < g.y0 || pos[1] > y1;
 }
 
+// kmap (adaptive tree): the leaf of every cell of the grid, else NULL
 template <bool TWO_D>
 __device__ __forceinline__ int32_t cell_key(const fp_config& g, double x, double y, double inv_dx,
-                                            double inv_dy) {
+                                            double inv_dy, const int32_t* __restrict__ kmap) {
     const int32_t kx = axis_cell(x, g.x0, inv_dx, g.nx);
     const int32_t ky = TWO_D ? axis_cell(y, g.y0, inv_dy, g.ny) : 0;
-    return ky * g.nx + kx;
+    const int32_t k = ky * g.nx + kx;
+    return kmap ? kmap[k] : k;
 }
 
 __host__ __device__ inline Walls make_walls(const fp_config& g) {
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
     T* __restrict__ py, T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
     const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step_arg, int move,
     const uint32_t* __restrict__ stepp, int32_t* __restrict__ pend, int32_t* __restrict__ plist,
-    uint32_t* __restrict__ stepc) {
+    uint32_t* __restrict__ stepc, const int32_t* __restrict__ kmap) {
     const uint32_t step = stepp ? stepp[0] : step_arg;
     if (stepc && blockIdx.x == 0 && threadIdx.x == 0) stepc[0] = step;   // for flight_rest
     const int64_t gt = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
@@ -378,7 +380,7 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
         px[p] = (T)x;
         if (TWO_D) py[p] = (T)y;
         pvx[p] = v0; pvy[p] = v1; pvz[p] = v2;
-        pkey[p] = gone ? ncell : cell_key<TWO_D>(g, x, y, inv_dx, inv_dy);
+        pkey[p] = gone ? ncell : cell_key<TWO_D>(g, x, y, inv_dx, inv_dy, kmap);
     };
     // returns false when the full flight is still to do (velocity already stored)
     auto finish_fast = [&](int32_t p, T v0, T v1, T v2) -> bool {
@@ -459,7 +461,8 @@ __global__ __launch_bounds__(FR_BLOCK) void flight_rest_kernel(
     const int32_t* __restrict__ pend, const int32_t* __restrict__ plist, T* __restrict__ px,
     T* __restrict__ py, T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
     const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step_arg,
-    const uint32_t* stepp, uint32_t* adv, const uint32_t* __restrict__ stepc) {
+    const uint32_t* stepp, uint32_t* adv, const uint32_t* __restrict__ stepc,
+    const int32_t* __restrict__ kmap) {
     constexpr int FR_CELLS = FR;
     if (adv && blockIdx.x == 0 && threadIdx.x == 0) adv[0] = stepc[0] + 1u;
     const int lane = threadIdx.x & 63;
@@ -499,7 +502,7 @@ __global__ __launch_bounds__(FR_BLOCK) void flight_rest_kernel(
         px[p] = (T)pos[0];
         if (TWO_D) py[p] = (T)pos[1];
         pvx[p] = (T)v[0]; pvy[p] = (T)v[1]; pvz[p] = (T)v[2];
-        pkey[p] = gone ? ncell : cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy);
+        pkey[p] = gone ? ncell : cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy, kmap);
     }
 }
 
@@ -510,7 +513,8 @@ __global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, 
                                                          T* __restrict__ pvy, T* __restrict__ pvz,
                                                          const uint32_t* __restrict__ ppid,
                                                          int32_t* __restrict__ pkey, uint32_t step_arg,
-                                                         int keys_only, const uint32_t* __restrict__ stepp) {
+                                                         int keys_only, const uint32_t* __restrict__ stepp,
+                                                         int32_t ncell, const int32_t* __restrict__ kmap) {
     const uint32_t step = stepp ? stepp[0] : step_arg;
     constexpr bool TWO_D = GEOM != FP_COUETTE1D;
     const int64_t p = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
@@ -533,7 +537,7 @@ __global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, 
         if (TWO_D) py[p] = (T)pos[1];
         pvx[p] = (T)v[0]; pvy[p] = (T)v[1]; pvz[p] = (T)v[2];
     }
-    pkey[p] = gone ? g.nx * g.ny : cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy);
+    pkey[p] = gone ? ncell : cell_key<TWO_D>(g, pos[0], pos[1], inv_dx, inv_dy, kmap);
 }
 
 template <typename T, int G, int GEOM>
@@ -548,7 +552,7 @@ static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const
     hipLaunchKernelGGL((collide_kernel<T, G, K, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
                        c->cfg, c->ncell, off, mom, rec, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy,
                        (T*)p->vz, p->pid, p->key, step, move, stepp, c->pend, c->bidx,
-                       adv ? c->stepc : nullptr);
+                       adv ? c->stepc : nullptr, (const int32_t*)c->leafmap);
     if (move) {
         const int fr = c->ncell <= 65536 ? 2 : 4;
         const int32_t per_block = FR_BLOCK / 64 * fr;
@@ -557,12 +561,12 @@ static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const
             hipLaunchKernelGGL((flight_rest_kernel<T, GEOM, 2>), fgrid, dim3(FR_BLOCK), 0, s, c->cfg,
                                c->ncell, off, (const int32_t*)c->pend, (const int32_t*)c->bidx, (T*)p->x,
                                (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key, step, stepp,
-                               adv, (const uint32_t*)c->stepc);
+                               adv, (const uint32_t*)c->stepc, (const int32_t*)c->leafmap);
         else
             hipLaunchKernelGGL((flight_rest_kernel<T, GEOM, 4>), fgrid, dim3(FR_BLOCK), 0, s, c->cfg,
                                c->ncell, off, (const int32_t*)c->pend, (const int32_t*)c->bidx, (T*)p->x,
                                (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key, step, stepp,
-                               adv, (const uint32_t*)c->stepc);
+                               adv, (const uint32_t*)c->stepc, (const int32_t*)c->leafmap);
     }
 }
 
@@ -615,15 +619,15 @@ static void step_typed(fp_ctx* c, fp_particles* p, const int32_t* off, const dou
     if (geom == FP_CAVITY2D)
         hipLaunchKernelGGL((move_kernel<T, FP_CAVITY2D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
                            p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
-                           step, keys_only, sp);
+                           step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap);
     else if (geom == FP_CYLINDER2D)
         hipLaunchKernelGGL((move_kernel<T, FP_CYLINDER2D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
                            p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
-                           step, keys_only, sp);
+                           step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap);
     else
         hipLaunchKernelGGL((move_kernel<T, FP_COUETTE1D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
                            p->n, (T*)p->x, (T*)nullptr, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid,
-                           p->key, step, keys_only, sp);
+                           p->key, step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap);
 }
 
 
@@ -658,13 +662,13 @@ __global__ __launch_bounds__(ST_BLOCK) void inject_kernel(fp_config g, InjectGeo
                                                           T* __restrict__ px, T* __restrict__ py,
                                                           T* __restrict__ pvx, T* __restrict__ pvy,
                                                           T* __restrict__ pvz, uint32_t* __restrict__ ppid,
-                                                          int32_t* __restrict__ pkey) {
+                                                          int32_t* __restrict__ pkey, int32_t ncell,
+                                                          const int32_t* __restrict__ kmap) {
     const int32_t slot = blockIdx.x * ST_BLOCK + threadIdx.x;
     if (slot >= ig.slot0[4]) return;
     int r = 0;
     while (r < 3 && slot >= ig.slot0[r + 1]) ++r;
     const int32_t k = slot - ig.slot0[r];
-    const int32_t ncell = g.nx * g.ny;
     const bool f32 = sizeof(T) == 4;
     if (k >= cnt[r]) {
         pkey[slot] = ncell;   // unused slot
@@ -697,7 +701,7 @@ __global__ __launch_bounds__(ST_BLOCK) void inject_kernel(fp_config g, InjectGeo
     pvy[slot] = (T)v1;
     pvz[slot] = (T)v2;
     ppid[slot] = id;
-    pkey[slot] = cell_key<true>(g, sx, sy, 1.0 / g.dx, 1.0 / g.dy);
+    pkey[slot] = cell_key<true>(g, sx, sy, 1.0 / g.dx, 1.0 / g.dy, kmap);
 }
 
 __global__ void inject_advance_kernel(const int32_t* __restrict__ cnt, uint32_t* __restrict__ pid_next) {
@@ -718,7 +722,7 @@ static void inject_typed(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_n
         hipLaunchKernelGGL((inject_kernel<T>), dim3((slots + ST_BLOCK - 1) / ST_BLOCK), dim3(ST_BLOCK),
                            0, s, c->cfg, ig, step, (const int32_t*)c->inj, (const uint32_t*)pid_next,
                            (T*)p->x + at, (T*)p->y + at, (T*)p->vx + at, (T*)p->vy + at, (T*)p->vz + at,
-                           p->pid + at, p->key + at);
+                           p->pid + at, p->key + at, c->ncell, (const int32_t*)c->leafmap);
     hipLaunchKernelGGL(inject_advance_kernel, dim3(1), dim3(64), 0, s, (const int32_t*)c->inj, pid_next);
 }
 

@@ -45,6 +45,12 @@ class FPConfig(C.Structure):
     ]
 
 
+class FPAMRParams(C.Structure):
+    _fields_ = [("tau_grad", C.c_double), ("tau_coarse", C.c_double), ("shock_factor", C.c_double),
+                ("p_inf", C.c_double), ("n_max", C.c_double), ("n_grad", C.c_double),
+                ("eps", C.c_double), ("age_min", C.c_int32), ("reserved", C.c_int32)]
+
+
 class FPParticles(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("vx", C.c_void_p), ("vy", C.c_void_p),
                 ("vz", C.c_void_p), ("pid", C.c_void_p), ("key", C.c_void_p), ("n", C.c_int64)]
@@ -87,6 +93,13 @@ def load():
         L.fp_closure_nn.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
         L.fp_nn_outputs.argtypes = [vp, vp, vp, vp]
         L.fp_nn_sensitivity.argtypes = [vp, vp, vp, i32, C.c_double, u64, vp, vp]
+        L.fp_amr_init.argtypes = [vp, i32]
+        L.fp_amr_adapt.argtypes = [vp, P(FPAMRParams), vp, vp, P(FPParticles), i32, vp]
+        L.fp_amr_tree.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fp_ncell.argtypes = [vp]
+        L.fp_ncell.restype = i32
+        L.fp_amr_nodes.argtypes = [vp]
+        L.fp_amr_nodes.restype = i64
         L.fp_nn_features.argtypes = [vp, vp, i64, vp, vp]
         L.fp_closure_build.argtypes = [vp, vp, i64, vp, vp]
         L.fp_nn_grad.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp, vp, vp]
@@ -100,7 +113,8 @@ def load():
                   "fp_nn_load", "fp_closure_nn", "fp_nn_outputs", "fp_nn_sensitivity", "fp_nn_features",
                   "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
                   "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
-                  "fp_inject", "fp_cell_volumes", "fp_step_dev", "fp_counter_add", "fp_diagnostics"):
+                  "fp_inject", "fp_cell_volumes", "fp_step_dev", "fp_counter_add", "fp_diagnostics",
+                  "fp_amr_init", "fp_amr_adapt", "fp_amr_tree"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -110,7 +124,7 @@ def header_functions():
     """Names of the functions declared in include/fp.h."""
     import re
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|int64_t|const char\*)\s+(fp_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|int32_t|int64_t|const char\*)\s+(fp_\w+)\s*\(", txt, re.M)))
 
 
 def make_config(w: dict, capacity: int) -> FPConfig:
@@ -290,6 +304,30 @@ class Context:
     def cell_volumes(self, vol, stream=None):
         self._check(self.lib.fp_cell_volumes(self.h, _ptr(vol), _stream(stream)), "fp_cell_volumes")
 
+    # ---- adaptive quadtree ------------------------------------------------------------
+    def amr_init(self, max_level):
+        self._check(self.lib.fp_amr_init(self.h, int(max_level)), "fp_amr_init")
+        self.ncell = int(self.lib.fp_ncell(self.h))
+
+    def amr_adapt(self, prm, acc, samp, p, steps, stream=None):
+        """prm: dict of fp_amr_params fields.  Synchronous; updates self.ncell."""
+        q = FPAMRParams()
+        for k in ("tau_grad", "tau_coarse", "shock_factor", "p_inf", "n_max", "n_grad", "eps"):
+            setattr(q, k, float(prm[k]))
+        q.age_min = int(prm["age_min"])
+        a = p.struct() if p is not None else None
+        self._check(self.lib.fp_amr_adapt(self.h, C.byref(q), _ptr(acc), _ptr(samp),
+                                          C.byref(a) if a is not None else None, int(steps),
+                                          _stream(stream)), "fp_amr_adapt")
+        self.ncell = int(self.lib.fp_ncell(self.h))
+
+    def amr_nodes(self):
+        return int(self.lib.fp_amr_nodes(self.h))
+
+    def amr_tree(self, state=None, age=None, leafmap=None, leaf_node=None, stream=None):
+        self._check(self.lib.fp_amr_tree(self.h, _ptr(state), _ptr(age), _ptr(leafmap), _ptr(leaf_node),
+                                         _stream(stream)), "fp_amr_tree")
+
     # ---- learned closure -------------------------------------------------------------
     def closure_build(self, mom, n, sys, stream=None):
         self._check(self.lib.fp_closure_build(self.h, _ptr(mom), int(n), _ptr(sys), _stream(stream)),
@@ -317,6 +355,100 @@ class Context:
     def nn_adam(self, params, grad, m, v, t, lr, stream=None):
         self._check(self.lib.fp_nn_adam(self.h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t),
                                         float(lr), _stream(stream)), "fp_nn_adam")
+
+
+class AMRSimulation:
+    """Loop of the open cylinder domain on an adaptive quadtree (the grid of w is the
+    finest level, max_level levels below the base grid): every adapt_every steps
+    fp_amr_adapt on the sampling sums of the leaves since the last adaptation, then
+    sort (fp_bin: the re-sort needs the uniform grid) -> moments -> sums (and sample) ->
+    closure -> collide + move -> inflow injection.  One host read of the live count per
+    step, one synchronous adaptation every adapt_every steps."""
+
+    def __init__(self, w, state, max_level, prm, adapt_every, capacity=None, device="cuda"):
+        self.w, self.prm, self.adapt_every = w, dict(prm), int(adapt_every)
+        n0 = state["x"].shape[0]
+        cap = int(capacity if capacity is not None else 2 * n0 + 1_000_000)
+        self.ctx = Context(w, cap)
+        self.ctx.amr_init(max_level)
+        self.slots = self.ctx.inject_slots()
+        self.a = Particles.from_numpy(w, state, capacity=cap, device=device)
+        self.b = Particles(0, self.a.dtype, True, device, capacity=cap)
+        nf = int(w["nx"]) * int(w["ny"])   # at most this many leaves
+        self.offs = [torch.zeros(nf + 1, dtype=torch.int32, device=device) for _ in range(2)]
+        self.mom = torch.zeros((nf, MOM_STRIDE), dtype=torch.float64, device=device)
+        self.rec = torch.zeros((nf, REC_STRIDE), dtype=torch.float64, device=device)
+        self.status = torch.zeros(nf, dtype=torch.int32, device=device)
+        self.samp = torch.zeros((nf, SAMP_STRIDE), dtype=torch.float64, device=device)
+        self.acc = torch.zeros((nf, SAMP_STRIDE), dtype=torch.float64, device=device)
+        self.pid_next = torch.tensor([int(state.get("pid_next", n0))], dtype=torch.int64,
+                                     device=device).to(torch.int32)
+        self.n_total = n0
+        self.since = None
+        self.ctx.step(self.a, None, None, None, 0, STEP_KEYS)   # leaf keys from positions
+
+    @property
+    def ncell(self):
+        return self.ctx.ncell
+
+    @property
+    def offsets(self):
+        return self.offs[0][:self.ncell + 1]
+
+    def adapt(self, steps):
+        self.a.n = self.n_total
+        self.ctx.amr_adapt(self.prm, self.acc, self.samp, self.a, steps)
+
+    def step(self, s, sample=False, closure=None):
+        if self.since is None:
+            self.since = s
+        elif self.adapt_every > 0 and s - self.since >= self.adapt_every:
+            self.adapt(s - self.since)
+            self.since = s
+        self.a.n = self.n_total
+        self.b.n = self.n_total
+        self.ctx.bin(self.a, self.b, self.offs[1])
+        self.offs.reverse()
+        self.a, self.b = self.b, self.a
+        nc = self.ncell
+        live = int(self.offs[0][nc])
+        self.a.n = live
+        self.ctx.moments(self.a, self.offs[0], self.mom)
+        self.ctx.sample(self.mom, self.acc)
+        if sample:
+            self.ctx.sample(self.mom, self.samp)
+        if closure is None:
+            self.ctx.closure_solve(self.mom, self.rec, self.status)
+        else:
+            closure(self.mom, self.rec, self.status)
+        self.ctx.step(self.a, self.offs[0], self.mom, self.rec, s, STEP_COLLIDE | STEP_MOVE)
+        self.ctx.inject(self.a, live, self.pid_next, s)
+        self.n_total = live + self.slots
+
+    def run(self, step0, nsteps, n_skip=None):
+        n_skip = self.w.get("n_skip", 0) if n_skip is None else n_skip
+        for s in range(step0, step0 + nsteps):
+            self.step(s, sample=s >= n_skip)
+
+    def tree(self):
+        """Host copies: (state[nodes], age[nodes], leafmap[nx ny], leaf_node[ncell])."""
+        dev = self.mom.device
+        nodes, nf = self.ctx.amr_nodes(), self.offs[0].shape[0] - 1
+        st = torch.zeros(nodes, dtype=torch.int8, device=dev)
+        age = torch.zeros(nodes, dtype=torch.int32, device=dev)
+        lm = torch.zeros(nf, dtype=torch.int32, device=dev)
+        ln = torch.zeros(max(self.ncell, 1), dtype=torch.int32, device=dev)
+        self.ctx.amr_tree(st, age, lm, ln)
+        torch.cuda.synchronize()
+        return st.cpu().numpy(), age.cpu().numpy(), lm.cpu().numpy(), ln[:self.ncell].cpu().numpy()
+
+    def live(self):
+        """Particles after the last move and injection, deleted and unused slots removed
+        (host copy, for checks)."""
+        self.a.n = self.n_total
+        out = self.a.numpy()
+        keep = out["key"] < self.ncell
+        return {k: v[keep] for k, v in out.items()}
 
 
 class Network:

@@ -1,0 +1,208 @@
+"""Adaptive quadtree on the GPU (fp_amr_init, fp_amr_adapt and the keys of the step)
+against the oracle of the tree: decisions, states, ages, leaf numbering and fine-cell map
+bit for bit; leaf volumes and carried sampling sums to the rounding of the two
+independent gas-volume evaluations (5e-12 of a cell); a whole open-domain loop with
+adaptations against the oracle's loop composed from its steps."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import amr_oracle as A
+from oracle import oracle as O
+from paper_2606_15622_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def fp():
+    from paper_2606_15622_amd import fpgpu
+    fpgpu.load()
+    return fpgpu
+
+
+def small(prec="f64", **kw):
+    return I.cylinder(cell=1e-2, nx=80, ny=60, fnum=2.5e14, precision=prec, **kw)
+
+
+def p_inf(w):
+    return w["n_inf"] * I.KB * w["T_inf"]
+
+
+def flat_tree(t):
+    st = np.concatenate([a.ravel() for a in t.state])
+    age = np.concatenate([a.ravel() for a in t.age])
+    return st, age
+
+
+def leaf_nodes(t):
+    off = np.cumsum([0] + [(t.nbx << l) * (t.nby << l) for l in range(t.L + 1)])
+    return np.array([off[l] + iy * (t.nbx << l) + ix for (l, ix, iy) in t.leaves()])
+
+
+def acc_rows(rng, vol, mode, w):
+    """Sampling sums of the leaves: random densities, velocities and temperatures."""
+    n = len(vol)
+    R = I.KB / w["mass"]
+    acc = np.zeros((n, A.SAMP))
+    for i in range(n):
+        if mode[i] == "empty" or vol[i] <= 0:
+            acc[i, 13] = 6
+            continue
+        dens = mode[i][0]
+        th = R * mode[i][1]
+        U = np.array(mode[i][2])
+        S = dens * vol[i] / w["fnum"] * 6
+        acc[i, 0] = S
+        acc[i, 1:4] = S * U
+        vv = np.outer(U, U) + th * np.eye(3)
+        acc[i, 4:10] = S * vv[[0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
+        acc[i, 13] = 6
+    return acc
+
+
+def check(F, ctx, sim_acc, samp_g, tree, vol_o, samp_o, label):
+    nodes = ctx.amr_nodes()
+    nf = ctx.cfg.nx * ctx.cfg.ny
+    st = torch.zeros(nodes, dtype=torch.int8, device="cuda")
+    age = torch.zeros(nodes, dtype=torch.int32, device="cuda")
+    lm = torch.zeros(nf, dtype=torch.int32, device="cuda")
+    ln = torch.zeros(ctx.ncell, dtype=torch.int32, device="cuda")
+    ctx.amr_tree(st, age, lm, ln)
+    vol = torch.zeros(ctx.ncell, dtype=torch.float64, device="cuda")
+    ctx.cell_volumes(vol)
+    torch.cuda.synchronize()
+    ost, oage = flat_tree(tree)
+    assert ctx.ncell == len(tree.leaves()), label
+    np.testing.assert_array_equal(st.cpu().numpy(), ost, err_msg=label)
+    np.testing.assert_array_equal(age.cpu().numpy(), oage, err_msg=label)
+    np.testing.assert_array_equal(lm.cpu().numpy(), tree.leaf_map(), err_msg=label)
+    np.testing.assert_array_equal(ln.cpu().numpy(), leaf_nodes(tree), err_msg=label)
+    full = ctx.w["dx"] * ctx.w["dy"]
+    assert np.abs(vol.cpu().numpy() - vol_o).max() <= 5e-12 * full * 16, label
+    np.testing.assert_array_equal(vol.cpu().numpy() == 0, vol_o == 0)
+    assert np.all(sim_acc[:ctx.ncell].cpu().numpy() == 0.0), label
+    sg = samp_g[:ctx.ncell].cpu().numpy()
+    # the volume shares carry the two gas-volume evaluations' rounding (5e-12 of a fine
+    # cell, relatively larger in nearly solid cut cells, whose sums are small)
+    np.testing.assert_allclose(sg, samp_o, rtol=1e-9, atol=1e-9 * max(np.abs(samp_o).max(), 1.0),
+                               err_msg=label)
+
+
+def test_adaptations_match_oracle():
+    F = fp()
+    w = small("f64")
+    ctx = F.Context(w, 200_000)
+    L = 2
+    ctx.amr_init(L)
+    fine = O.cell_volumes(w)
+    full_fine = (w["dx"] * w["dy"]) * w["depth"]
+    tree = A.Tree(w["nx"] >> L, w["ny"] >> L, L)
+    vol, _ = A.leaf_volumes(tree, fine, w["fnum"], full_fine)
+    rng = np.random.default_rng(21)
+    prm = dict(tau_grad=0.10, tau_coarse=0.05, shock_factor=1.2, p_inf=p_inf(w), n_max=1500.0,
+               n_grad=40.0, eps=1e-300, age_min=5)
+    nf = w["nx"] * w["ny"]
+    samp_o = np.zeros((len(vol), A.SAMP))
+    samp_g = torch.zeros((nf, A.SAMP), dtype=torch.float64, device="cuda")
+    # particles: random positions in the box, a tenth of them deleted
+    npart = 50_000
+    st = {"x": w["x0"] + rng.random(npart) * w["lx"], "y": w["y0"] + rng.random(npart) * w["ly"]}
+    for k in ("vx", "vy", "vz"):
+        st[k] = rng.standard_normal(npart)
+    st["pid"] = np.arange(npart, dtype=np.uint32)
+    fk = O.keys(w, st["x"], st["y"])
+    key = A.map_keys(tree.leaf_map(), fk, nf, len(vol))
+    key[rng.random(npart) < 0.1] = len(vol)
+    st["key"] = key
+    parts = F.Particles.from_numpy(w, st, capacity=npart)
+    merged = split = 0
+    for rnd in range(5):
+        n = len(vol)
+        leaves = tree.leaves()
+        mode = []
+        for i, (l, ix, iy) in enumerate(leaves):
+            u = rng.random()
+            if u < 0.1:
+                mode.append("empty")
+            elif rnd >= 2 and l > 0:
+                # siblings share one state in every other parent: merges once old enough
+                par = (ix >> 1) + 1000 * (iy >> 1) + 10**6 * l
+                r2 = np.random.default_rng(par + 7 * rnd)
+                quiet = r2.random() < 0.6
+                if quiet:
+                    mode.append((1e20 * r2.uniform(0.5, 1.1), 200 * r2.uniform(0.8, 1.2), (2600.0, 0, 0)))
+                else:
+                    mode.append((1e20 * rng.uniform(0.5, 3.0), 200 * rng.uniform(0.5, 4.0), (2600.0, 0, 0)))
+            else:
+                mode.append((1e20 * rng.uniform(0.5, 3.0), 200 * rng.uniform(0.5, 4.0),
+                             tuple(rng.standard_normal(3) * 100)))
+        acc = acc_rows(rng, vol, mode, w)
+        if rnd == 1:
+            samp_o = acc * 3.0      # sampling sums to carry through the next adaptations
+        samp_g[:n].copy_(torch.from_numpy(samp_o))
+        acc_g = torch.zeros((nf, A.SAMP), dtype=torch.float64, device="cuda")
+        acc_g[:n].copy_(torch.from_numpy(acc))
+        steps = 10
+        parts.n = npart
+        ctx.amr_adapt(prm, acc_g, samp_g, parts, steps)
+        new, ref, mer = A.adapt(tree, acc, vol, prm, steps, w["fnum"], w["mass"])
+        vol2, _ = A.leaf_volumes(new, fine, w["fnum"], full_fine)
+        samp_o = A.remap_samp(tree, new, samp_o, vol, vol2)
+        key = np.where((key >= 0) & (key < n), new.leaf_map()[fk], len(vol2)).astype(np.int32)
+        check(F, ctx, acc_g, samp_g, new, vol2, samp_o, f"round {rnd}")
+        np.testing.assert_array_equal(parts.key[:npart].cpu().numpy(), key)
+        if rnd == 0:
+            assert ref and not mer
+        merged += len(mer)
+        split += len(ref)
+        tree, vol = new, vol2
+    assert merged > 0 and split > 0
+
+
+@pytest.mark.parametrize("L,every", [(0, 0), (2, 4)])
+def test_open_run_with_tree_matches_oracle(L, every):
+    F = fp()
+    w = small("f64", mach=10.0)
+    s = I.freestream_state(w, seed=4)
+    n0 = s["x"].shape[0]
+    prm = dict(tau_grad=0.10, tau_coarse=0.05, shock_factor=1.2, p_inf=p_inf(w), n_max=1e9,
+               n_grad=40.0, eps=1e-300, age_min=4)
+    sim = F.AMRSimulation(w, s, L, prm, every)
+    sim.run(0, 12, n_skip=0)
+    torch.cuda.synchronize()
+    g = sim.live()
+    fine = O.cell_volumes(w)
+    o, opn, tree, omom, orec, ost, osamp, ovol = A.run_open_amr(w, s, n0, 0, 12, L, prm, every, fine)
+    nl = len(tree.leaves())
+    assert sim.ncell == nl
+    gst, gage, glm, _ = sim.tree()
+    tst, tage = flat_tree(tree)
+    np.testing.assert_array_equal(gst, tst)
+    np.testing.assert_array_equal(gage, tage)
+    if L > 0:
+        assert nl > (w["nx"] >> L) * (w["ny"] >> L)     # the body's neighbourhood was split
+    keep = o["key"] < nl
+    o = {k: v[keep] for k, v in o.items()}
+    np.testing.assert_array_equal(g["pid"], o["pid"])
+    np.testing.assert_array_equal(g["key"], o["key"])
+    assert int(sim.pid_next.cpu()[0]) == opn
+    for k in ("x", "y"):
+        assert np.abs(g[k] - o[k]).max() <= 1e-9
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(g[k] - o[k]).max() <= 1e-7 * 3000.0, k
+    np.testing.assert_array_equal(sim.status[:nl].cpu().numpy(), ost)
+    np.testing.assert_allclose(sim.samp[:nl].cpu().numpy(), osamp, rtol=1e-9, atol=1e-9 * np.abs(osamp).max())
+
+
+def test_rebin_is_refused_with_a_tree():
+    F = fp()
+    w = small("f32")
+    sim = F.AMRSimulation(w, I.freestream_state(w, seed=1), 1, dict(
+        tau_grad=0.1, tau_coarse=0.05, shock_factor=1.2, p_inf=1.0, n_max=1e9, n_grad=40.0,
+        eps=1e-300, age_min=10), 0)
+    with pytest.raises(RuntimeError):
+        sim.ctx.rebin(sim.a, sim.offs[0], sim.b, sim.offs[1])
+    with pytest.raises(RuntimeError):
+        sim.ctx.amr_init(1)          # already has a tree
