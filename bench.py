@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-other", action="store_true", help="skip the Couette and cylinder lines")
     ap.add_argument("--cylinder-steps", type=int, default=20)
     ap.add_argument("--amr-steps", type=int, default=100)
+    ap.add_argument("--amr-only", action="store_true",
+                    help="run only the quadtree cylinder line (for its kernel profile)")
     return ap.parse_args()
 
 
@@ -266,6 +268,9 @@ def main():
     F.load()
     torch.cuda.set_device(0)
 
+    if args.amr_only:
+        print(json.dumps({"cylinder_amr": cylinder_amr_line(torch, F, I, args.amr_steps)}), flush=True)
+        return
     w = I.cavity(kn=args.kn, ncell=100, ppc=100, precision="f32", seed=1)
     res = run_workload(torch, F, I, w, args.steps, args.warmup, graph=True)
     res_eager = run_workload(torch, F, I, w, min(args.steps, 50), 5, graph=False, kernel_times=False)

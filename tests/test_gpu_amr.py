@@ -90,11 +90,11 @@ def check(F, ctx, sim_acc, samp_g, tree, vol_o, samp_o, label):
                                err_msg=label)
 
 
-def test_adaptations_match_oracle():
+@pytest.mark.parametrize("nx,ny,L", [(80, 60, 2), (80, 60, 1), (96, 64, 4)])
+def test_adaptations_match_oracle(nx, ny, L):
     F = fp()
-    w = small("f64")
+    w = I.cylinder(cell=1e-2, nx=nx, ny=ny, fnum=2.5e14, precision="f64")
     ctx = F.Context(w, 200_000)
-    L = 2
     ctx.amr_init(L)
     fine = O.cell_volumes(w)
     full_fine = (w["dx"] * w["dy"]) * w["depth"]
@@ -206,3 +206,8 @@ def test_rebin_is_refused_with_a_tree():
         sim.ctx.rebin(sim.a, sim.offs[0], sim.b, sim.offs[1])
     with pytest.raises(RuntimeError):
         sim.ctx.amr_init(1)          # already has a tree
+    for w2, L in ((small("f32"), 5), (small("f32"), 3), (I.cavity(ncell=16, ppc=4), 1)):
+        ctx = F.Context(w2, 1000)     # level above 4; 60 cells not a multiple of 8; no cylinder
+        with pytest.raises(RuntimeError):
+            ctx.amr_init(L)
+        assert ctx.ncell == w2["nx"] * w2["ny"]
