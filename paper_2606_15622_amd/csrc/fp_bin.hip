@@ -165,9 +165,31 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_final_kernel(
 template <int G>
 struct GatherShape {
     static constexpr int GROUPS = BIN_BLOCK / G;
-    static constexpr int CAPP = 24 * G;  // particle slots per cell held in LDS
     static constexpr int CAPC = 6 * G;   // contributions per cell held in LDS
 };
+
+// position of the r-th set bit (from 0) of a mask with more than r set bits: the half of
+// the current window that holds it, by population counts, down to one bit
+__device__ __forceinline__ int select_bit(uint64_t m, int r) {
+    int pos = 0;
+    uint32_t w = (uint32_t)m;
+    const int c = __popc(w);
+    if (r >= c) {
+        r -= c;
+        w = (uint32_t)(m >> 32);
+        pos = 32;
+    }
+#pragma unroll
+    for (int half = 16; half >= 1; half >>= 1) {
+        const int cl = __popc(w & ((1u << half) - 1u));
+        if (r >= cl) {
+            r -= cl;
+            w >>= half;
+            pos += half;
+        }
+    }
+    return pos;
+}
 
 template <typename T, int G>
 __global__ __launch_bounds__(BIN_BLOCK) void bin_gather_kernel(
@@ -181,8 +203,8 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_gather_kernel(
     int32_t* __restrict__ dkey, int32_t* __restrict__ perm) {
     using S = GatherShape<G>;
     __shared__ int32_t s_w[S::GROUPS][S::CAPC];
+    __shared__ int32_t s_base[S::GROUPS][S::CAPC];
     __shared__ uint64_t s_m[S::GROUPS][S::CAPC];
-    __shared__ int32_t s_idx[S::GROUPS][S::CAPP];
 
     // counters of the count and place passes are spent: leave them zero for the next call
     for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i <= ncell;
@@ -203,7 +225,6 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_gather_kernel(
         m = coff[cell + 1] - cb;
     }
     const bool lds_c = m <= S::CAPC;
-    const bool lds_p = np <= S::CAPP;
 
     // phase A: contributions of this cell into LDS
     if (lds_c)
@@ -213,9 +234,9 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_gather_kernel(
         }
     __syncthreads();
 
-    // phase B: slot base of every contribution = particles of contributions from
-    // earlier source waves (source waves are unique within a cell); expand lane masks
-    int32_t* idx = lds_p ? s_idx[grp] : gidx + b;
+    // phase B: slot base of every contribution = particles of contributions from earlier
+    // source waves (source waves are unique within a cell).  Cells with more
+    // contributions than LDS holds expand their masks into a slot list in gidx.
     for (int32_t j = lg; j < m; j += G) {
         const int32_t wj = lds_c ? s_w[grp][j] : cwave[cb + j];
         uint64_t mj = lds_c ? s_m[grp][j] : cmask[cb + j];
@@ -225,18 +246,37 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_gather_kernel(
             const uint64_t mi = lds_c ? s_m[grp][i] : cmask[cb + i];
             base += wi < wj ? __popcll(mi) : 0;
         }
-        const int32_t src0 = wj << 6;
-        while (mj) {
-            const int t = __builtin_ctzll(mj);
-            idx[base++] = src0 + t;
-            mj &= mj - 1;
+        if (lds_c) {
+            s_base[grp][j] = base;
+        } else {
+            int32_t* idx = gidx + b;
+            const int32_t src0 = wj << 6;
+            while (mj) {
+                const int t = __builtin_ctzll(mj);
+                idx[base++] = src0 + t;
+                mj &= mj - 1;
+            }
         }
     }
     __syncthreads();
 
-    // phase C: gather records into the destination slots
+    // phase C: every lane takes slots; the source of slot s is the r-th lane of the
+    // contribution whose range [base, base + count) holds s
     for (int32_t s = lg; s < np; s += G) {
-        const int32_t p = idx[s];
+        int32_t p;
+        if (lds_c) {
+            int32_t j = 0, r = 0;
+            for (int32_t i = 0; i < m; ++i) {
+                const int32_t bi = s_base[grp][i];
+                if (s >= bi && s < bi + __popcll(s_m[grp][i])) {
+                    j = i;
+                    r = s - bi;
+                }
+            }
+            p = (s_w[grp][j] << 6) + select_bit(s_m[grp][j], r);
+        } else {
+            p = gidx[b + s];
+        }
         const int32_t d = b + s;
         dx[d] = sx[p];
         if (sy) dy[d] = sy[p];
