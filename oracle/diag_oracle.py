@@ -62,3 +62,32 @@ def diagnostics(samp, dens_factor, mass_over_kB, theta_inf, n_inf, dg_inf):
         out[k, 18] = ds_eq - (dg - dg_inf)
         out[k, 19] = (qh @ qh) / 5.0
     return out
+
+
+def surface_coefficients(wall, t_total, w):
+    """Surface coefficients of the cylinder (Sec. "Extension to External Aerodynamics":
+    C_p, C_f, C_h along the surface angle theta, 180 degrees at the front stagnation
+    point) from the exchange sums wall[nbins][4] of the flights (per unit molecular mass:
+    hits, normal momentum, tangential momentum towards the rear, energy given to the
+    wall) accumulated over a time t_total.  Standard definitions, each bin taking both
+    halves of the circle (area 2 R (pi / nbins) depth):
+      p = m fnum S_n / (A t),  tau = m fnum S_t / (A t),  q = m fnum S_e / (A t),
+      C_p = (p - p_inf) / (rho_inf U^2 / 2),  C_f = tau / (rho_inf U^2 / 2),
+      C_h = q / (rho_inf U^3 / 2),  rho_inf = n_inf m, p_inf = n_inf k_B T_inf.
+    Returns [nbins][4]: bin-centre theta in degrees, C_p, C_f, C_h."""
+    wall = np.asarray(wall, dtype=np.float64)
+    nb = wall.shape[0]
+    m, fnum = float(w["mass"]), float(w["fnum"])
+    R, depth = float(w["circle"][2]), float(w["depth"])
+    area = 2.0 * R * (np.pi / nb) * depth
+    U = float(np.sqrt(np.sum(np.asarray(w["u_inf"], dtype=np.float64) ** 2)))
+    rho = float(w["n_inf"]) * m
+    p_inf = float(w["n_inf"]) * float(w["kB"]) * float(w["T_inf"])
+    dyn = 0.5 * rho * U * U
+    scale = m * fnum / (area * t_total)
+    out = np.zeros((nb, 4))
+    out[:, 0] = (np.arange(nb) + 0.5) * 180.0 / nb
+    out[:, 1] = (scale * wall[:, 1] - p_inf) / dyn
+    out[:, 2] = scale * wall[:, 2] / dyn
+    out[:, 3] = scale * wall[:, 3] / (dyn * U)
+    return out

@@ -549,8 +549,32 @@ static void emit_circle(const or_config* cfg, double px, double py, uint32_t pid
 /* Free flight in the open cylinder domain: straight segments between diffuse hits on
  * the circle |p - c| = R; a particle whose end point lies outside the box is deleted.
  * Returns 1 if deleted. */
+/* Exchange of one diffuse re-emission at the cylinder, per unit molecular mass, into the
+ * bin of the surface angle theta = |atan2(n_y, n_x)| (0 at the rear point, pi at the front):
+ * hits, normal momentum given to the wall v_out.n - v_in.n, tangential momentum given to
+ * the wall towards the rear (v_in - v_out).t with t the unit tangent along decreasing
+ * theta, energy given to the wall (|v_in|^2 - |v_out|^2) / 2. */
+static void wall_record(const or_config* cfg, double px, double py, const double vin[3],
+                        const double vout[3], double* wall, int32_t nbins)
+{
+    double nx = (px - cfg->circle[0]) / cfg->circle[2];
+    double ny = (py - cfg->circle[1]) / cfg->circle[2];
+    double theta = fabs(atan2(ny, nx));
+    int32_t bin = (int32_t)(theta / OR_PI * (double)nbins);
+    if (bin > nbins - 1) bin = nbins - 1;
+    if (bin < 0) bin = 0;
+    double sgn = ny >= 0.0 ? 1.0 : -1.0;
+    double tx = sgn * ny, ty = -sgn * nx;
+    double* w = wall + 4 * (int64_t)bin;
+    w[0] += 1.0;
+    w[1] += (vout[0] * nx + vout[1] * ny) - (vin[0] * nx + vin[1] * ny);
+    w[2] += (vin[0] * tx + vin[1] * ty) - (vout[0] * tx + vout[1] * ty);
+    w[3] += 0.5 * ((vin[0] * vin[0] + vin[1] * vin[1] + vin[2] * vin[2]) -
+                   (vout[0] * vout[0] + vout[1] * vout[1] + vout[2] * vout[2]));
+}
+
 static int fly_cylinder(const or_config* cfg, double pos[2], double v[3], uint32_t pid,
-                        uint32_t step)
+                        uint32_t step, double* wall, int32_t nbins)
 {
     const double cx = cfg->circle[0], cy = cfg->circle[1], R = cfg->circle[2];
     double trem = cfg->dt;
@@ -589,8 +613,10 @@ static int fly_cylinder(const or_config* cfg, double pos[2], double v[3], uint32
             break;
         }
         if (bounce == cfg->max_bounces) return 0;      /* stop on the surface */
+        double vin[3] = {v[0], v[1], v[2]};
         emit_circle(cfg, pos[0], pos[1], pid, step, (uint32_t)bounce, v);
         for (int i = 0; i < 3; ++i) v[i] = store(cfg, v[i]);
+        if (wall) wall_record(cfg, pos[0], pos[1], vin, v, wall, nbins);
         trem = trem - th;
     }
     double x1 = cfg->x0 + cfg->lx, y1 = cfg->y0 + cfg->ly;
@@ -600,12 +626,19 @@ static int fly_cylinder(const or_config* cfg, double pos[2], double v[3], uint32
 void or_move(const or_config* cfg, int64_t n, double* x, double* y, double* vx, double* vy,
              double* vz, const uint32_t* pid, int32_t* key, uint32_t step)
 {
+    or_move_wall(cfg, n, x, y, vx, vy, vz, pid, key, step, NULL, 0);
+}
+
+void or_move_wall(const or_config* cfg, int64_t n, double* x, double* y, double* vx,
+                  double* vy, double* vz, const uint32_t* pid, int32_t* key, uint32_t step,
+                  double* wall, int32_t nbins)
+{
     if (cfg->geometry == OR_CYLINDER2D) {
         int32_t ncell = cfg->nx * cfg->ny;
         for (int64_t p = 0; p < n; ++p) {
             double pos[2] = {x[p], y[p]};
             double v[3] = {vx[p], vy[p], vz[p]};
-            int gone = fly_cylinder(cfg, pos, v, pid[p], step);
+            int gone = fly_cylinder(cfg, pos, v, pid[p], step, wall, nbins);
             x[p] = store(cfg, pos[0]);
             y[p] = store(cfg, pos[1]);
             vx[p] = v[0]; vy[p] = v[1]; vz[p] = v[2];

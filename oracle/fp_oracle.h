@@ -114,6 +114,13 @@ void or_update(const or_config* cfg, int32_t ncell, const int32_t* offsets, doub
  * open cylinder domain a particle leaving the box gets key = ncell (deleted) */
 void or_move(const or_config* cfg, int64_t n, double* x, double* y, double* vx, double* vy,
              double* vz, const uint32_t* pid, int32_t* key, uint32_t step);
+/* or_move that also adds the exchange of every re-emission at the cylinder to
+ * wall[nbins][4] (per unit molecular mass, bins of the surface angle theta = |atan2| from
+ * the rear point): hits, normal momentum, tangential momentum towards the rear, energy
+ * given to the wall.  wall = NULL: plain or_move. */
+void or_move_wall(const or_config* cfg, int64_t n, double* x, double* y, double* vx,
+                  double* vy, double* vz, const uint32_t* pid, int32_t* key, uint32_t step,
+                  double* wall, int32_t nbins);
 /* Inflow through the open boundaries of the cylinder domain: candidates drawn uniformly
  * in a buffer frame of width (|u_inf| + 4 sqrt(2 R T_inf)) dt around the domain with a
  * Maxwellian(u_inf, T_inf) velocity fly for dt; those ending inside the domain are

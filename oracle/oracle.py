@@ -77,6 +77,8 @@ def _declare(L):
     L.or_closure.argtypes = [cfgp, i32, P(d), P(d), P(d), P(i32)]
     L.or_update.argtypes = [cfgp, i32, P(i32), P(d), P(d), P(d), P(u32), P(d), P(d), u32]
     L.or_move.argtypes = [cfgp, i64, P(d), P(d), P(d), P(d), P(d), P(u32), P(i32), u32]
+    L.or_move_wall.argtypes = [cfgp, i64, P(d), P(d), P(d), P(d), P(d), P(u32), P(i32), u32,
+                               P(d), i32]
     L.or_sample.argtypes = [i32, P(i32), P(d), P(d), P(d), P(d)]
     L.or_run.argtypes = [cfgp, i64, P(d), P(d), P(d), P(d), P(d), P(u32), P(i32), u32, i32,
                          u32, P(d), P(d), P(i32), P(d)]
@@ -237,8 +239,9 @@ def update(w, offsets, vx, vy, vz, pid, mom, rec, step):
     return vx, vy, vz
 
 
-def move(w, x, y, vx, vy, vz, pid, step):
-    """Returns (x, y, vx, vy, vz, key) after free flight with walls."""
+def move(w, x, y, vx, vy, vz, pid, step, wall=None):
+    """Returns (x, y, vx, vy, vz, key) after free flight with walls.  wall: optional
+    float64 array [nbins][4] to which the cylinder exchange sums are added in place."""
     L = lib()
     cfg = make_config(w)
     x = _f64(x).copy()
@@ -247,9 +250,16 @@ def move(w, x, y, vx, vy, vz, pid, step):
     pid = np.ascontiguousarray(pid, dtype=np.uint32)
     n = x.shape[0]
     key = np.empty(n, dtype=np.int32)
-    L.or_move(C.byref(cfg), n, _p(x, C.c_double), _p(y, C.c_double), _p(vx, C.c_double),
-              _p(vy, C.c_double), _p(vz, C.c_double), _p(pid, C.c_uint32),
-              _p(key, C.c_int32), int(step))
+    if wall is None:
+        L.or_move(C.byref(cfg), n, _p(x, C.c_double), _p(y, C.c_double), _p(vx, C.c_double),
+                  _p(vy, C.c_double), _p(vz, C.c_double), _p(pid, C.c_uint32),
+                  _p(key, C.c_int32), int(step))
+    else:
+        assert wall.dtype == np.float64 and wall.flags.c_contiguous and wall.shape[1] == 4
+        L.or_move_wall(C.byref(cfg), n, _p(x, C.c_double), _p(y, C.c_double),
+                       _p(vx, C.c_double), _p(vy, C.c_double), _p(vz, C.c_double),
+                       _p(pid, C.c_uint32), _p(key, C.c_int32), int(step),
+                       _p(wall, C.c_double), int(wall.shape[0]))
     return x, y, vx, vy, vz, key
 
 
