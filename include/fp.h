@@ -216,6 +216,26 @@ int64_t fp_inject_slots(const fp_ctx* ctx);
  * area count as solid, volume 0); box geometries dx dy (1 m depth). */
 int fp_cell_volumes(fp_ctx* ctx, double* vol, hipStream_t s);
 
+/* Surface sampling of the cylinder (for the C_p, C_f, C_h distributions of Sec.
+ * "Extension to External Aerodynamics"): while sums is set, every diffuse re-emission at
+ * the body during fp_step (MOVE) adds its exchange to sums[nbins][4] (device doubles,
+ * caller-owned, zeroed by the caller): hits, normal momentum v_out.n - v_in.n, tangential
+ * momentum towards the rear (v_in - v_out).t, energy (|v_in|^2 - |v_out|^2)/2, per unit
+ * molecular mass, n the outward normal, t the tangent along decreasing theta, in bins of
+ * the surface angle theta = |atan2(n_y, n_x)| (0 at the rear point, pi at the front
+ * stagnation point; both halves of the circle share a bin).  FP64 atomic adds (their
+ * order, and so the last bits of the sums, vary from run to run).  sums = NULL stops.
+ * A HIP graph captured meanwhile keeps the pointer.  FP_EINVAL for other geometries or
+ * nbins outside [1, 65536]. */
+int fp_wall_sampling(fp_ctx* ctx, double* sums, int32_t nbins);
+/* Surface coefficients from such sums gathered over a time t_total [s]: out[nbins][4]
+ * (device) = (bin-centre theta in degrees, C_p, C_f, C_h) with A = 2 R (pi / nbins) depth,
+ * p = m fnum S_n / (A t), tau = m fnum S_t / (A t), q = m fnum S_e / (A t),
+ * C_p = (p - p_inf) / (rho_inf U^2 / 2), C_f = tau / (rho_inf U^2 / 2),
+ * C_h = q / (rho_inf U^3 / 2), rho_inf = n_inf m, p_inf = n_inf k_B T_inf, U = |u_inf|. */
+int fp_surface_coefficients(fp_ctx* ctx, const double* sums, int32_t nbins, double t_total,
+                            double* out, hipStream_t s);
+
 /* ---- adaptive quadtree of the cylinder domain -----------------------------------------
  * Sec. "Extension to External Aerodynamics", Problem Description: hierarchical Cartesian
  * quadtree, cells split on the normalised deviation |phi - phi_parent| / (|phi| + eps)

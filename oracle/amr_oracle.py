@@ -282,13 +282,14 @@ def map_keys(leafmap, fine_key, nfine, nleaf):
 
 
 def run_open_amr(w, state, pid_next, step0, nsteps, max_level, prm, adapt_every, fine_vol,
-                 n_skip=0):
+                 n_skip=0, wall=None):
     """The open cylinder loop on the tree, composed from the oracle's steps: every
     adapt_every steps an adaptation on the sums since the last one (keys of the particles
     from their positions, sampling sums carried over), then sort, moments, sums, closure
     (density from the leaf gas volumes), velocity update, flight, injection.  fine_vol:
     gas volumes of the fine cells.  Returns (state, pid_next, tree, mom, rec, status,
-    samp, vol) after the last step."""
+    samp, vol) after the last step.  wall (optional, [nbins][4]): the exchange sums at the
+    body are added to it."""
     from oracle import oracle as O
     nx, ny = int(w["nx"]), int(w["ny"])
     nfine = nx * ny
@@ -330,7 +331,7 @@ def run_open_amr(w, state, pid_next, step0, nsteps, max_level, prm, adapt_every,
         rec, st = O.closure(w, mom, nvol)
         s["vx"], s["vy"], s["vz"] = O.update(w, off, s["vx"], s["vy"], s["vz"], s["pid"], mom, rec, step)
         s["x"], s["y"], s["vx"], s["vy"], s["vz"], fk = O.move(w, s["x"], s["y"], s["vx"], s["vy"],
-                                                               s["vz"], s["pid"], step)
+                                                               s["vz"], s["pid"], step, wall=wall)
         key = map_keys(lm, fk, nfine, nleaf)
         inj, pid_next = O.inject(w, step, pid_next)
         for k in ("x", "y", "vx", "vy", "vz", "pid"):

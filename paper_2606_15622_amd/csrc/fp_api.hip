@@ -212,7 +212,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     for (void* q : {(void*)c->amr_state, (void*)c->amr_flag, (void*)c->amr_age, (void*)c->amr_sum,
                     (void*)c->leafmap, (void*)c->leafmap_old, (void*)c->leaf_node, (void*)c->leaf_node_old,
                     (void*)c->amr_first, (void*)c->amr_part, (void*)c->fine_vol, (void*)c->vol_old,
-                    (void*)c->samp_old})
+                    (void*)c->samp_old, (void*)c->wall_edge})
         (void)hipFree(q);
     (void)hipFree(c->inj);
     delete c;
@@ -318,6 +318,39 @@ extern "C" int fp_diagnostics(fp_ctx* c, const double* samp, double theta_inf, d
     if (!c || !samp || !diag || !(theta_inf > 0.0) || !(n_inf > 0.0) || !std::isfinite(dg_inf))
         return set_err(c, FP_EINVAL, "fp_diagnostics: bad argument");
     return launch_diagnostics(c, samp, theta_inf, n_inf, dg_inf, diag, s);
+}
+
+extern "C" int fp_wall_sampling(fp_ctx* c, double* sums, int32_t nbins) {
+    if (!c) return FP_EINVAL;
+    if (c->cfg.geometry != FP_CYLINDER2D)
+        return set_err(c, FP_EINVAL, "fp_wall_sampling: the cylinder domain only");
+    if (sums && (nbins < 1 || nbins > 65536)) return set_err(c, FP_EINVAL, "fp_wall_sampling: nbins");
+    c->wall = nullptr;
+    c->wall_nbins = 0;
+    if (!sums) return FP_OK;
+    // bin edges by the cosine of the surface angle (host cosines, copied once)
+    std::vector<double> edge((size_t)nbins + 1);
+    for (int32_t k = 0; k <= nbins; ++k) edge[k] = std::cos((double)k * 3.14159265358979323846 / (double)nbins);
+    (void)hipFree(c->wall_edge);
+    c->wall_edge = nullptr;
+    if (hipMalloc((void**)&c->wall_edge, sizeof(double) * edge.size()) != hipSuccess ||
+        hipMemcpy(c->wall_edge, edge.data(), sizeof(double) * edge.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return set_err(c, FP_ENOMEM, "fp_wall_sampling: allocation failed");
+    c->wall = sums;
+    c->wall_nbins = nbins;
+    return FP_OK;
+}
+
+extern "C" int fp_surface_coefficients(fp_ctx* c, const double* sums, int32_t nbins, double t_total,
+                                       double* out, hipStream_t s) {
+    if (!c || !sums || !out || nbins < 1 || nbins > 65536 || !(t_total > 0.0))
+        return set_err(c, FP_EINVAL, "fp_surface_coefficients: bad argument");
+    if (c->cfg.geometry != FP_CYLINDER2D || !(c->cfg.n_inf > 0.0))
+        return set_err(c, FP_EINVAL, "fp_surface_coefficients: needs the cylinder's free stream");
+    const double U2 = c->cfg.u_inf[0] * c->cfg.u_inf[0] + c->cfg.u_inf[1] * c->cfg.u_inf[1] +
+                      c->cfg.u_inf[2] * c->cfg.u_inf[2];
+    if (!(U2 > 0.0)) return set_err(c, FP_EINVAL, "fp_surface_coefficients: free stream at rest");
+    return launch_surface(c, sums, nbins, t_total, out, s);
 }
 
 extern "C" int fp_sample(fp_ctx* c, const double* mom, double* samp, hipStream_t s) {

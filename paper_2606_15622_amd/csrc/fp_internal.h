@@ -46,6 +46,11 @@ struct fp_ctx {
     double inj_rect[4][4] = {};  // x_a, x_b, y_a, y_b of the four inflow rectangles
     double inj_lambda[4] = {};   // expected candidates per rectangle and step
     int32_t inj_slot0[5] = {};   // slot prefix: floor(lambda_r) + 1 slots per rectangle
+    // surface sampling of the cylinder (fp_wall_sampling): exchange sums of the
+    // re-emissions at the body, [wall_nbins][4], caller-owned
+    double* wall = nullptr;
+    double* wall_edge = nullptr;  // [wall_nbins + 1] cos(k pi / nbins), library-owned
+    int32_t wall_nbins = 0;
     // adaptive quadtree (fp_amr_init; the grid of cfg is the finest level): ncell is then
     // the number of leaves and every key is looked up in leafmap
     int32_t amr_L = -1;          // levels below the base grid, -1: no tree
@@ -204,6 +209,8 @@ int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* o
                int32_t* perm, hipStream_t s);
 int launch_diagnostics(fp_ctx* c, const double* samp, double theta_inf, double n_inf,
                        double dg_inf, double* diag, hipStream_t s);
+int launch_surface(fp_ctx* c, const double* sums, int32_t nbins, double t_total, double* out,
+                   hipStream_t s);
 int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_particles* dst,
                  int32_t* offsets, int32_t* perm, double* mom, double* samp, hipStream_t s);
 int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,

@@ -3,6 +3,8 @@
 // added to the running sums.
 #include "fp_sample_dev.h"
 
+#include <cmath>
+
 namespace fpg {
 
 // 64 cells per workgroup: their moment records and sums are staged through LDS with
@@ -121,6 +123,33 @@ int launch_diagnostics(fp_ctx* c, const double* samp, double theta_inf, double n
                        (const double*)c->nvol, c->cfg.fnum_over_vol, c->cfg.mass / c->cfg.kB,
                        theta_inf, n_inf, dg_inf, diag);
     return check_launch(c, "fp_diagnostics");
+}
+
+// surface coefficients of the cylinder from the exchange sums of the re-emissions: one
+// thread per bin; each bin holds both halves of the circle (area 2 R (pi / nbins) depth)
+__global__ void surface_kernel(int32_t nbins, const double* __restrict__ sums, double scale,
+                               double p_inf, double dyn, double U, double* __restrict__ out) {
+    const int32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nbins) return;
+    const double* w = sums + 4 * (int64_t)b;
+    double* o = out + 4 * (int64_t)b;
+    o[0] = ((double)b + 0.5) * 180.0 / (double)nbins;
+    o[1] = (scale * w[1] - p_inf) / dyn;
+    o[2] = scale * w[2] / dyn;
+    o[3] = scale * w[3] / (dyn * U);
+}
+
+int launch_surface(fp_ctx* c, const double* sums, int32_t nbins, double t_total, double* out,
+                   hipStream_t s) {
+    const fp_config& g = c->cfg;
+    const double area = 2.0 * g.circle[2] * (3.14159265358979323846 / (double)nbins) * g.depth;
+    const double U = std::sqrt(g.u_inf[0] * g.u_inf[0] + g.u_inf[1] * g.u_inf[1] + g.u_inf[2] * g.u_inf[2]);
+    const double rho = g.n_inf * g.mass;
+    const double dyn = 0.5 * rho * U * U;
+    const double scale = g.mass * g.fnum / (area * t_total);
+    hipLaunchKernelGGL(surface_kernel, dim3((nbins + 255) / 256), dim3(256), 0, s, nbins, sums, scale,
+                       g.n_inf * g.kB * g.T_inf, dyn, U, out);
+    return check_launch(c, "fp_surface_coefficients");
 }
 
 int launch_sample(fp_ctx* c, const double* mom, double* samp, hipStream_t s) {

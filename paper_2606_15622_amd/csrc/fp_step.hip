@@ -141,10 +141,41 @@ __device__ __forceinline__ void circle_emit(const fp_config& g, double px, doubl
     v[2] = s * zb;
 }
 
+// exchange of one re-emission at the body, per unit molecular mass, into the bin of the
+// surface angle theta (0 at the rear point, pi at the front) with cos theta = n_x: bin b
+// holds edge[b + 1] < n_x <= edge[b], edge[k] = cos(k pi / nbins) (host cosines, found by
+// bisection): hits, normal momentum v_out.n - v_in.n, tangential momentum towards the
+// rear (v_in - v_out).t (t the unit tangent along decreasing theta), energy
+// (|v_in|^2 - |v_out|^2) / 2
+__device__ __forceinline__ void wall_record(const fp_config& g, double px, double py, const double vin[3],
+                                            const double vout[3], double* __restrict__ wall,
+                                            const double* __restrict__ edge, int32_t nbins) {
+    const double nx = (px - g.circle[0]) / g.circle[2];
+    const double ny = (py - g.circle[1]) / g.circle[2];
+    int32_t lo = 0, hi = nbins;   // nx <= edge[lo] (edge[0] = 1), nx > edge[hi] unless hi = nbins
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (nx <= edge[mid]) lo = mid;
+        else hi = mid;
+    }
+    const double sg = ny >= 0.0 ? 1.0 : -1.0;
+    const double tx = sg * ny, ty = -sg * nx;
+    double* w = wall + 4 * (int64_t)lo;
+    unsafeAtomicAdd(w, 1.0);
+    unsafeAtomicAdd(w + 1, (vout[0] * nx + vout[1] * ny) - (vin[0] * nx + vin[1] * ny));
+    unsafeAtomicAdd(w + 2, (vin[0] * tx + vin[1] * ty) - (vout[0] * tx + vout[1] * ty));
+    unsafeAtomicAdd(w + 3, 0.5 * ((vin[0] * vin[0] + vin[1] * vin[1] + vin[2] * vin[2]) -
+                                  (vout[0] * vout[0] + vout[1] * vout[1] + vout[2] * vout[2])));
+}
+
 // free flight in the open cylinder domain: straight segments between diffuse hits on the
-// circle; returns true if the particle ends outside the box (deleted)
+// circle; returns true if the particle ends outside the box (deleted).  wall (optional):
+// exchange sums of the re-emissions, nbins bins of the surface angle
+template <bool REC = false>
 __device__ __forceinline__ bool fly_open(const fp_config& g, double pos[2], double v[3],
-                                         uint32_t pid, uint32_t step, bool f32) {
+                                         uint32_t pid, uint32_t step, bool f32,
+                                         double* __restrict__ wall = nullptr,
+                                         const double* __restrict__ edge = nullptr, int32_t nbins = 0) {
     const double cx = g.circle[0], cy = g.circle[1], R = g.circle[2];
     double trem = g.dt;
     for (int bounce = 0;; ++bounce) {
@@ -182,10 +213,12 @@ __device__ __forceinline__ bool fly_open(const fp_config& g, double pos[2], doub
             break;
         }
         if (bounce == g.max_bounces) return false;   // stop on the surface
+        [[maybe_unused]] const double vin[3] = {v[0], v[1], v[2]};
         circle_emit(g, pos[0], pos[1], pid, step, (uint32_t)bounce, v);
         v[0] = st_round(v[0], f32);
         v[1] = st_round(v[1], f32);
         v[2] = st_round(v[2], f32);
+        if constexpr (REC) wall_record(g, pos[0], pos[1], vin, v, wall, edge, nbins);
         trem = trem - th;
     }
     const double x1 = g.x0 + g.lx, y1 = g.y0 + g.ly;
@@ -455,14 +488,15 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
 // in this kernel) to the next step number.
 constexpr int FR_BLOCK = 256;
 
-template <typename T, int GEOM, int FR>
+template <typename T, int GEOM, int FR, bool REC = false>
 __global__ __launch_bounds__(FR_BLOCK) void flight_rest_kernel(
     fp_config g, int32_t ncell, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ pend, const int32_t* __restrict__ plist, T* __restrict__ px,
     T* __restrict__ py, T* __restrict__ pvx, T* __restrict__ pvy, T* __restrict__ pvz,
     const uint32_t* __restrict__ ppid, int32_t* __restrict__ pkey, uint32_t step_arg,
     const uint32_t* stepp, uint32_t* adv, const uint32_t* __restrict__ stepc,
-    const int32_t* __restrict__ kmap) {
+    const int32_t* __restrict__ kmap, double* __restrict__ wall, const double* __restrict__ wall_edge,
+    int32_t wall_nbins) {
     constexpr int FR_CELLS = FR;
     if (adv && blockIdx.x == 0 && threadIdx.x == 0) adv[0] = stepc[0] + 1u;
     const int lane = threadIdx.x & 63;
@@ -493,7 +527,7 @@ __global__ __launch_bounds__(FR_BLOCK) void flight_rest_kernel(
         double v[3] = {(double)pvx[p], (double)pvy[p], (double)pvz[p]};
         bool gone = false;
         if constexpr (GEOM == FP_CYLINDER2D) {
-            gone = fly_open(g, pos, v, ppid[p], step, f32);
+            gone = fly_open<REC>(g, pos, v, ppid[p], step, f32, wall, wall_edge, wall_nbins);
             pos[0] = st_round(pos[0], f32);
             pos[1] = st_round(pos[1], f32);
         } else {
@@ -507,14 +541,16 @@ __global__ __launch_bounds__(FR_BLOCK) void flight_rest_kernel(
 }
 
 // flight (or key recomputation) without a collision: one thread per particle
-template <typename T, int GEOM>
+template <typename T, int GEOM, bool REC = false>
 __global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, T* __restrict__ px,
                                                          T* __restrict__ py, T* __restrict__ pvx,
                                                          T* __restrict__ pvy, T* __restrict__ pvz,
                                                          const uint32_t* __restrict__ ppid,
                                                          int32_t* __restrict__ pkey, uint32_t step_arg,
                                                          int keys_only, const uint32_t* __restrict__ stepp,
-                                                         int32_t ncell, const int32_t* __restrict__ kmap) {
+                                                         int32_t ncell, const int32_t* __restrict__ kmap,
+                                                         double* __restrict__ wall,
+                                                         const double* __restrict__ wall_edge, int32_t wall_nbins) {
     const uint32_t step = stepp ? stepp[0] : step_arg;
     constexpr bool TWO_D = GEOM != FP_COUETTE1D;
     const int64_t p = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
@@ -526,7 +562,7 @@ __global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, 
         const bool f32 = sizeof(T) == 4;
         double v[3] = {(double)pvx[p], (double)pvy[p], (double)pvz[p]};
         if constexpr (GEOM == FP_CYLINDER2D) {
-            gone = fly_open(g, pos, v, ppid[p], step, f32);
+            gone = fly_open<REC>(g, pos, v, ppid[p], step, f32, wall, wall_edge, wall_nbins);
             pos[0] = st_round(pos[0], f32);
             pos[1] = st_round(pos[1], f32);
         } else {
@@ -557,16 +593,23 @@ static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const
         const int fr = c->ncell <= 65536 ? 2 : 4;
         const int32_t per_block = FR_BLOCK / 64 * fr;
         const dim3 fgrid((c->ncell + per_block - 1) / per_block);
-        if (fr == 2)
-            hipLaunchKernelGGL((flight_rest_kernel<T, GEOM, 2>), fgrid, dim3(FR_BLOCK), 0, s, c->cfg,
-                               c->ncell, off, (const int32_t*)c->pend, (const int32_t*)c->bidx, (T*)p->x,
-                               (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key, step, stepp,
-                               adv, (const uint32_t*)c->stepc, (const int32_t*)c->leafmap);
-        else
-            hipLaunchKernelGGL((flight_rest_kernel<T, GEOM, 4>), fgrid, dim3(FR_BLOCK), 0, s, c->cfg,
-                               c->ncell, off, (const int32_t*)c->pend, (const int32_t*)c->bidx, (T*)p->x,
-                               (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key, step, stepp,
-                               adv, (const uint32_t*)c->stepc, (const int32_t*)c->leafmap);
+        // surface sampling: a variant with the exchange records (their registers stay out
+        // of the plain kernel)
+        auto fr_launch = [&](auto kern) {
+            hipLaunchKernelGGL(kern, fgrid, dim3(FR_BLOCK), 0, s, c->cfg, c->ncell, off,
+                               (const int32_t*)c->pend, (const int32_t*)c->bidx, (T*)p->x, (T*)p->y,
+                               (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key, step, stepp, adv,
+                               (const uint32_t*)c->stepc, (const int32_t*)c->leafmap, c->wall,
+                               (const double*)c->wall_edge, c->wall_nbins);
+        };
+        const bool rec = GEOM == FP_CYLINDER2D && c->wall != nullptr;
+        if (fr == 2) {
+            if (rec) fr_launch(flight_rest_kernel<T, GEOM, 2, GEOM == FP_CYLINDER2D>);
+            else fr_launch(flight_rest_kernel<T, GEOM, 2, false>);
+        } else {
+            if (rec) fr_launch(flight_rest_kernel<T, GEOM, 4, GEOM == FP_CYLINDER2D>);
+            else fr_launch(flight_rest_kernel<T, GEOM, 4, false>);
+        }
     }
 }
 
@@ -619,15 +662,23 @@ static void step_typed(fp_ctx* c, fp_particles* p, const int32_t* off, const dou
     if (geom == FP_CAVITY2D)
         hipLaunchKernelGGL((move_kernel<T, FP_CAVITY2D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
                            p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
-                           step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap);
+                           step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap, c->wall,
+                           (const double*)c->wall_edge, c->wall_nbins);
+    else if (geom == FP_CYLINDER2D && c->wall)
+        hipLaunchKernelGGL((move_kernel<T, FP_CYLINDER2D, true>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
+                           p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
+                           step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap, c->wall,
+                           (const double*)c->wall_edge, c->wall_nbins);
     else if (geom == FP_CYLINDER2D)
         hipLaunchKernelGGL((move_kernel<T, FP_CYLINDER2D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
                            p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
-                           step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap);
+                           step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap, c->wall,
+                           (const double*)c->wall_edge, c->wall_nbins);
     else
         hipLaunchKernelGGL((move_kernel<T, FP_COUETTE1D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
                            p->n, (T*)p->x, (T*)nullptr, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid,
-                           p->key, step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap);
+                           p->key, step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap, c->wall,
+                           (const double*)c->wall_edge, c->wall_nbins);
 }
 
 

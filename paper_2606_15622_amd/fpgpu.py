@@ -93,6 +93,8 @@ def load():
         L.fp_closure_nn.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
         L.fp_nn_outputs.argtypes = [vp, vp, vp, vp]
         L.fp_nn_sensitivity.argtypes = [vp, vp, vp, i32, C.c_double, u64, vp, vp]
+        L.fp_wall_sampling.argtypes = [vp, vp, i32]
+        L.fp_surface_coefficients.argtypes = [vp, vp, i32, C.c_double, vp, vp]
         L.fp_amr_init.argtypes = [vp, i32]
         L.fp_amr_adapt.argtypes = [vp, P(FPAMRParams), vp, vp, P(FPParticles), i32, vp]
         L.fp_amr_tree.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -114,7 +116,8 @@ def load():
                   "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
                   "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
                   "fp_inject", "fp_cell_volumes", "fp_step_dev", "fp_counter_add", "fp_diagnostics",
-                  "fp_amr_init", "fp_amr_adapt", "fp_amr_tree"):
+                  "fp_amr_init", "fp_amr_adapt", "fp_amr_tree", "fp_wall_sampling",
+                  "fp_surface_coefficients"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -303,6 +306,17 @@ class Context:
 
     def cell_volumes(self, vol, stream=None):
         self._check(self.lib.fp_cell_volumes(self.h, _ptr(vol), _stream(stream)), "fp_cell_volumes")
+
+    # ---- surface sampling of the cylinder ---------------------------------------------
+    def wall_sampling(self, sums):
+        """sums: float64 tensor [nbins][4] on the device (None stops)."""
+        nb = int(sums.shape[0]) if sums is not None else 0
+        self._check(self.lib.fp_wall_sampling(self.h, _ptr(sums), nb), "fp_wall_sampling")
+
+    def surface_coefficients(self, sums, t_total, out, stream=None):
+        self._check(self.lib.fp_surface_coefficients(self.h, _ptr(sums), int(sums.shape[0]),
+                                                     float(t_total), _ptr(out), _stream(stream)),
+                    "fp_surface_coefficients")
 
     # ---- adaptive quadtree ------------------------------------------------------------
     def amr_init(self, max_level):

@@ -182,3 +182,41 @@ def test_cylinder_full_size_one_step():
     for k in ("vx", "vy", "vz"):
         assert np.abs(g[k] - o[k]).max() <= 1e-5 * (sc + 2700.0), k
     assert np.abs(g["x"] - o["x"]).max() <= 1e-6
+
+
+def test_surface_sampling_matches_oracle():
+    """Exchange sums at the body over 12 steps of the open loop against the oracle's loop
+    (hit counts exact; momentum and energy sums to the order of the FP64 atomic adds and
+    the 1e-9 agreement of the trajectories), and the surface coefficients computed from
+    them against the oracle's formulas."""
+    from oracle import amr_oracle as A
+    from oracle import diag_oracle as D
+    F = fp()
+    w = small("f64", mach=10.0)
+    s = I.freestream_state(w, seed=4)
+    s["key"] = O.keys(w, s["x"], s["y"])
+    n0 = s["x"].shape[0]
+    nb = 18
+    sim = F.OpenSimulation(w, s)
+    sums = torch.zeros((nb, 4), dtype=torch.float64, device="cuda")
+    sim.ctx.wall_sampling(sums)
+    sim.run(0, 12, n_skip=0)
+    sim.ctx.wall_sampling(None)
+    sim.step(12)                       # not recorded
+    torch.cuda.synchronize()
+    g = sums.cpu().numpy()
+    wall = np.zeros((nb, 4))
+    A.run_open_amr(w, s, n0, 0, 12, 0, {}, 0, O.cell_volumes(w), wall=wall)
+    assert wall[:, 0].sum() > 1000
+    np.testing.assert_array_equal(g[:, 0], wall[:, 0])
+    for k in (1, 2, 3):
+        np.testing.assert_allclose(g[:, k], wall[:, k], rtol=1e-8, atol=1e-8 * np.abs(wall[:, k]).max())
+    out = torch.zeros((nb, 4), dtype=torch.float64, device="cuda")
+    t = 12 * w["dt"]
+    sim.ctx.surface_coefficients(sums, t, out)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out.cpu().numpy(), D.surface_coefficients(g, t, w), rtol=1e-12, atol=1e-15)
+    c = out.cpu().numpy()
+    assert c[-1, 1] > 1.0                  # stagnation region: C_p of order 2
+    with pytest.raises(RuntimeError):
+        sim.ctx.surface_coefficients(sums, 0.0, out)
