@@ -550,7 +550,9 @@ static void emit_circle(const or_config* cfg, double px, double py, uint32_t pid
  * the circle |p - c| = R; a particle whose end point lies outside the box is deleted.
  * Returns 1 if deleted. */
 /* Exchange of one diffuse re-emission at the cylinder, per unit molecular mass, into the
- * bin of the surface angle theta = |atan2(n_y, n_x)| (0 at the rear point, pi at the front):
+ * bin of the surface angle theta (0 at the rear point, pi at the front; cos theta = n_x):
+ * bin b holds the points with cos((b+1) pi / nbins) < n_x <= cos(b pi / nbins), i.e. b is
+ * the number of interior edges k = 1 .. nbins-1 with n_x <= cos(k pi / nbins).  Recorded:
  * hits, normal momentum given to the wall v_out.n - v_in.n, tangential momentum given to
  * the wall towards the rear (v_in - v_out).t with t the unit tangent along decreasing
  * theta, energy given to the wall (|v_in|^2 - |v_out|^2) / 2. */
@@ -559,10 +561,9 @@ static void wall_record(const or_config* cfg, double px, double py, const double
 {
     double nx = (px - cfg->circle[0]) / cfg->circle[2];
     double ny = (py - cfg->circle[1]) / cfg->circle[2];
-    double theta = fabs(atan2(ny, nx));
-    int32_t bin = (int32_t)(theta / OR_PI * (double)nbins);
-    if (bin > nbins - 1) bin = nbins - 1;
-    if (bin < 0) bin = 0;
+    int32_t bin = 0;
+    for (int32_t k = 1; k < nbins; ++k)
+        if (nx <= cos((double)k * OR_PI / (double)nbins)) bin = k;
     double sgn = ny >= 0.0 ? 1.0 : -1.0;
     double tx = sgn * ny, ty = -sgn * nx;
     double* w = wall + 4 * (int64_t)bin;

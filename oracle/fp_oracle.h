@@ -115,9 +115,10 @@ void or_update(const or_config* cfg, int32_t ncell, const int32_t* offsets, doub
 void or_move(const or_config* cfg, int64_t n, double* x, double* y, double* vx, double* vy,
              double* vz, const uint32_t* pid, int32_t* key, uint32_t step);
 /* or_move that also adds the exchange of every re-emission at the cylinder to
- * wall[nbins][4] (per unit molecular mass, bins of the surface angle theta = |atan2| from
- * the rear point): hits, normal momentum, tangential momentum towards the rear, energy
- * given to the wall.  wall = NULL: plain or_move. */
+ * wall[nbins][4] (per unit molecular mass, bins of the surface angle theta from the rear
+ * point by the edges cos(k pi / nbins) of cos theta = n_x): hits, normal momentum,
+ * tangential momentum towards the rear, energy given to the wall.  wall = NULL: plain
+ * or_move. */
 void or_move_wall(const or_config* cfg, int64_t n, double* x, double* y, double* vx,
                   double* vy, double* vz, const uint32_t* pid, int32_t* key, uint32_t step,
                   double* wall, int32_t nbins);
