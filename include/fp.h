@@ -224,8 +224,9 @@ int fp_cell_volumes(fp_ctx* ctx, double* vol, hipStream_t s);
  * molecular mass, n the outward normal, t the tangent along decreasing theta, in bins of
  * the surface angle theta = |atan2(n_y, n_x)| (0 at the rear point, pi at the front
  * stagnation point; both halves of the circle share a bin).  FP64 atomic adds (their
- * order, and so the last bits of the sums, vary from run to run).  sums = NULL stops.
- * A HIP graph captured meanwhile keeps the pointer.  FP_EINVAL for other geometries or
+ * order, and so the last bits of the sums, vary from run to run).  sums = NULL stops;
+ * the caller keeps sums allocated until then (the context holds only the pointer).  A HIP
+ * graph captured meanwhile keeps the pointer.  FP_EINVAL for other geometries or
  * nbins outside [1, 65536]. */
 int fp_wall_sampling(fp_ctx* ctx, double* sums, int32_t nbins);
 /* Surface coefficients from such sums gathered over a time t_total [s]: out[nbins][4]

@@ -211,3 +211,59 @@ def test_rebin_is_refused_with_a_tree():
         with pytest.raises(RuntimeError):
             ctx.amr_init(L)
         assert ctx.ncell == w2["nx"] * w2["ny"]
+
+
+def test_full_size_tree_properties():
+    """The quadtree cylinder of the bench (base 400 x 300 cells of 2 mm, two levels, about
+    1.8e7 FP32 particles) through two adaptations: a valid tree (exactly one leaf above
+    every fine cell), a fine map consistent with the leaf nodes, leaf volumes that add up
+    to the gas volume, particles and sampling sums carried through unchanged in total."""
+    F = fp()
+    w = I.cylinder(cell=0.5e-3, nx=1600, ny=1200, precision="f32", seed=3)
+    ppc_base = w["n_inf"] * (2e-3) ** 2 * w["depth"] / w["fnum"]
+    prm = dict(tau_grad=0.10, tau_coarse=0.05, shock_factor=1.2, p_inf=p_inf(w),
+               n_max=4.0 * ppc_base, n_grad=200.0, eps=1e-300, age_min=2000)
+    sim = F.AMRSimulation(w, I.freestream_state(w), 2, prm, 0)
+    vol0 = torch.zeros(sim.ncell, dtype=torch.float64, device="cuda")
+    sim.ctx.cell_volumes(vol0)
+    total_vol = float(vol0.sum())
+    for s in range(120):
+        sim.step(s, sample=True)
+    for k in range(2):
+        sim.a.n = sim.n_total
+        keys = sim.a.key[:sim.n_total].clone()
+        live0 = int((keys < sim.ncell).sum())
+        samp0 = sim.samp[:sim.ncell].sum(0).cpu().numpy()
+        nleaf0 = sim.ncell
+        sim.adapt(60)
+        torch.cuda.synchronize()
+        live1 = int((sim.a.key[:sim.n_total] < sim.ncell).sum())
+        assert live1 == live0
+        samp1 = sim.samp[:sim.ncell].sum(0).cpu().numpy()
+        np.testing.assert_allclose(samp1[:13], samp0[:13], rtol=1e-9)
+        assert sim.ncell != nleaf0 or k == 1
+        for s in range(120 + 60 * k, 180 + 60 * k):
+            sim.step(s, sample=True)
+    st, age, lm, ln = sim.tree()
+    L, nbx, nby = 2, 400, 300
+    off = np.cumsum([0] + [(nbx << l) * (nby << l) for l in range(L + 1)])
+    nxf = nbx << L
+    fx, fy = np.meshgrid(np.arange(nxf), np.arange(nby << L))
+    leaves_above = np.zeros(fx.shape, dtype=np.int32)
+    for l in range(L + 1):
+        node = off[l] + (fy >> (L - l)) * (nbx << l) + (fx >> (L - l))
+        leaves_above += (st[node] == 1)
+    assert np.all(leaves_above == 1)
+    nleaf = sim.ncell
+    assert int((st == 1).sum()) == nleaf > nbx * nby
+    # the node of the leaf named by the map covers the fine cell
+    rng = np.random.default_rng(0)
+    f = rng.integers(0, nxf * (nby << L), 200_000)
+    node = ln[lm[f]]
+    lev = np.searchsorted(off, node, side="right") - 1
+    r = node - off[lev]
+    ix, iy = r % (nbx << lev), r // (nbx << lev)
+    assert np.all(ix == (f % nxf) >> (L - lev)) and np.all(iy == (f // nxf) >> (L - lev))
+    vol = torch.zeros(nleaf, dtype=torch.float64, device="cuda")
+    sim.ctx.cell_volumes(vol)
+    assert float(vol.sum()) == pytest.approx(total_vol, rel=1e-12)
