@@ -184,17 +184,19 @@ def philox(c0, c1, c2, c3, k0, k1):
     return x
 
 
-def dropout_keep(seed, ncell, npass, p):
-    """keep[cell][pass][layer-1][unit] of the three hidden layers (bool)."""
-    cell, pss, sub = np.meshgrid(np.arange(ncell), np.arange(npass), np.arange(3 * NH // 4),
-                                 indexing="ij")
+def dropout_keep(seed, ncell, npass, p, cells=None):
+    """keep[cell][pass][layer-1][unit] of the three hidden layers (bool); cells: the cell
+    indices of the rows (default 0 .. ncell-1)."""
+    ids = np.arange(ncell) if cells is None else np.asarray(cells)
+    cell, pss, sub = np.meshgrid(ids, np.arange(npass), np.arange(3 * NH // 4), indexing="ij")
     w = philox(cell, pss, np.full_like(cell, PURPOSE_DROPOUT), sub, seed & 0xFFFFFFFF, seed >> 32)
     words = np.stack(w, axis=-1).reshape(ncell, npass, 3, NH)
     return words >= np.uint64(int(np.floor(p * 2.0**32)))
 
 
-def dropout_sensitivity(p_flat, mom, eps_hat, npass, p, seed, emulate_bf16=True):
-    """sens[n][2] = (sigma_Stress, sigma_Heat) of moment records mom[n][32]."""
+def dropout_sensitivity(p_flat, mom, eps_hat, npass, p, seed, emulate_bf16=True, cells=None):
+    """sens[n][2] = (sigma_Stress, sigma_Heat) of moment records mom[n][32]; cells: the
+    cell index of every record (default 0 .. n-1), which keys its dropout masks."""
     P = unpack(p_flat)
     mom = np.asarray(mom, dtype=np.float64)
     n = mom.shape[0]
@@ -203,7 +205,7 @@ def dropout_sensitivity(p_flat, mom, eps_hat, npass, p, seed, emulate_bf16=True)
     if valid.any():
         f[valid] = features(mom[valid], eps_hat)
     xs = (f - P["x_mean"]) / P["x_std"]
-    keep = dropout_keep(seed, n, npass, p)
+    keep = dropout_keep(seed, n, npass, p, cells)
     scale = 1.0 / (1.0 - p)
     q = (lambda a: bf16(a)) if emulate_bf16 else (lambda a: a)
     ys = np.zeros((npass, n, 9))

@@ -84,9 +84,9 @@ static void mom_launch(fp_ctx* c, const fp_particles* p, const int32_t* off, dou
 template <typename T>
 static void mom_dispatch(fp_ctx* c, const fp_particles* p, const int32_t* off, double* mom,
                          hipStream_t s) {
-    // at least about four particles per lane (the smallest width with 4 G >= mean count):
-    // on cells of 24, 52 and 120 particles 8, 16 and 32 lanes beat both neighbours
-    switch (lanes_per_cell(c, p->n, 0, 5)) {
+    // about five particles per lane (the smallest width with 4.8 G >= mean count): on
+    // cells of 24, 52 and 150 particles 8, 16 and 32 lanes beat their neighbours
+    switch (lanes_per_cell(c, p->n, 0, 6)) {
         case 4: mom_launch<T, 4>(c, p, off, mom, s); break;
         case 8: mom_launch<T, 8>(c, p, off, mom, s); break;
         case 16: mom_launch<T, 16>(c, p, off, mom, s); break;

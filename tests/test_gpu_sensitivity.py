@@ -65,3 +65,32 @@ def test_sensitivity_degenerate_cases_are_exactly_zero():
         run(F, ctx, net, mom, 0, 0.2, 5)
     with pytest.raises(RuntimeError):
         run(F, ctx, net, mom, 4, 1.0, 5)
+
+
+def test_sensitivity_at_the_cylinder_mesh_size_sampled():
+    """1.2e5 cells (the 400 x 300 cylinder mesh), 50 passes at p = 0.2 as in the paper's
+    probe: 400 sampled cells against the oracle evaluated for those cells alone."""
+    F = fp()
+    nc = 400 * 300
+    rng = np.random.default_rng(13)
+    mom = np.zeros((nc, 32))             # random central-moment records (valid features)
+    mom[:, 0] = rng.uniform(20, 400, nc)
+    mom[:, 1:4] = rng.standard_normal((nc, 3))
+    mom[:, 4] = rng.uniform(0.5, 2.0, nc)
+    mom[:, 5:32] = rng.standard_normal((nc, 27)) * 0.1
+    for q in (5, 8, 10):
+        mom[:, q] += mom[:, 4]
+    for q in (21, 24, 26):
+        mom[:, q] += 5 * mom[:, 4] ** 2
+    w = I.couette(ncell=nc, eps_hat=0.01)
+    ctx = F.Context(w, 1)
+    net = F.Network(ctx, 0)
+    pflat = M.pack(random_params(9)).astype(np.float32)
+    net.load(dev(pflat, torch.float32))
+    seed = (11 << 32) | 5
+    g = run(F, ctx, net, mom, 50, 0.2, seed)
+    pick = np.sort(np.random.default_rng(2).choice(nc, 400, replace=False))
+    o = M.dropout_sensitivity(pflat.astype(np.float64), mom[pick], 0.01, 50, 0.2, seed, cells=pick)
+    assert np.all(np.isfinite(g)) and np.all(g > 0)
+    for k in range(2):
+        assert rel_l2(g[pick, k], o[:, k]) < 2e-2, k
