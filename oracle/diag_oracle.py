@@ -91,3 +91,45 @@ def surface_coefficients(wall, t_total, w):
     out[:, 2] = scale * wall[:, 2] / dyn
     out[:, 3] = scale * wall[:, 3] / (dyn * U)
     return out
+
+
+# ---------------------------------------------------------------------------------------
+# Normalised high-order fields (Sec. "Conservation, stability, entropy proxy, and noise
+# sensitivity" and the high-order diagnostics of the cavity): from the peculiar velocity
+# c = v - U of a cell, R_ij = <c_i c_j |c|^2>, Delta_4 = <|c|^4> - 15 theta^2 and
+# DM6 = <|c|^6>, theta = <|c|^2> / 3, each divided by the local Maxwellian scale
+# (theta^2, theta^2, theta^3).  Reading: the averaged fields are particle-weighted time
+# averages of each sampled step's cell moments (about that step's cell mean):
+#   hsamp = [sum N, sum N theta, sum N R_ij (6), sum N <|c|^4>, sum N <|c|^6>, 0...]
+#   R_ij,norm = Rbar_ij / thetabar^2, Delta_4,norm = <|c|^4>bar / thetabar^2 - 15,
+#   DM6_norm = <|c|^6>bar / thetabar^3   (Maxwellian: 5 delta_ij, 0, 105).
+HSAMP = 16
+
+
+def sample_high(mom, hsamp=None):
+    """Adds the high-order sums of moment records mom[ncell][32] to hsamp[ncell][16]."""
+    mom = np.asarray(mom, dtype=np.float64)
+    if hsamp is None:
+        hsamp = np.zeros((mom.shape[0], HSAMP))
+    N = mom[:, 0]
+    has = N > 0
+    R = mom[:, 21:27]
+    hsamp[has, 0] += N[has]
+    hsamp[has, 1] += N[has] * mom[has, 4]
+    hsamp[has, 2:8] += N[has, None] * R[has]
+    hsamp[has, 8] += N[has] * (R[has, 0] + R[has, 3] + R[has, 5])
+    hsamp[has, 9] += N[has] * mom[has, 30]
+    return hsamp
+
+
+def high_order(hsamp):
+    """[ncell][8]: R_ij,norm (11 12 13 22 23 33), Delta_4,norm, DM6_norm; NaN where a
+    cell has no particles or zero temperature."""
+    h = np.asarray(hsamp, dtype=np.float64)
+    out = np.full((h.shape[0], 8), np.nan)
+    ok = (h[:, 0] > 0) & (h[:, 1] > 0)
+    th = h[ok, 1] / h[ok, 0]
+    out[ok, 0:6] = h[ok, 2:8] / h[ok, 0][:, None] / (th * th)[:, None]
+    out[ok, 6] = h[ok, 8] / h[ok, 0] / (th * th) - 15.0
+    out[ok, 7] = h[ok, 9] / h[ok, 0] / (th * th * th)
+    return out

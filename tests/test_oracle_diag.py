@@ -88,3 +88,45 @@ def test_singular_covariance_has_no_entropy_deficit():
     out = D.diagnostics(sums_of(v)[None], np.array([1.0]), 1.0, 1.0, 1.0, 0.0)[0]
     assert np.isfinite(out[5]) and out[5] > 0
     assert np.isnan(out[17]) and np.isnan(out[18]) and np.isfinite(out[16])
+
+
+def test_high_order_fields_maxwellian_and_brute_force():
+    """Normalised high-order fields: a Maxwellian cell gives R_ij,norm = 5 delta_ij,
+    Delta_4,norm = 0, DM6_norm = 105 (Gaussian moments <|c|^4> = 15 theta^2,
+    <|c|^6> = 105 theta^3) within sampling error; and the sums over steps equal brute-force
+    particle averages written out directly."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(3)
+    n, steps = 400_000, 3
+    h = None
+    for s in range(steps):
+        v = rng.standard_normal((n, 3)) * 2.0 + np.array([1.0, -2.0, 0.5])
+        mom = O.moments(np.array([0, n], dtype=np.int32), v[:, 0], v[:, 1], v[:, 2])
+        h = D.sample_high(mom, h)
+    f = D.high_order(h)[0]
+    np.testing.assert_allclose(f[0:6], [5, 0, 0, 5, 0, 5], atol=0.05)
+    assert abs(f[6]) < 0.1 and abs(f[7] - 105) < 2.0
+    # brute force: two cells over two steps, central moments about each step's cell mean
+    hs = np.zeros((2, D.HSAMP))
+    acc = np.zeros((2, 5))
+    for s in range(2):
+        counts = [7, 13]
+        v = rng.standard_normal((20, 3)) * np.array([1.0, 2.0, 0.5]) + rng.standard_normal(3)
+        off = np.array([0, 7, 20], dtype=np.int32)
+        hs = D.sample_high(O.moments(off, v[:, 0], v[:, 1], v[:, 2]), hs)
+        for cidx in range(2):
+            c = v[off[cidx]:off[cidx + 1]]
+            c = c - c.mean(0)
+            c2 = (c * c).sum(1)
+            k = counts[cidx]
+            acc[cidx] += [k, k * c2.mean() / 3, k * (c[:, 0] * c[:, 1] * c2).mean(),
+                          k * (c2 * c2).mean(), k * (c2 ** 3).mean()]
+    np.testing.assert_allclose(hs[:, 0], acc[:, 0], rtol=0)
+    np.testing.assert_allclose(hs[:, 1], acc[:, 1], rtol=1e-13)
+    np.testing.assert_allclose(hs[:, 3], acc[:, 2], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(hs[:, 8], acc[:, 3], rtol=1e-12)
+    np.testing.assert_allclose(hs[:, 9], acc[:, 4], rtol=1e-12)
+    f2 = D.high_order(hs)
+    th = acc[:, 1] / acc[:, 0]
+    np.testing.assert_allclose(f2[:, 7], acc[:, 4] / acc[:, 0] / th ** 3, rtol=1e-12)
+    assert np.all(np.isnan(D.high_order(np.zeros((1, D.HSAMP)))))
