@@ -216,6 +216,18 @@ int64_t fp_inject_slots(const fp_ctx* ctx);
  * area count as solid, volume 0); box geometries dx dy (1 m depth). */
 int fp_cell_volumes(fp_ctx* ctx, double* vol, hipStream_t s);
 
+/* Normalised high-order fields of the averaged particle fields (the cavity's high-order
+ * diagnostics: R_ij = <c_i c_j |c|^2>, Delta_4 = <|c|^4> - 15 theta^2, DM6 = <|c|^6>, over
+ * the local Maxwellian scales).  fp_sample_high adds, for every cell with particles,
+ * [N, N theta, N R_ij (11 12 13 22 23 33), N <|c|^4>, N <|c|^6>] of one step's moment
+ * records (mom, moments through fifth order) to hsamp[ncell][16] (device, caller-owned,
+ * entries 10..15 untouched).  fp_high_order writes out[ncell][8] = (R_ij / theta^2 (6),
+ * <|c|^4> / theta^2 - 15, <|c|^6> / theta^3) of the particle-weighted averages
+ * (theta = sum N theta / sum N, ...): 5 delta_ij, 0 and 105 for a Maxwellian; NaN for
+ * cells without particles or temperature. */
+int fp_sample_high(fp_ctx* ctx, const double* mom, double* hsamp, hipStream_t s);
+int fp_high_order(fp_ctx* ctx, const double* hsamp, double* out, hipStream_t s);
+
 /* Surface sampling of the cylinder (for the C_p, C_f, C_h distributions of Sec.
  * "Extension to External Aerodynamics"): while sums is set, every diffuse re-emission at
  * the body during fp_step (MOVE) adds its exchange to sums[nbins][4] (device doubles,

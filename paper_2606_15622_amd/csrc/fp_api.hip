@@ -353,6 +353,19 @@ extern "C" int fp_surface_coefficients(fp_ctx* c, const double* sums, int32_t nb
     return launch_surface(c, sums, nbins, t_total, out, s);
 }
 
+extern "C" int fp_sample_high(fp_ctx* c, const double* mom, double* hsamp, hipStream_t s) {
+    if (!c || !mom || !hsamp || (const double*)hsamp == mom)
+        return set_err(c, FP_EINVAL, "fp_sample_high: bad argument");
+    if (c->cfg.moment_order == 3)
+        return set_err(c, FP_EINVAL, "fp_sample_high: the records hold moments through third order");
+    return launch_sample_high(c, mom, hsamp, s);
+}
+
+extern "C" int fp_high_order(fp_ctx* c, const double* hsamp, double* out, hipStream_t s) {
+    if (!c || !hsamp || !out) return set_err(c, FP_EINVAL, "fp_high_order: bad argument");
+    return launch_high_order(c, hsamp, out, s);
+}
+
 extern "C" int fp_sample(fp_ctx* c, const double* mom, double* samp, hipStream_t s) {
     if (!c || !mom || !samp) return set_err(c, FP_EINVAL, "fp_sample: bad argument");
     return launch_sample(c, mom, samp, s);

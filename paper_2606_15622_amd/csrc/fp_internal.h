@@ -211,6 +211,8 @@ int launch_diagnostics(fp_ctx* c, const double* samp, double theta_inf, double n
                        double dg_inf, double* diag, hipStream_t s);
 int launch_surface(fp_ctx* c, const double* sums, int32_t nbins, double t_total, double* out,
                    hipStream_t s);
+int launch_sample_high(fp_ctx* c, const double* mom, double* hsamp, hipStream_t s);
+int launch_high_order(fp_ctx* c, const double* hsamp, double* out, hipStream_t s);
 int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_particles* dst,
                  int32_t* offsets, int32_t* perm, double* mom, double* samp, hipStream_t s);
 int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,

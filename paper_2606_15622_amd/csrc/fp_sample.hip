@@ -125,6 +125,57 @@ int launch_diagnostics(fp_ctx* c, const double* samp, double theta_inf, double n
     return check_launch(c, "fp_diagnostics");
 }
 
+// high-order sums of every cell, one lane per cell: hsamp += [N, N theta, N R_ij (6),
+// N <|c|^4> = N tr R, N <|c|^6>] of this step's moment record (cells with particles)
+__global__ void sample_high_kernel(int32_t ncell, const double* __restrict__ mom,
+                                   double* __restrict__ hsamp) {
+    const int32_t cell = blockIdx.x * 256 + threadIdx.x;
+    if (cell >= ncell) return;
+    const double* m = mom + (int64_t)cell * MOM;
+    const double N = m[M_N];
+    if (!(N > 0.0)) return;
+    double* h = hsamp + (int64_t)cell * SAMP;
+    h[0] += N;
+    h[1] += N * m[M_TH];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) h[2 + i] += N * m[M_R + i];
+    h[8] += N * ((m[M_R + 0] + m[M_R + 3]) + m[M_R + 5]);
+    h[9] += N * m[M_H];
+}
+
+// normalised high-order fields of the averaged cells: out[cell][8] = R_ij / theta^2 (6),
+// <|c|^4> / theta^2 - 15, <|c|^6> / theta^3 with the particle-weighted averages of hsamp
+__global__ void high_order_kernel(int32_t ncell, const double* __restrict__ hsamp,
+                                  double* __restrict__ out) {
+    const int32_t cell = blockIdx.x * 256 + threadIdx.x;
+    if (cell >= ncell) return;
+    const double* h = hsamp + (int64_t)cell * SAMP;
+    double* o = out + (int64_t)cell * 8;
+    if (!(h[0] > 0.0 && h[1] > 0.0)) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = __longlong_as_double(0x7ff8000000000000LL);
+        return;
+    }
+    const double th = h[1] / h[0];
+    const double th2 = th * th;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) o[i] = h[2 + i] / h[0] / th2;
+    o[6] = h[8] / h[0] / th2 - 15.0;
+    o[7] = h[9] / h[0] / (th2 * th);
+}
+
+int launch_sample_high(fp_ctx* c, const double* mom, double* hsamp, hipStream_t s) {
+    hipLaunchKernelGGL(sample_high_kernel, dim3((c->ncell + 255) / 256), dim3(256), 0, s, c->ncell, mom,
+                       hsamp);
+    return check_launch(c, "fp_sample_high");
+}
+
+int launch_high_order(fp_ctx* c, const double* hsamp, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(high_order_kernel, dim3((c->ncell + 255) / 256), dim3(256), 0, s, c->ncell, hsamp,
+                       out);
+    return check_launch(c, "fp_high_order");
+}
+
 // surface coefficients of the cylinder from the exchange sums of the re-emissions: one
 // thread per bin; each bin holds both halves of the circle (area 2 R (pi / nbins) depth)
 __global__ void surface_kernel(int32_t nbins, const double* __restrict__ sums, double scale,

@@ -93,6 +93,8 @@ def load():
         L.fp_closure_nn.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
         L.fp_nn_outputs.argtypes = [vp, vp, vp, vp]
         L.fp_nn_sensitivity.argtypes = [vp, vp, vp, i32, C.c_double, u64, vp, vp]
+        L.fp_sample_high.argtypes = [vp, vp, vp, vp]
+        L.fp_high_order.argtypes = [vp, vp, vp, vp]
         L.fp_wall_sampling.argtypes = [vp, vp, i32]
         L.fp_surface_coefficients.argtypes = [vp, vp, i32, C.c_double, vp, vp]
         L.fp_amr_init.argtypes = [vp, i32]
@@ -117,7 +119,7 @@ def load():
                   "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
                   "fp_inject", "fp_cell_volumes", "fp_step_dev", "fp_counter_add", "fp_diagnostics",
                   "fp_amr_init", "fp_amr_adapt", "fp_amr_tree", "fp_wall_sampling",
-                  "fp_surface_coefficients"):
+                  "fp_surface_coefficients", "fp_sample_high", "fp_high_order"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -306,6 +308,15 @@ class Context:
 
     def cell_volumes(self, vol, stream=None):
         self._check(self.lib.fp_cell_volumes(self.h, _ptr(vol), _stream(stream)), "fp_cell_volumes")
+
+    # ---- high-order fields -------------------------------------------------------------
+    def sample_high(self, mom, hsamp, stream=None):
+        self._check(self.lib.fp_sample_high(self.h, _ptr(mom), _ptr(hsamp), _stream(stream)),
+                    "fp_sample_high")
+
+    def high_order(self, hsamp, out, stream=None):
+        self._check(self.lib.fp_high_order(self.h, _ptr(hsamp), _ptr(out), _stream(stream)),
+                    "fp_high_order")
 
     # ---- surface sampling of the cylinder ---------------------------------------------
     def wall_sampling(self, sums):

@@ -82,3 +82,32 @@ def test_cylinder_cut_cell_densities():
     g, o = run(F, sim.ctx, samp, dens, I.MASS_AR / I.KB, (th_inf, w["n_inf"], 0.0))
     free = np.isfinite(o[:, 16]) & (np.abs(o[:, 2] - w["u_inf"][0]) < 0.05 * w["u_inf"][0])
     assert free.sum() > 100
+
+
+def test_high_order_fields_match_oracle():
+    """fp_sample_high over two steps' moment records (mixture cells, some empty) and
+    fp_high_order against the oracle: the same products, sums and quotients in the same
+    order, so the same bits; NaN where the oracle has NaN."""
+    F = fp()
+    rng = np.random.default_rng(5)
+    ncell = 1000 + 37
+    w = I.couette(ncell=ncell, eps_hat=0.01)
+    ctx = F.Context(w, 1)
+    hs = torch.zeros((ncell, 16), dtype=torch.float64, device="cuda")
+    ho = None
+    for step in range(2):
+        counts = rng.integers(0, 60, ncell)
+        counts[::17] = 0
+        vx, vy, vz, off = I.mixture_cells(counts, seed=20 + step)
+        mom = O.moments(off, vx, vy, vz)
+        ctx.sample_high(torch.from_numpy(mom).cuda(), hs)
+        ho = D.sample_high(mom, ho)
+    out = torch.full((ncell, 8), -7.0, dtype=torch.float64, device="cuda")
+    ctx.high_order(hs, out)
+    torch.cuda.synchronize()
+    g = hs.cpu().numpy()
+    np.testing.assert_array_equal(g[:, :10], ho[:, :10])
+    assert np.all(g[:, 10:] == 0)
+    go, oo = out.cpu().numpy(), D.high_order(ho)
+    assert np.array_equal(np.isnan(go), np.isnan(oo)) and np.isnan(oo).any()
+    np.testing.assert_array_equal(np.nan_to_num(go), np.nan_to_num(oo))
