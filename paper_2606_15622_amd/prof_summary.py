@@ -131,6 +131,40 @@ def counters(a):
     return "\n".join(out)
 
 
+def instruction_mix(a):
+    """Per kernel and grid: waves, wave instructions per wave (VALU, LDS, SALU, vector
+    memory reads and writes) from one rocprofv3 --pmc run of SQ counters, and the VALU
+    time they imply at four cycles per wave instruction on 1024 SIMDs at 2.4 GHz."""
+    rows = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(a.csv)):
+        name = re.sub(r"\(.*$", "", re.sub(r"^void ", "", r["Kernel_Name"])).replace("fpg::", "")
+        if a.match and not re.search(a.match, name):
+            continue
+        rows[(name, int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    avg = lambda v: sum(v) / len(v) if v else 0.0
+    out = []
+    if a.title:
+        out.append(f"# {a.title}")
+    if a.command:
+        out.append(f"# command: {a.command}")
+    out.append("# SQ_* counters summed over the chip per dispatch, averaged over dispatches; "
+               "instructions are wave instructions")
+    out.append(f"{'kernel':<40}{'grid':>9}{'waves':>8}{'valu/w':>8}{'lds/w':>7}{'salu/w':>7}"
+               f"{'vmrd/w':>7}{'vmwr/w':>7}{'valu_us':>9}")
+    for key in sorted(rows):
+        c = rows[key]
+        w = avg(c.get("SQ_WAVES", []))
+        if w <= 0:
+            continue
+        valu = avg(c.get("SQ_INSTS_VALU", []))
+        us = valu * 4.0 / (1024 * 2.4e9) * 1e6
+        out.append(f"{key[0][:40]:<40}{key[1]:>9}{w:>8.0f}{valu / w:>8.0f}"
+                   f"{avg(c.get('SQ_INSTS_LDS', [])) / w:>7.0f}{avg(c.get('SQ_INSTS_SALU', [])) / w:>7.0f}"
+                   f"{avg(c.get('SQ_INSTS_VMEM_RD', [])) / w:>7.1f}{avg(c.get('SQ_INSTS_VMEM_WR', [])) / w:>7.1f}"
+                   f"{us:>9.1f}")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -139,6 +173,11 @@ def main():
     t.add_argument("--title", default="")
     t.add_argument("--command", default="")
     sub.add_parser("copy")
+    m = sub.add_parser("mix")
+    m.add_argument("csv")
+    m.add_argument("--match", default="")
+    m.add_argument("--title", default="")
+    m.add_argument("--command", default="")
     c = sub.add_parser("counters")
     for k in ("--fetch", "--write", "--copy-fetch", "--copy-write"):
         c.add_argument(k, required=True)
@@ -152,6 +191,8 @@ def main():
         print(summarize(a.trace, a.title, a.command))
     elif a.cmd == "copy":
         copy_reference()
+    elif a.cmd == "mix":
+        print(instruction_mix(a))
     else:
         print(counters(a))
 
