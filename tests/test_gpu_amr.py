@@ -206,6 +206,15 @@ def test_rebin_is_refused_with_a_tree():
         sim.ctx.rebin(sim.a, sim.offs[0], sim.b, sim.offs[1])
     with pytest.raises(RuntimeError):
         sim.ctx.amr_init(1)          # already has a tree
+    # optional arguments: no sampling sums, no particles; the tree still adapts
+    acc = torch.zeros((sim.ctx.cfg.nx * sim.ctx.cfg.ny, 16), dtype=torch.float64, device="cuda")
+    acc[:sim.ncell, 0] = 1e6
+    acc[:sim.ncell, 13] = 1.0
+    n0 = sim.ncell
+    sim.ctx.amr_adapt(dict(tau_grad=0.1, tau_coarse=0.05, shock_factor=1.2, p_inf=1.0, n_max=10.0,
+                           n_grad=1e30, eps=1e-300, age_min=10), acc, None, None, 1)
+    assert sim.ctx.ncell > n0                   # every cell with gas above N_max split
+    assert float(acc[:sim.ctx.ncell].abs().sum()) == 0.0
     for w2, L in ((small("f32"), 5), (small("f32"), 3), (I.cavity(ncell=16, ppc=4), 1)):
         ctx = F.Context(w2, 1000)     # level above 4; 60 cells not a multiple of 8; no cylinder
         with pytest.raises(RuntimeError):

@@ -220,3 +220,8 @@ def test_surface_sampling_matches_oracle():
     assert c[-1, 1] > 1.0                  # stagnation region: C_p of order 2
     with pytest.raises(RuntimeError):
         sim.ctx.surface_coefficients(sums, 0.0, out)
+    # a buffer with no bins is refused (a NULL buffer stops the sampling instead)
+    assert sim.ctx.lib.fp_wall_sampling(sim.ctx.h, sums.data_ptr(), 0) == F.FP_EINVAL
+    box = F.Context(I.cavity(ncell=8, ppc=4), 10)
+    with pytest.raises(RuntimeError):
+        box.wall_sampling(sums)
