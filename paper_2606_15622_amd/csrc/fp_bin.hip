@@ -966,9 +966,22 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
             }
         }
     };
+    // velocities of the first round stay in registers: a cell that one round covers and
+    // that has no far arrival takes its moments from them instead of reading its slots back
+    T kvx[GM_U], kvy[GM_U], kvz[GM_U];
+#pragma unroll
+    for (int u = 0; u < GM_U; ++u) kvx[u] = kvy[u] = kvz[u] = (T)0;
     for (int32_t q0 = 0; q0 < nk; q0 += G * GM_U) {
         T tx[GM_U], ty[GM_U], tz[GM_U];
         round(q0, tx, ty, tz);
+        if (q0 == 0) {
+#pragma unroll
+            for (int u = 0; u < GM_U; ++u) {
+                kvx[u] = tx[u];
+                kvy[u] = ty[u];
+                kvz[u] = tz[u];
+            }
+        }
     }
     // far arrivals of this cell, placed by counting: after every bucket whose old cell
     // starts before it and every arrival with a smaller source index
@@ -987,11 +1000,24 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
     // barrier makes the group's writes visible to all of its lanes
     __syncthreads();
     const int32_t ncnt = in ? (int32_t)min((int64_t)nk + (f1 - f0), lim - base) : 0;
+    // register path (group-uniform): slot q of the cell is position q, held by lane q % G
+    // as round value q / G -- the same values in the same per-lane order as the slots
+    const bool regs = nf == 0 && ncnt == nk && nk <= G * GM_U;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int32_t q = lg; q < ncnt; q += G) {
-        s0 += (double)r.dvx[base + q];
-        s1 += (double)r.dvy[base + q];
-        s2 += (double)r.dvz[base + q];
+    if (regs) {
+#pragma unroll
+        for (int u = 0; u < GM_U; ++u)
+            if (u * G + lg < ncnt) {
+                s0 += (double)kvx[u];
+                s1 += (double)kvy[u];
+                s2 += (double)kvz[u];
+            }
+    } else {
+        for (int32_t q = lg; q < ncnt; q += G) {
+            s0 += (double)r.dvx[base + q];
+            s1 += (double)r.dvy[base + q];
+            s2 += (double)r.dvz[base + q];
+        }
     }
     s0 = group_sum<G>(s0);
     s1 = group_sum<G>(s1);
@@ -1001,9 +1027,16 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
     double acc[NVX];
 #pragma unroll
     for (int i = 0; i < NVX; ++i) acc[i] = 0.0;
-    for (int32_t q = lg; q < ncnt; q += G)
-        mom_accum<NVX>((double)r.dvx[base + q] - U0, (double)r.dvy[base + q] - U1,
-                       (double)r.dvz[base + q] - U2, acc);
+    if (regs) {
+#pragma unroll
+        for (int u = 0; u < GM_U; ++u)
+            if (u * G + lg < ncnt)
+                mom_accum<NVX>((double)kvx[u] - U0, (double)kvy[u] - U1, (double)kvz[u] - U2, acc);
+    } else {
+        for (int32_t q = lg; q < ncnt; q += G)
+            mom_accum<NVX>((double)r.dvx[base + q] - U0, (double)r.dvy[base + q] - U1,
+                           (double)r.dvz[base + q] - U2, acc);
+    }
     mom_finish<BIN_BLOCK, G, NVX>(sm, acc, grp, lg, in, ncnt, U0, U1, U2,
                              mom + (int64_t)(in ? k : 0) * MOM);
     if (samp) {
