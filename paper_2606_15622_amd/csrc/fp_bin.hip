@@ -1039,10 +1039,13 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
     }
     mom_finish<BIN_BLOCK, G, NVX>(sm, acc, grp, lg, in, ncnt, U0, U1, U2,
                              mom + (int64_t)(in ? k : 0) * MOM);
-    if (samp) {
-        // time-average sums from the record, once all of the group's lanes wrote it
-        __syncthreads();
-        if (in && lg == 0) sample_add(mom + (int64_t)k * MOM, samp + (int64_t)k * SAMP);
+    if (samp && in && lg == 0) {
+        // time-average sums from the record's entries, rebuilt from the final sums in LDS
+        // (the values mom_finish stored) instead of reading the record back
+        double m[M_T + 10];
+#pragma unroll
+        for (int e = 0; e < M_T + 10; ++e) m[e] = mom_entry<BIN_BLOCK, G, NVX>(sm, grp, ncnt, U0, U1, U2, e);
+        sample_add(m, samp + (int64_t)k * SAMP);
     }
 }
 

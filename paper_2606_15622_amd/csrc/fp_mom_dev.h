@@ -45,6 +45,19 @@ struct MomShared {
     double fin[BLOCK / G][NV];
 };
 
+// entry e of the moment record from the group's final sums in LDS
+template <int BLOCK, int G, int NVX = NV>
+__device__ __forceinline__ double mom_entry(const MomShared<BLOCK, G>& sm, int grp, int32_t n,
+                                            double U0, double U1, double U2, int e) {
+    const double inv_n = n > 0 ? 1.0 / (double)n : 0.0;
+    if (e == M_N) return (double)n;
+    if (e < M_TH) return e == M_U ? U0 : (e == M_U + 1 ? U1 : U2);
+    if (e == M_TH)
+        return (sm.fin[grp][0] * inv_n + sm.fin[grp][3] * inv_n + sm.fin[grp][5] * inv_n) / 3.0;
+    if (e < M_P + NVX) return sm.fin[grp][e - M_P] * inv_n;
+    return 0.0;
+}
+
 // Cross-lane sums of acc over the group (lane v adds the partials of value v in lane
 // order, MR values per round), then the record of the cell, one entry per lane:
 // N, U, theta, P, T, R, W, H (moments / N; R, W, H zero when only NV_LOW values were
@@ -66,19 +79,8 @@ __device__ __forceinline__ void mom_finish(MomShared<BLOCK, G>& sm, const double
         }
         __syncthreads();
     }
-    if (in) {
-        const double inv_n = n > 0 ? 1.0 / (double)n : 0.0;
-        for (int e = lg; e < MOM; e += G) {
-            double val;
-            if (e == M_N) val = (double)n;
-            else if (e < M_TH) val = e == M_U ? U0 : (e == M_U + 1 ? U1 : U2);
-            else if (e == M_TH)
-                val = (sm.fin[grp][0] * inv_n + sm.fin[grp][3] * inv_n + sm.fin[grp][5] * inv_n) / 3.0;
-            else if (e < M_P + NVX) val = sm.fin[grp][e - M_P] * inv_n;
-            else val = 0.0;
-            rec[e] = val;
-        }
-    }
+    if (in)
+        for (int e = lg; e < MOM; e += G) rec[e] = mom_entry<BLOCK, G, NVX>(sm, grp, n, U0, U1, U2, e);
 }
 
 }  // namespace fpg
