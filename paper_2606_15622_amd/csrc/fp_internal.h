@@ -38,7 +38,7 @@ struct fp_ctx {
     int32_t* farn = nullptr;     // [1] re-sort: length of the list of particles that moved far
     int32_t* pend = nullptr;     // [ncell] step: flights left for flight_rest_kernel per cell
     uint32_t* stepc = nullptr;   // [1] step: the step number collide_kernel read, for flight_rest_kernel
-    unsigned long long* errcount = nullptr;  // invalid keys
+    unsigned long long* errcount = nullptr;  // [2] invalid keys, injection overflows
     // open cylinder domain
     double* vol = nullptr;       // [ncell] gas volume of every cell
     double* nvol = nullptr;      // [ncell] real molecules per particle / gas volume
@@ -116,15 +116,33 @@ __device__ __forceinline__ void normals3d(uint4 r, double& z0, double& z1, doubl
     z2 = r1 * cos(TWO_PI * u3);
 }
 
-// single precision: hardware log2, square root (about 1 ulp; the correctly rounded
-// expansion costs a dozen instructions more) and sin/cos of revolutions (v_sin/v_cos take
-// x in units of 2 pi, so sin(2 pi u) is one instruction for u in (0, 1]); the argument of
-// the root is 0 or at least 2e-10, never denormal
-__device__ __forceinline__ void normals3f(uint4 r, float& z0, float& z1, float& z2) {
-    const float u0 = u01f(r.x), u1 = u01f(r.y), u2 = u01f(r.z), u3 = u01f(r.w);
+// -2 ln u for u = (k + 1/2) 2^-32 in single precision (the Box-Muller radius squared).
+// Below one half, u01f(k) carries u to 2^-24 relative and its hardware log2 is used
+// directly.  Above, u itself is not representable to the precision its logarithm needs: a u
+// within 2^-25 of 1 rounds to 1 and would give radius 0 where the exact one reaches 2e-4.
+// There t = 1 - u = (~k + 1/2) 2^-32, which FP32 holds to 2^-24 relative, gives
+// ln u = ln(1 - t) by the log1p form ln(w) x / (w - 1) with x = -t and w = fl(1 + x)
+// (w - 1 is exact for w in [1/2, 1]), and ln u = -t where w rounds to 1.  The result is 0
+// never and at least 2.3e-10, never denormal.
+__device__ __forceinline__ float m2lnu_f(uint32_t k) {
     constexpr float M2LN2 = -1.3862943611198906f;  // -2 ln 2
-    const float r0 = __builtin_amdgcn_sqrtf(M2LN2 * __builtin_amdgcn_logf(u0));
-    const float r1 = __builtin_amdgcn_sqrtf(M2LN2 * __builtin_amdgcn_logf(u2));
+    const bool hi = k >= 0x80000000u;
+    const float t = __builtin_fmaf((float)(~k), 0x1p-32f, 0x1p-33f);
+    const float w = hi ? 1.0f - t : u01f(k);
+    const float d = 1.0f - w;
+    const float l = M2LN2 * __builtin_amdgcn_logf(w);
+    const float f = hi ? t * __builtin_amdgcn_rcpf(d) : 1.0f;
+    return (hi && d == 0.0f) ? 2.0f * t : l * f;
+}
+
+// single precision: the radius from m2lnu_f, hardware log2 and square root (about 1 ulp;
+// the correctly rounded expansion costs a dozen instructions more) and sin/cos of
+// revolutions (v_sin/v_cos take x in units of 2 pi, so sin(2 pi u) is one instruction for
+// u in (0, 1])
+__device__ __forceinline__ void normals3f(uint4 r, float& z0, float& z1, float& z2) {
+    const float u1 = u01f(r.y), u3 = u01f(r.w);
+    const float r0 = __builtin_amdgcn_sqrtf(m2lnu_f(r.x));
+    const float r1 = __builtin_amdgcn_sqrtf(m2lnu_f(r.z));
     z0 = r0 * __builtin_amdgcn_cosf(u1);
     z1 = r0 * __builtin_amdgcn_sinf(u1);
     z2 = r1 * __builtin_amdgcn_cosf(u3);
@@ -204,6 +222,12 @@ inline int lanes_per_cell(const fp_ctx* c, int64_t n, int64_t min_threads = 0, i
 // resident waves on each of the 1024 SIMDs)
 constexpr int64_t FILL_4 = 1024 * 4 * 64, FILL_8 = 1024 * 8 * 64;
 
+// slots a call's per-particle grid covers: the host count, or with a device count
+// (p->n_dev) the capacity of the arrays
+inline int64_t slots_of(const fp_particles* p) {
+    return p->n_dev ? (p->capacity > 0 ? p->capacity : p->n) : p->n;
+}
+
 // ---- launchers implemented in the kernel files -------------------------------------------
 int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* offsets,
                int32_t* perm, hipStream_t s);
@@ -219,7 +243,7 @@ int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, dou
                    hipStream_t s);
 int launch_closure(fp_ctx* c, const double* mom, double* rec, int32_t* status, hipStream_t s);
 int launch_inject(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_next, uint32_t step,
-                  hipStream_t s);
+                  const uint32_t* step_dev, uint32_t* advance, hipStream_t s);
 int launch_step(fp_ctx* c, fp_particles* p, const int32_t* offsets, const double* mom,
                 const double* rec, uint64_t step, uint32_t flags, const uint32_t* step_dev,
                 hipStream_t s);

@@ -3,10 +3,18 @@ the FP64 MLP oracle (through the C ABI).
 
 The oracle evaluates the network in FP64 with the weights, inputs, hidden activations
 and back-propagated pre-activation gradients rounded to bfloat16 at the points where the
-GPU holds them in that format.  The remaining differences come from FP32 (GPU) versus
-FP64 accumulation of <= 128-term dot products (~1e-6 relative) and the rare bfloat16
-rounding flips they cause (one bfloat16 ulp = 2^-8 relative in one element); the
-tolerances below (relative L2 1e-2 on outputs and gradients) bound that with margin.
+GPU holds them in that format.  The remaining differences are FP32 (GPU) against FP64
+accumulation of <= 128-term dot products (~1e-6 relative), FP32 against FP64 SiLU, and
+the bfloat16 rounding flips they cause now and then: an activation whose pre-rounding
+values straddle a rounding boundary differs by one bfloat16 ulp (2^-8 relative) between
+the two sides.  The bounds are element by element:
+  * outputs: |y_gpu - y_oracle| <= 2^-9 |y_oracle| + 2^-10 of the output's rms over the
+    cells (a quarter of a bfloat16 ulp of that scale), and at least 99 % of the cells (no
+    flip on their path) within 1e-4 of |y_oracle| + rms; measured on an MI355X: largest
+    error 9.5e-5 of the rms, every cell within 1e-4;
+  * gradients: every entry within 2^-8 of the rms of its own tensor (W1, b1, ..., b4),
+    and at least 99 % of the entries within 2^-9 of it; measured: largest error 6.7e-4
+    (MSE loss) and 1.1e-3 (residual loss) of the rms, every entry within 2^-9.
 """
 import numpy as np
 import pytest
@@ -82,8 +90,15 @@ def test_inference_matches_bf16_oracle():
     xs = (M.features(mom, 0.01) - p32["x_mean"]) / p32["x_std"]
     yo, _ = M.forward(p32, xs, emulate_bf16=True)
     assert np.all(yg[:, 9:] == 0)
-    assert rel_l2(yg[:, :9], yo[:, :9]) < 1e-2
-    assert np.abs(yg[:, :9] - yo[:, :9]).max() < 0.05 * np.abs(yo[:, :9]).max()
+    err = np.abs(yg[:, :9] - yo[:, :9])
+    rms = np.sqrt((yo[:, :9] ** 2).mean(0))
+    lim = 2.0 ** -9 * np.abs(yo[:, :9]) + 2.0 ** -10 * rms
+    tight = 1e-4 * (np.abs(yo[:, :9]) + rms)
+    print(f"\ninference: max err / bound {float((err / lim).max()):.3e}, "
+          f"max err / rms {float((err / rms).max()):.3e}, "
+          f"cells within 1e-4: {float(np.all(err <= tight, 1).mean()):.4f}")
+    assert np.all(err <= lim)
+    assert np.all(err <= tight, 1).mean() >= 0.99
     stn = st.cpu().numpy()
     assert np.all(stn == F.CELL_NN)
     # the record is the de-standardised network output, de-normalised
@@ -197,10 +212,21 @@ def test_gradient_matches_bf16_oracle(loss_kind):
         dy = np.zeros((B, 16))
         dy[:, :9] = 2.0 * np.einsum("nik,ni->nk", A, r) / B * p32["y_std"][:9]
     go = M.grads_flat(M.backward(p32, cache, dy, emulate_bf16=True))
-    assert float(loss.cpu()) == pytest.approx(lo, rel=2e-2)
-    assert rel_l2(g[:M.N_TRAIN], go[:M.N_TRAIN]) < 1e-2
-    cos = g[:M.N_TRAIN] @ go[:M.N_TRAIN] / np.linalg.norm(g[:M.N_TRAIN]) / np.linalg.norm(go[:M.N_TRAIN])
-    assert cos > 0.9999
+    assert float(loss.cpu()) == pytest.approx(lo, rel=1e-3)
+    o = 0
+    worst, bulk = 0.0, 1.0
+    for name, shp in M.SHAPES[:8]:
+        n = int(np.prod(shp))
+        ge, gr = g[o:o + n], go[o:o + n]
+        rms = float(np.sqrt((gr ** 2).mean()))
+        e = np.abs(ge - gr) / rms
+        worst = max(worst, float(e.max()))
+        bulk = min(bulk, float((e <= 2.0 ** -9).mean()))
+        assert np.all(e <= 2.0 ** -8), (name, float(e.max()))
+        o += n
+    print(f"\ngradient ({loss_kind}): max |err| / tensor rms {worst:.3e}, "
+          f"smallest share within 2^-9: {bulk:.4f}")
+    assert bulk >= 0.99
     assert np.all(g[M.N_TRAIN:] == 0)
 
 

@@ -208,8 +208,19 @@ def test_closure_parity_and_status():
         cond = np.ones(nc)
         for c in np.nonzero(ok)[0]:
             cond[c] = np.linalg.cond(O.closure_system(mom[c], eps_hat)[0])
-        lim = np.maximum(1e-10, 1e-14 * cond)[:, None] * (1 + np.abs(orec * sn))
-        assert np.all(err[:, :9] <= lim[:, :9])
+        rel = (err[:, :9] / (1 + np.abs(orec * sn)[:, :9])).max(1)
+        well = ok & (cond < 1e4)
+        ill = ok & (cond >= 1e4)
+        assert well.sum() > 100
+        # the FP64 contract holds outright on well-conditioned systems
+        assert rel[well].max() <= 1e-10, float(rel[well].max())
+        # on the others the two LU factorisations (same pivots, different rounding order of
+        # the assembly) differ by at most a small multiple of cond * 2^-52
+        ratio = rel[ill] / (cond[ill] * 2.0 ** -52) if ill.any() else np.zeros(1)
+        print(f"\nclosure eps_hat={eps_hat}: well-conditioned {int(well.sum())} cells, max rel "
+              f"{float(rel[well].max()):.2e}; cond >= 1e4: {int(ill.sum())} cells (max cond "
+              f"{float(cond.max()):.2e}), max rel / (cond 2^-52) {float(ratio.max()):.3f}")
+        assert np.all(ratio <= 1.0)
         assert cond.max() < 1e9   # cells with >= n_min = 5 particles are well posed
         np.testing.assert_allclose(g[:, 9:14], orec[:, 9:14], rtol=1e-12)
         np.testing.assert_array_equal(g[:, 14], orec[:, 14])
@@ -346,8 +357,9 @@ def test_cavity_f32_short_run_and_determinism():
     np.testing.assert_array_equal(g["pid"], o["pid"])
     np.testing.assert_array_equal(g["key"], o["key"])
     sc = math.sqrt(I.KB / I.MASS_AR * 273.0)
-    for k in ("vx", "vy", "vz"):
-        assert np.abs(g[k] - o[k]).max() <= 1e-4 * sc, k
+    dv = max(float(np.abs(g[k] - o[k]).max()) for k in ("vx", "vy", "vz"))
+    print(f"\nFP32 cavity, 8 steps: max |dv| / sqrt(theta) = {dv / sc:.3e}")
+    assert dv <= 1e-5 * sc
     # macroscopic fields of the sampled sums within 1e-5 relative
     gs = outs[0][1]
     U_g = gs[:, 1:4] / gs[:, :1]
@@ -439,3 +451,94 @@ def test_step_dev_advance_matches_host_step_number():
         for k in ha:
             np.testing.assert_array_equal(da[k], ha[k], err_msg=f"flags {flags} {k}")
         step += 1
+
+
+def test_cavity_f32_lockstep_128_steps():
+    """FP32 cavity (32 x 32 cells, 100 particles per cell, lid 300 m/s) for 128 steps in
+    lockstep: every step the oracle takes the GPU's sorted particles, computes moments,
+    closure, velocity update (eqs. update_vel, update_N, exact conservation) and flight
+    with diffuse walls (eq. update_pos) in FP64, and the GPU's result of the same step is
+    compared with it; so each step is checked on its own, without the divergence of two
+    independent FP32/FP64 trajectories.  Sort order and offsets: bit-exact against the
+    oracle's counting sort of the GPU's previous keys.  Velocities: within 1e-5 sqrt(theta)
+    per component; positions within one FP32 ulp plus dt times that bound; keys equal wherever the positions are
+    equal, and every GPU key is the cell of its own position."""
+    F = fp()
+    w = I.cavity(kn=1.0, ncell=32, ppc=100, precision="f32", seed=17, lid=300.0)
+    s = I.maxwellian_state(w)
+    sim = F.Simulation(w, s)
+    nc = I.ncells(w)
+    sc = math.sqrt(I.KB / I.MASS_AR * 273.0)
+    prev_key = None
+    worst_v = worst_x = 0.0
+    key_diff = 0
+    for step in range(128):
+        sim.sort(mom=sim.mom)
+        a = sim.a.numpy()
+        off = cpu(sim.offsets)
+        if prev_key is not None:
+            operm, ooff = O.bin_particles(nc, prev_key["key"])
+            np.testing.assert_array_equal(off, ooff, err_msg=f"step {step}")
+            for k in ("x", "y", "vx", "vy", "vz", "pid", "key"):
+                np.testing.assert_array_equal(a[k], prev_key[k][operm], err_msg=f"step {step} {k}")
+        mom = O.moments(off, a["vx"], a["vy"], a["vz"])
+        rec, st = O.closure(w, mom)
+        ovx, ovy, ovz = O.update(w, off, a["vx"], a["vy"], a["vz"], a["pid"], mom, rec, step)
+        ox, oy, ovx, ovy, ovz, okey = O.move(w, a["x"], a["y"], ovx, ovy, ovz, a["pid"], step)
+        sim.ctx.closure_solve(sim.mom, sim.rec, sim.status)
+        sim.ctx.step(sim.a, sim.offsets, sim.mom, sim.rec, step, F.STEP_COLLIDE | F.STEP_MOVE)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(cpu(sim.status), st, err_msg=f"step {step}")
+        g = sim.a.numpy()
+        dv = max(float(np.abs(g[k] - ov).max()) for k, ov in (("vx", ovx), ("vy", ovy), ("vz", ovz)))
+        worst_v = max(worst_v, dv / sc)
+        assert dv <= 1e-5 * sc, (step, dv / sc)
+        for k, ov in (("x", ox), ("y", oy)):
+            # one FP32 ulp of the stored position plus the flight of the velocity bound
+            lim = np.spacing(np.abs(ov).astype(np.float32)).astype(np.float64) + 1e-5 * sc * w["dt"]
+            d = np.abs(g[k] - ov)
+            worst_x = max(worst_x, float((d / lim).max()))
+            assert np.all(d <= lim), (step, k)
+        same = (g["x"] == ox) & (g["y"] == oy)
+        np.testing.assert_array_equal(g["key"][same], okey[same], err_msg=f"step {step}")
+        key_diff += int((g["key"] != okey).sum())
+        np.testing.assert_array_equal(g["key"], O.keys(w, g["x"], g["y"]), err_msg=f"step {step}")
+        prev_key = g
+    print(f"\nlockstep 128 steps: max |dv| / sqrt(theta) {worst_v:.3e}, max |dx| / bound "
+          f"{worst_x:.3f}, keys differing where positions differ: {key_diff}")
+
+
+def test_cavity_448_full_size_one_step():
+    """The scaled cavity of the bandwidth runs (448 x 448 cells, 100 particles per cell,
+    2.0e7 FP32 particles) through Simulation.step, in the launch configuration of the
+    benchmark (its flight kernel takes the large-grid form above 65,536 cells): one
+    whole step from the seeded initial state against the oracle."""
+    F = fp()
+    w = I.cavity(kn=1.0, ncell=448, ppc=100, precision="f32", seed=1)
+    s = I.maxwellian_state(w)
+    sim = F.Simulation(w, s)
+    sim.step(0, sample=True)
+    torch.cuda.synchronize()
+    s2 = dict(s)
+    s2["key"] = O.keys(w, s["x"], s["y"])
+    o, omom, orec, ost, osamp = O.run(w, s2, 0, 1, n_skip=0)
+    g = sim.a.numpy()
+    np.testing.assert_array_equal(g["pid"], o["pid"])
+    np.testing.assert_array_equal(cpu(sim.status), ost)
+    gm = cpu(sim.mom)
+    th = omom[:, 4]
+    assert np.all(np.abs(gm[:, 5:11] - omom[:, 5:11]) <= 1e-10 * th[:, None])
+    sc = math.sqrt(I.KB / I.MASS_AR * 273.0)
+    dv = max(float(np.abs(g[k] - o[k]).max()) for k in ("vx", "vy", "vz"))
+    assert dv <= 1e-5 * sc
+    # positions within one FP32 ulp plus the flight of the velocity bound; a position one
+    # ulp apart may sit on the other side of a cell face, so keys are compared where the
+    # positions are equal, and every GPU key must be the cell of its own position
+    for k in ("x", "y"):
+        lim = np.spacing(np.abs(o[k]).astype(np.float32)).astype(np.float64) + 1e-5 * sc * w["dt"]
+        assert np.all(np.abs(g[k] - o[k]) <= lim), k
+    same = (g["x"] == o["x"]) & (g["y"] == o["y"])
+    np.testing.assert_array_equal(g["key"][same], o["key"][same])
+    np.testing.assert_array_equal(g["key"], O.keys(w, g["x"], g["y"]))
+    print(f"\n448^2 cavity one step: max |dv| / sqrt(theta) {dv / sc:.3e}, positions differing "
+          f"by one ulp {int((~same).sum())}, keys differing {int((g['key'] != o['key']).sum())}")

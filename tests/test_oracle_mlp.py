@@ -94,3 +94,45 @@ def test_pack_unpack_layout():
     for k in p:
         np.testing.assert_array_equal(p[k], q[k])
     assert M.N_TRAIN == 39312 and M.N_PARAMS == 39408
+
+
+def test_forward_matches_torch_fp64_layers():
+    """The oracle's plain forward (no BF16 emulation) against an independent FP64 forward
+    built from torch's dense layer and SiLU (Sec. "Neural Network Architecture": dense
+    layers, a non-linear activation between them, a linear output layer)."""
+    p = random_params(6, scale=1.5)
+    rng = np.random.default_rng(8)
+    xs = rng.standard_normal((257, 32)) * 2.0
+    y, (hs, zs) = M.forward(p, xs)
+    t = {k: torch.from_numpy(v) for k, v in p.items()}
+    h = torch.from_numpy(xs)
+    for layer in (1, 2, 3):
+        h = torch.nn.functional.silu(torch.nn.functional.linear(h, t[f"W{layer}"], t[f"b{layer}"]))
+        np.testing.assert_allclose(hs[layer], h.numpy(), rtol=1e-13, atol=1e-13)
+    yt = torch.nn.functional.linear(h, t["W4"], t["b4"]).numpy()
+    np.testing.assert_allclose(y, yt, rtol=1e-13, atol=1e-13)
+    # a dropped term, a transposed weight or a missing bias would be far outside this
+    assert np.abs(y).max() > 0.1
+
+
+def test_bf16_forward_rounds_where_the_gpu_stores_bf16():
+    """With emulation every layer input is a bfloat16 value and the layer is the FP64
+    product of those values: the same numbers as torch's FP64 layers applied to the
+    bfloat16-rounded weights and activations."""
+    p = random_params(9, scale=1.5)
+    rng = np.random.default_rng(10)
+    xs = rng.standard_normal((64, 32))
+    y, (hs, _) = M.forward(p, xs, emulate_bf16=True)
+
+    def r(a):
+        return torch.as_tensor(a).to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    t = {k: torch.from_numpy(v) for k, v in p.items()}
+    h = r(xs)
+    np.testing.assert_array_equal(hs[0], h.numpy())
+    for layer in (1, 2, 3):
+        z = torch.nn.functional.linear(h, r(t[f"W{layer}"]), t[f"b{layer}"])
+        h = r(torch.nn.functional.silu(z))
+        np.testing.assert_allclose(hs[layer], h.numpy(), rtol=0, atol=0)
+    yt = torch.nn.functional.linear(h, r(t["W4"]), t["b4"]).numpy()
+    np.testing.assert_allclose(y, yt, rtol=1e-13, atol=1e-13)
