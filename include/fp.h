@@ -112,12 +112,23 @@ typedef struct fp_config {
 
 /* Particle arrays in structure-of-arrays form.  x, y, vx, vy, vz are float
  * (FP_F32) or double (FP_F64); y may be NULL in 1-D.  pid is a unique particle id
- * (the Philox counter); key is the cell index (row-major, ky*nx + kx). */
+ * (the Philox counter); key is the cell index (row-major, ky*nx + kx).
+ *
+ * The number of particles is either the host value n, or, when n_dev is set, the value
+ * *n_dev on the device at the moment the kernels of a call run (so that a loop whose
+ * count changes on the device, as the open domain's deletion and injection make it,
+ * needs no host read and can be captured in a HIP graph).  Then capacity is the number
+ * of slots the arrays hold (kernels never touch a slot at or beyond it; at most the
+ * context's capacity) and n is only a hint of the count for launch shapes.  fp_bin and
+ * fp_rebin write the number of particles they keep to dst->n_dev (when set; it must not
+ * be src->n_dev), fp_inject_dev appends at *n_dev and advances it. */
 typedef struct fp_particles {
     void *x, *y, *vx, *vy, *vz;
     uint32_t* pid;
     int32_t* key;
-    int64_t n;               /* number of particles */
+    int64_t n;               /* number of particles (host), or the hint with n_dev */
+    int64_t* n_dev;          /* device count (one int64, caller-owned) or NULL */
+    int64_t capacity;        /* slots of the arrays when n_dev is set (ignored otherwise) */
 } fp_particles;
 
 typedef struct fp_ctx fp_ctx;
@@ -209,6 +220,17 @@ int fp_counter_add(fp_ctx* ctx, uint32_t* ctr, uint32_t inc, hipStream_t s);
  * candidates.  Returns FP_EINVAL for other geometries. */
 int fp_inject(fp_ctx* ctx, fp_particles* p, int64_t at, uint32_t* pid_next, uint64_t step,
               hipStream_t s);
+/* fp_inject for a particle count and a step number kept on the device (a loop captured
+ * in a HIP graph): the slots start at *p->n_dev (p->n_dev required), the step number is
+ * *step_dev (one uint32) when the kernels run, and afterwards *p->n_dev has advanced by
+ * fp_inject_slots(ctx); with FP_STEP_ADVANCE in flags *step_dev also advances by 1 (in the
+ * call's last kernel, after every kernel has read it).  If the slots would reach beyond
+ * p->capacity nothing is written, *p->n_dev keeps its value and the overflow is counted
+ * on the device (fp_capacity_overflows). */
+int fp_inject_dev(fp_ctx* ctx, fp_particles* p, uint32_t* pid_next, uint32_t* step_dev,
+                  uint32_t flags, hipStream_t s);
+/* Number of fp_inject_dev calls since fp_init that found no room (synchronous read-back). */
+int64_t fp_capacity_overflows(fp_ctx* ctx, hipStream_t s);
 /* Number of slots fp_inject writes per call (a configuration constant). */
 int64_t fp_inject_slots(const fp_ctx* ctx);
 /* Gas volume of every cell [m^3] into vol[ncell] (device): cylinder cells lose the part

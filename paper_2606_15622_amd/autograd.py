@@ -52,6 +52,8 @@ class ExactClosure(torch.autograd.Function):
 def _view(ctx, vx, vy, vz, n):
     p = F.Particles.__new__(F.Particles)
     p.n = n
+    p.n_dev = None
+    p.capacity = n
     p.x = vx            # positions are not read by the moment kernels
     p.y = None
     p.vx, p.vy, p.vz = vx, vy, vz

@@ -414,10 +414,11 @@ __global__ void amr_zero8_kernel(int64_t n, int8_t* __restrict__ a) {
 // keys of the particles under the new tree; keys outside [0, old_ncell) (deleted or
 // unused slots) become new_ncell
 template <typename T>
-__global__ void amr_rekey_kernel(fp_config g, int64_t n, const T* __restrict__ px,
-                                 const T* __restrict__ py, int32_t* __restrict__ key,
-                                 int32_t old_ncell, int32_t new_ncell,
+__global__ void amr_rekey_kernel(fp_config g, int64_t n, const int64_t* __restrict__ n_dev,
+                                 const T* __restrict__ px, const T* __restrict__ py,
+                                 int32_t* __restrict__ key, int32_t old_ncell, int32_t new_ncell,
                                  const int32_t* __restrict__ leafmap) {
+    if (n_dev) n = *n_dev;
     const int64_t p = (int64_t)blockIdx.x * AMR_BLOCK + threadIdx.x;
     if (p >= n) return;
     const int32_t k = key[p];
@@ -523,7 +524,8 @@ extern "C" int fp_amr_adapt(fp_ctx* c, const fp_amr_params* prm, double* acc, do
     if (!c || !prm || !acc || steps < 0 || prm->reserved != 0)
         return set_err(c, FP_EINVAL, "fp_amr_adapt: bad argument");
     if (c->amr_L < 0) return set_err(c, FP_EINVAL, "fp_amr_adapt: no tree (fp_amr_init)");
-    if (p && (!p->x || !p->y || !p->key || p->n < 0 || p->n > c->cfg.capacity))
+    if (p && (!p->x || !p->y || !p->key || p->n < 0 || p->n > c->cfg.capacity ||
+              (p->n_dev && (p->capacity < p->n || p->capacity > c->cfg.capacity))))
         return set_err(c, FP_EINVAL, "fp_amr_adapt: bad particles");
     const TreeDims t = dims(c);
     const int64_t nodes = t.off[t.L + 1];
@@ -567,14 +569,14 @@ extern "C" int fp_amr_adapt(fp_ctx* c, const fp_amr_params* prm, double* acc, do
                            (const double*)c->vol_old, (const double*)c->vol, samp);
     hipLaunchKernelGGL(amr_zero_kernel, dim3(blocks((int64_t)nleaf * SAMP)), dim3(AMR_BLOCK), 0, s,
                        (int64_t)nleaf * SAMP, acc);
-    if (p && p->n > 0) {
+    if (p && slots_of(p) > 0) {
         if (c->cfg.precision == FP_F32)
-            hipLaunchKernelGGL(amr_rekey_kernel<float>, dim3(blocks(p->n)), dim3(AMR_BLOCK), 0, s, c->cfg,
-                               p->n, (const float*)p->x, (const float*)p->y, p->key, old_ncell, nleaf,
+            hipLaunchKernelGGL(amr_rekey_kernel<float>, dim3(blocks(slots_of(p))), dim3(AMR_BLOCK), 0, s,
+                               c->cfg, p->n, (const int64_t*)p->n_dev, (const float*)p->x, (const float*)p->y, p->key, old_ncell, nleaf,
                                (const int32_t*)c->leafmap);
         else
-            hipLaunchKernelGGL(amr_rekey_kernel<double>, dim3(blocks(p->n)), dim3(AMR_BLOCK), 0, s, c->cfg,
-                               p->n, (const double*)p->x, (const double*)p->y, p->key, old_ncell, nleaf,
+            hipLaunchKernelGGL(amr_rekey_kernel<double>, dim3(blocks(slots_of(p))), dim3(AMR_BLOCK), 0, s,
+                               c->cfg, p->n, (const int64_t*)p->n_dev, (const double*)p->x, (const double*)p->y, p->key, old_ncell, nleaf,
                                (const int32_t*)c->leafmap);
     }
     return check_launch(c, "fp_amr_adapt");

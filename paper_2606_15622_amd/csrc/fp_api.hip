@@ -140,10 +140,10 @@ extern "C" int fp_init(const fp_config* cfg, fp_ctx** out) {
     bool ok = dalloc(&c->cnt, nc) && dalloc(&c->ccnt, nc) && dalloc(&c->coff, nc + 1) &&
               dalloc(&c->ccur, nc) && dalloc(&c->cwave, cap) && dalloc(&c->cmask, cap) &&
               dalloc(&c->gidx, cap) && dalloc(&c->blocksum, 2 * 8192) &&
-              dalloc(&c->errcount, 1) && dalloc(&c->ncnt, 9 * (nc - 1) + 1) && dalloc(&c->farn, 1) &&
+              dalloc(&c->errcount, 2) && dalloc(&c->ncnt, 9 * (nc - 1) + 1) && dalloc(&c->farn, 1) &&
               dalloc(&c->bidx, cap) && dalloc(&c->pend, nc) && dalloc(&c->stepc, 1);
     // the sort counters start at zero; every fp_bin / fp_rebin leaves them zero again
-    if (ok) ok = hipMemset(c->errcount, 0, sizeof(unsigned long long)) == hipSuccess &&
+    if (ok) ok = hipMemset(c->errcount, 0, 2 * sizeof(unsigned long long)) == hipSuccess &&
                  hipMemset(c->cnt, 0, sizeof(int32_t) * nc) == hipSuccess &&
                  hipMemset(c->ccnt, 0, sizeof(int32_t) * nc) == hipSuccess &&
                  hipMemset(c->ccur, 0, sizeof(int32_t) * nc) == hipSuccess &&
@@ -231,7 +231,8 @@ extern "C" int64_t fp_error_count(fp_ctx* c, hipStream_t s) {
 
 static bool particles_ok(const fp_ctx* c, const fp_particles* p, bool need_pos) {
     if (!p || p->n < 0 || p->n > c->cfg.capacity) return false;
-    if (p->n == 0) return true;
+    if (p->n_dev && (p->capacity < p->n || p->capacity > c->cfg.capacity)) return false;
+    if (slots_of(p) == 0) return true;
     if (!p->vx || !p->vy || !p->vz || !p->pid || !p->key) return false;
     if (need_pos && (!p->x || (c->cfg.geometry != FP_COUETTE1D && !p->y))) return false;
     return true;
@@ -241,9 +242,11 @@ extern "C" int fp_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int
                       int32_t* perm, hipStream_t s) {
     if (!c || !offsets || !particles_ok(c, src, true) || !dst)
         return set_err(c, FP_EINVAL, "fp_bin: bad argument");
-    if (src->n > 0 && (!dst->vx || !dst->vy || !dst->vz || !dst->pid || !dst->key || !dst->x ||
-                       (c->cfg.geometry != FP_COUETTE1D && !dst->y)))
+    if (slots_of(src) > 0 && (!dst->vx || !dst->vy || !dst->vz || !dst->pid || !dst->key || !dst->x ||
+                              (c->cfg.geometry != FP_COUETTE1D && !dst->y)))
         return set_err(c, FP_EINVAL, "fp_bin: bad destination");
+    if (dst->n_dev && dst->n_dev == src->n_dev)
+        return set_err(c, FP_EINVAL, "fp_bin: src and dst share their device count");
     if (src->vx == dst->vx || src->x == dst->x || src->pid == dst->pid)
         return set_err(c, FP_EINVAL, "fp_bin: src and dst alias");
     return launch_bin(c, src, dst, offsets, perm, s);
@@ -257,9 +260,11 @@ extern "C" int fp_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_o
     if (samp && samp == mom) return set_err(c, FP_EINVAL, "fp_rebin: samp and mom alias");
     if (c->amr_L >= 0)
         return set_err(c, FP_EINVAL, "fp_rebin: the re-sort needs the uniform grid (adaptive tree: fp_bin)");
-    if (src->n > 0 && (!dst->vx || !dst->vy || !dst->vz || !dst->pid || !dst->key || !dst->x ||
-                       (c->cfg.geometry != FP_COUETTE1D && !dst->y)))
+    if (slots_of(src) > 0 && (!dst->vx || !dst->vy || !dst->vz || !dst->pid || !dst->key || !dst->x ||
+                              (c->cfg.geometry != FP_COUETTE1D && !dst->y)))
         return set_err(c, FP_EINVAL, "fp_rebin: bad destination");
+    if (dst->n_dev && dst->n_dev == src->n_dev)
+        return set_err(c, FP_EINVAL, "fp_rebin: src and dst share their device count");
     if (src->vx == dst->vx || src->x == dst->x || src->pid == dst->pid)
         return set_err(c, FP_EINVAL, "fp_rebin: src and dst alias");
     if (src_offsets == offsets) return set_err(c, FP_EINVAL, "fp_rebin: src_offsets and offsets alias");
@@ -385,7 +390,27 @@ extern "C" int fp_inject(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_n
     if (!p->x || !p->y || !p->vx || !p->vy || !p->vz || !p->pid || !p->key)
         return set_err(c, FP_EINVAL, "fp_inject: bad particles");
     if (step > 0xFFFFFFFFull) return set_err(c, FP_EINVAL, "fp_inject: step beyond 2^32");
-    return launch_inject(c, p, at, pid_next, (uint32_t)step, s);
+    return launch_inject(c, p, at, pid_next, (uint32_t)step, nullptr, nullptr, s);
+}
+
+extern "C" int fp_inject_dev(fp_ctx* c, fp_particles* p, uint32_t* pid_next, uint32_t* step_dev,
+                             uint32_t flags, hipStream_t s) {
+    if (!c || !p || !pid_next || !step_dev || c->cfg.geometry != FP_CYLINDER2D || (flags & ~FP_STEP_ADVANCE))
+        return set_err(c, FP_EINVAL, "fp_inject_dev: bad argument or geometry");
+    if (!p->n_dev || p->capacity < 1 || p->capacity > c->cfg.capacity)
+        return set_err(c, FP_EINVAL, "fp_inject_dev: needs a device count and a capacity");
+    if (!p->x || !p->y || !p->vx || !p->vy || !p->vz || !p->pid || !p->key)
+        return set_err(c, FP_EINVAL, "fp_inject_dev: bad particles");
+    return launch_inject(c, p, -1, pid_next, 0u, step_dev, (flags & FP_STEP_ADVANCE) ? step_dev : nullptr, s);
+}
+
+extern "C" int64_t fp_capacity_overflows(fp_ctx* c, hipStream_t s) {
+    if (!c) return FP_EINVAL;
+    unsigned long long v = 0;
+    if (hipMemcpyAsync(&v, c->errcount + 1, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_err(c, FP_EDEVICE, "fp_capacity_overflows: copy failed");
+    return (int64_t)v;
 }
 
 extern "C" int fp_cell_volumes(fp_ctx* c, double* vol, hipStream_t s) {

@@ -18,10 +18,11 @@ constexpr int BIN_BLOCK = 256;
 // PLACE = true:  write the contribution records at their slots.
 template <bool PLACE>
 __global__ __launch_bounds__(BIN_BLOCK) void bin_wave_kernel(
-    const int32_t* __restrict__ key, int64_t n, int32_t ncell, int32_t* __restrict__ cnt,
-    int32_t* __restrict__ ccnt, int32_t* __restrict__ ccur, const int32_t* __restrict__ coff,
-    int32_t* __restrict__ cwave, uint64_t* __restrict__ cmask,
+    const int32_t* __restrict__ key, int64_t n, const int64_t* __restrict__ n_dev, int32_t ncell,
+    int32_t* __restrict__ cnt, int32_t* __restrict__ ccnt, int32_t* __restrict__ ccur,
+    const int32_t* __restrict__ coff, int32_t* __restrict__ cwave, uint64_t* __restrict__ cmask,
     unsigned long long* __restrict__ errcount) {
+    if (n_dev) n = *n_dev;   // the count kept on the device (the grid covers the slots)
     const int64_t p = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x;
     const int32_t wave = (int32_t)(p >> 6);
     const int lane = threadIdx.x & 63;
@@ -200,7 +201,8 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_gather_kernel(
     const T* __restrict__ svx, const T* __restrict__ svy, const T* __restrict__ svz,
     const uint32_t* __restrict__ spid, T* __restrict__ dx, T* __restrict__ dy,
     T* __restrict__ dvx, T* __restrict__ dvy, T* __restrict__ dvz, uint32_t* __restrict__ dpid,
-    int32_t* __restrict__ dkey, int32_t* __restrict__ perm) {
+    int32_t* __restrict__ dkey, int32_t* __restrict__ perm, int64_t* __restrict__ kept) {
+    if (kept && blockIdx.x == 0 && threadIdx.x == 0) *kept = offsets[ncell];
     using S = GatherShape<G>;
     __shared__ int32_t s_w[S::GROUPS][S::CAPC];
     __shared__ int32_t s_base[S::GROUPS][S::CAPC];
@@ -301,7 +303,7 @@ static void gather_launch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
                        two_d ? (const T*)src->y : (const T*)nullptr, (const T*)src->vx,
                        (const T*)src->vy, (const T*)src->vz, src->pid, (T*)dst->x,
                        two_d ? (T*)dst->y : (T*)nullptr, (T*)dst->vx, (T*)dst->vy,
-                       (T*)dst->vz, dst->pid, dst->key, perm);
+                       (T*)dst->vz, dst->pid, dst->key, perm, dst->n_dev);
 }
 
 template <typename T>
@@ -431,11 +433,12 @@ __device__ __forceinline__ int32_t strip_cell(int32_t t, int32_t nx, int32_t ny)
 
 template <int G>
 __global__ __launch_bounds__(BIN_BLOCK) void rebin_count_kernel(
-    int32_t ncell, int32_t nx, int64_t n, int64_t cap, int32_t cell_blocks,
-    const int32_t* __restrict__ src_off, const int32_t* __restrict__ key,
+    int32_t ncell, int32_t nx, int64_t n, const int64_t* __restrict__ n_dev, int64_t cap,
+    int32_t cell_blocks, const int32_t* __restrict__ src_off, const int32_t* __restrict__ key,
     int32_t* __restrict__ bend, int32_t* __restrict__ bidx, int32_t* __restrict__ cnt,
     int32_t* __restrict__ fcnt, int32_t* __restrict__ farn, uint64_t* __restrict__ flist,
     unsigned long long* __restrict__ errcount) {
+    if (n_dev) n = *n_dev;
     __shared__ int32_t sh[BIN_BLOCK / 64 + 1];
     __shared__ int32_t s_base;
     __shared__ int32_t s_next[BIN_BLOCK / G][9];
@@ -696,12 +699,15 @@ struct Rec {
 // call.
 template <typename T, int G>
 __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_kernel(
-    int32_t ncell, int32_t nx, int32_t ny, int64_t n, int64_t cap, int32_t cell_blocks,
+    int32_t ncell, int32_t nx, int32_t ny, int64_t n, const int64_t* __restrict__ n_dev,
+    int64_t* __restrict__ kept, int64_t cap, int32_t cell_blocks,
     const int32_t* __restrict__ src_off, const int32_t* __restrict__ bend,
     const int32_t* __restrict__ bidx, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ foff, const int32_t* __restrict__ fkey,
     const int32_t* __restrict__ fsrc, int32_t* __restrict__ cnt, int32_t* __restrict__ fcnt,
     int32_t* __restrict__ fcur, int32_t* __restrict__ farn, Rec<T> r) {
+    if (n_dev) n = *n_dev;
+    if (kept && blockIdx.x == 0 && threadIdx.x == 0) *kept = offsets[ncell];
     constexpr int GROUPS = BIN_BLOCK / G;
     __shared__ int32_t s_run[GROUPS][9][3];   // bucket start in bidx, length, far arrivals before
     for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i <= ncell;
@@ -834,12 +840,15 @@ constexpr int GM_U = 4;
 
 template <typename T, int G, int NVX>
 __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
-    int32_t ncell, int32_t nx, int32_t ny, int64_t n, int64_t cap,
+    int32_t ncell, int32_t nx, int32_t ny, int64_t n, const int64_t* __restrict__ n_dev,
+    int64_t* __restrict__ kept, int64_t cap,
     const int32_t* __restrict__ src_off, const int32_t* __restrict__ bend,
     const int32_t* __restrict__ bidx, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ foff, const int32_t* __restrict__ fsrc,
     int32_t* __restrict__ cnt, int32_t* __restrict__ fcnt, int32_t* __restrict__ fcur,
     int32_t* __restrict__ farn, Rec<T> r, double* __restrict__ mom, double* __restrict__ samp) {
+    if (n_dev) n = *n_dev;
+    if (kept && blockIdx.x == 0 && threadIdx.x == 0) *kept = offsets[ncell];
     constexpr int GROUPS = BIN_BLOCK / G;
     __shared__ int32_t s_run[GROUPS][9][4];   // start in bidx, length, far before, range start
     __shared__ int32_t s_pre[GROUPS][10];     // bucket starts in the cell's concatenation
@@ -1058,7 +1067,8 @@ static void rebin_count_launch(fp_ctx* c, const fp_particles* src, const int32_t
     // cnt, ccnt (far counts), ccur and farn are zero on entry: the previous sort call left
     // them so
     hipLaunchKernelGGL((rebin_count_kernel<G>), dim3(cblocks + FAR_BLOCKS), dim3(BIN_BLOCK), 0, s, nc,
-                       c->cfg.nx, src->n, c->cfg.capacity, cblocks, src_off, (const int32_t*)src->key,
+                       c->cfg.nx, src->n, (const int64_t*)src->n_dev, c->cfg.capacity, cblocks, src_off,
+                       (const int32_t*)src->key,
                        c->ncnt, c->bidx, c->cnt, c->ccnt, c->farn, c->cmask, c->errcount);
 }
 
@@ -1079,18 +1089,21 @@ static void rebin_gather_launch(fp_ctx* c, const fp_particles* src, const int32_
     if (mom) {
         if (c->cfg.moment_order == 3)
             hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G, NV_LOW>), dim3(cblocks), dim3(BIN_BLOCK), 0, s,
-                               nc, nx, ny, n, cap, src_off, (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
+                               nc, nx, ny, n, (const int64_t*)src->n_dev, dst->n_dev, cap, src_off,
+                               (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
                                (const int32_t*)offsets, (const int32_t*)c->coff, (const int32_t*)c->gidx,
                                c->cnt, c->ccnt, c->ccur, c->farn, r, mom, samp);
         else
             hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G, NV>), dim3(cblocks), dim3(BIN_BLOCK), 0, s,
-                               nc, nx, ny, n, cap, src_off, (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
+                               nc, nx, ny, n, (const int64_t*)src->n_dev, dst->n_dev, cap, src_off,
+                               (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
                                (const int32_t*)offsets, (const int32_t*)c->coff, (const int32_t*)c->gidx,
                                c->cnt, c->ccnt, c->ccur, c->farn, r, mom, samp);
         return;
     }
     hipLaunchKernelGGL((rebin_gather_kernel<T, G>), dim3(cblocks + FAR_BLOCKS), dim3(BIN_BLOCK),
-                       0, s, nc, nx, ny, n, cap, cblocks, src_off, (const int32_t*)c->ncnt,
+                       0, s, nc, nx, ny, n, (const int64_t*)src->n_dev, dst->n_dev, cap, cblocks, src_off,
+                       (const int32_t*)c->ncnt,
                        (const int32_t*)c->bidx, (const int32_t*)offsets, (const int32_t*)c->coff,
                        (const int32_t*)c->cwave, (const int32_t*)c->gidx, c->cnt, c->ccnt, c->ccur,
                        c->farn, r);
@@ -1151,12 +1164,12 @@ int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* o
                int32_t* perm, hipStream_t s) {
     // cnt, ccnt and ccur are zero on entry (fp_init, and every fp_bin/fp_rebin leaves them so)
     const int32_t nc = c->ncell;
-    const int64_t n = src->n;
-    const int64_t pgrid = (n + BIN_BLOCK - 1) / BIN_BLOCK;
-    if (n > 0)
+    const int64_t n = src->n, slots = slots_of(src);
+    const int64_t pgrid = (slots + BIN_BLOCK - 1) / BIN_BLOCK;
+    if (slots > 0)
         hipLaunchKernelGGL(bin_wave_kernel<false>, dim3((unsigned)pgrid), dim3(BIN_BLOCK), 0, s,
-                           src->key, n, nc, c->cnt, c->ccnt, c->ccur, (const int32_t*)c->coff,
-                           c->cwave, c->cmask, c->errcount);
+                           src->key, n, (const int64_t*)src->n_dev, nc, c->cnt, c->ccnt, c->ccur,
+                           (const int32_t*)c->coff, c->cwave, c->cmask, c->errcount);
     const int32_t nblocks = (nc + SCAN_TILE - 1) / SCAN_TILE;
     if (nblocks > 8191) return set_err(c, FP_EINVAL, "fp_bin: too many cells for the scan");
     hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt,
@@ -1164,10 +1177,10 @@ int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* o
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(SCAN_BLOCK), 0, s, c->blocksum, nblocks);
     hipLaunchKernelGGL(scan_final_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt,
                        nc, c->blocksum, nblocks, offsets, c->coff);
-    if (n > 0)
+    if (slots > 0)
         hipLaunchKernelGGL(bin_wave_kernel<true>, dim3((unsigned)pgrid), dim3(BIN_BLOCK), 0, s,
-                           src->key, n, nc, c->cnt, c->ccnt, c->ccur, (const int32_t*)c->coff,
-                           c->cwave, c->cmask, c->errcount);
+                           src->key, n, (const int64_t*)src->n_dev, nc, c->cnt, c->ccnt, c->ccur,
+                           (const int32_t*)c->coff, c->cwave, c->cmask, c->errcount);
     if (c->cfg.precision == FP_F32)
         gather_dispatch<float>(c, src, dst, offsets, perm, s);
     else

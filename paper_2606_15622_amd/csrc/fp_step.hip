@@ -542,7 +542,8 @@ __global__ __launch_bounds__(FR_BLOCK) void flight_rest_kernel(
 
 // flight (or key recomputation) without a collision: one thread per particle
 template <typename T, int GEOM, bool REC = false>
-__global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, T* __restrict__ px,
+__global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n,
+                                                         const int64_t* __restrict__ n_dev, T* __restrict__ px,
                                                          T* __restrict__ py, T* __restrict__ pvx,
                                                          T* __restrict__ pvy, T* __restrict__ pvz,
                                                          const uint32_t* __restrict__ ppid,
@@ -552,6 +553,7 @@ __global__ __launch_bounds__(ST_BLOCK) void move_kernel(fp_config g, int64_t n, 
                                                          double* __restrict__ wall,
                                                          const double* __restrict__ wall_edge, int32_t wall_nbins) {
     const uint32_t step = stepp ? stepp[0] : step_arg;
+    if (n_dev) n = *n_dev;
     constexpr bool TWO_D = GEOM != FP_COUETTE1D;
     const int64_t p = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
     if (p >= n) return;
@@ -656,27 +658,29 @@ static void step_typed(fp_ctx* c, fp_particles* p, const int32_t* off, const dou
         else collide_dispatch<T, FP_COUETTE1D>(c, p, off, mom, rec, step, 0, sp, nullptr, s);
         return;
     }
-    if (p->n == 0) return;
-    const unsigned grid = (unsigned)((p->n + ST_BLOCK - 1) / ST_BLOCK);
+    const int64_t slots = slots_of(p);
+    if (slots == 0) return;
+    const unsigned grid = (unsigned)((slots + ST_BLOCK - 1) / ST_BLOCK);
+    const int64_t* nd = p->n_dev;
     const int keys_only = (flags & FP_STEP_KEYS) ? 1 : 0;
     if (geom == FP_CAVITY2D)
         hipLaunchKernelGGL((move_kernel<T, FP_CAVITY2D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
-                           p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
+                           p->n, nd, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
                            step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap, c->wall,
                            (const double*)c->wall_edge, c->wall_nbins);
     else if (geom == FP_CYLINDER2D && c->wall)
         hipLaunchKernelGGL((move_kernel<T, FP_CYLINDER2D, true>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
-                           p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
+                           p->n, nd, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
                            step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap, c->wall,
                            (const double*)c->wall_edge, c->wall_nbins);
     else if (geom == FP_CYLINDER2D)
         hipLaunchKernelGGL((move_kernel<T, FP_CYLINDER2D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
-                           p->n, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
+                           p->n, nd, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key,
                            step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap, c->wall,
                            (const double*)c->wall_edge, c->wall_nbins);
     else
         hipLaunchKernelGGL((move_kernel<T, FP_COUETTE1D>), dim3(grid), dim3(ST_BLOCK), 0, s, c->cfg,
-                           p->n, (T*)p->x, (T*)nullptr, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid,
+                           p->n, nd, (T*)p->x, (T*)nullptr, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid,
                            p->key, step, keys_only, sp, c->ncell, (const int32_t*)c->leafmap, c->wall,
                            (const double*)c->wall_edge, c->wall_nbins);
 }
@@ -684,10 +688,25 @@ static void step_typed(fp_ctx* c, fp_particles* p, const int32_t* off, const dou
 
 // ---- free-stream inflow of the open domain ------------------------------------------------
 // counts of the four rectangles: floor(lambda_r) + Bernoulli(lambda_r - floor(lambda_r))
-// with the uniform of counter (r, step, 5, 1); cnt[0..3] counts, cnt[4..8] prefix
+// with the uniform of counter (r, step, 5, 1); cnt[0..3] counts, cnt[4..8] prefix, cnt[9]
+// the first slot (the host's at, or *n_dev; -1 when the slots do not fit below cap, which
+// is counted in *ovf), cnt[10] the step number (the host's, or *step_dev)
 __global__ void inject_count_kernel(fp_config g, double l0, double l1, double l2, double l3,
-                                    uint32_t step, int32_t* __restrict__ cnt) {
+                                    uint32_t step, const uint32_t* __restrict__ step_dev,
+                                    int64_t at, const int64_t* __restrict__ n_dev, int64_t cap,
+                                    int32_t slots, int32_t* __restrict__ cnt,
+                                    unsigned long long* __restrict__ ovf) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (step_dev) step = *step_dev;
+    if (n_dev) {
+        at = *n_dev;
+        if (at < 0 || at + slots > cap) {
+            at = -1;
+            atomicAdd(ovf, 1ull);
+        }
+    }
+    cnt[9] = (int32_t)at;
+    cnt[10] = (int32_t)step;
     const double lam[4] = {l0, l1, l2, l3};
     int32_t pre = 0;
     cnt[4] = 0;
@@ -707,7 +726,7 @@ struct InjectGeom {
 };
 
 template <typename T>
-__global__ __launch_bounds__(ST_BLOCK) void inject_kernel(fp_config g, InjectGeom ig, uint32_t step,
+__global__ __launch_bounds__(ST_BLOCK) void inject_kernel(fp_config g, InjectGeom ig,
                                                           const int32_t* __restrict__ cnt,
                                                           const uint32_t* __restrict__ pid_next,
                                                           T* __restrict__ px, T* __restrict__ py,
@@ -715,11 +734,15 @@ __global__ __launch_bounds__(ST_BLOCK) void inject_kernel(fp_config g, InjectGeo
                                                           T* __restrict__ pvz, uint32_t* __restrict__ ppid,
                                                           int32_t* __restrict__ pkey, int32_t ncell,
                                                           const int32_t* __restrict__ kmap) {
-    const int32_t slot = blockIdx.x * ST_BLOCK + threadIdx.x;
-    if (slot >= ig.slot0[4]) return;
+    const int32_t at = cnt[9];
+    const uint32_t step = (uint32_t)cnt[10];
+    if (at < 0) return;   // no room: nothing is written
+    const int32_t k0 = blockIdx.x * ST_BLOCK + threadIdx.x;   // slot of the call
+    if (k0 >= ig.slot0[4]) return;
+    const int64_t slot = (int64_t)at + k0;
     int r = 0;
-    while (r < 3 && slot >= ig.slot0[r + 1]) ++r;
-    const int32_t k = slot - ig.slot0[r];
+    while (r < 3 && k0 >= ig.slot0[r + 1]) ++r;
+    const int32_t k = k0 - ig.slot0[r];
     const bool f32 = sizeof(T) == 4;
     if (k >= cnt[r]) {
         pkey[slot] = ncell;   // unused slot
@@ -755,32 +778,45 @@ __global__ __launch_bounds__(ST_BLOCK) void inject_kernel(fp_config g, InjectGeo
     pkey[slot] = cell_key<true>(g, sx, sy, 1.0 / g.dx, 1.0 / g.dy, kmap);
 }
 
-__global__ void inject_advance_kernel(const int32_t* __restrict__ cnt, uint32_t* __restrict__ pid_next) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) pid_next[0] += (uint32_t)cnt[8];
+// after the slots are written: ids advance by the candidates drawn, the device count (if
+// any) by the slots, the step counter (if asked) by one
+__global__ void inject_advance_kernel(const int32_t* __restrict__ cnt, uint32_t* __restrict__ pid_next,
+                                      int64_t* __restrict__ n_dev, int32_t slots,
+                                      uint32_t* __restrict__ adv) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (cnt[9] >= 0) {
+        pid_next[0] += (uint32_t)cnt[8];
+        if (n_dev) n_dev[0] = (int64_t)cnt[9] + slots;
+    }
+    if (adv) adv[0] += 1u;
 }
 
 template <typename T>
 static void inject_typed(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_next, uint32_t step,
-                         hipStream_t s) {
+                         const uint32_t* step_dev, uint32_t* adv, hipStream_t s) {
     InjectGeom ig;
     for (int r = 0; r < 4; ++r)
         for (int k = 0; k < 4; ++k) ig.rect[r][k] = c->inj_rect[r][k];
     for (int r = 0; r < 5; ++r) ig.slot0[r] = c->inj_slot0[r];
-    hipLaunchKernelGGL(inject_count_kernel, dim3(1), dim3(64), 0, s, c->cfg, c->inj_lambda[0],
-                       c->inj_lambda[1], c->inj_lambda[2], c->inj_lambda[3], step, c->inj);
     const int32_t slots = ig.slot0[4];
+    // at < 0: the first slot is the device count (fp_inject_dev)
+    int64_t* n_dev = at < 0 ? p->n_dev : nullptr;
+    hipLaunchKernelGGL(inject_count_kernel, dim3(1), dim3(64), 0, s, c->cfg, c->inj_lambda[0],
+                       c->inj_lambda[1], c->inj_lambda[2], c->inj_lambda[3], step, step_dev, at,
+                       (const int64_t*)n_dev, (int64_t)p->capacity, slots, c->inj, c->errcount + 1);
     if (slots > 0)
         hipLaunchKernelGGL((inject_kernel<T>), dim3((slots + ST_BLOCK - 1) / ST_BLOCK), dim3(ST_BLOCK),
-                           0, s, c->cfg, ig, step, (const int32_t*)c->inj, (const uint32_t*)pid_next,
-                           (T*)p->x + at, (T*)p->y + at, (T*)p->vx + at, (T*)p->vy + at, (T*)p->vz + at,
-                           p->pid + at, p->key + at, c->ncell, (const int32_t*)c->leafmap);
-    hipLaunchKernelGGL(inject_advance_kernel, dim3(1), dim3(64), 0, s, (const int32_t*)c->inj, pid_next);
+                           0, s, c->cfg, ig, (const int32_t*)c->inj, (const uint32_t*)pid_next,
+                           (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy, (T*)p->vz, p->pid, p->key, c->ncell,
+                           (const int32_t*)c->leafmap);
+    hipLaunchKernelGGL(inject_advance_kernel, dim3(1), dim3(64), 0, s, (const int32_t*)c->inj, pid_next,
+                       n_dev, slots, adv);
 }
 
 int launch_inject(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_next, uint32_t step,
-                  hipStream_t s) {
-    if (c->cfg.precision == FP_F32) inject_typed<float>(c, p, at, pid_next, step, s);
-    else inject_typed<double>(c, p, at, pid_next, step, s);
+                  const uint32_t* step_dev, uint32_t* adv, hipStream_t s) {
+    if (c->cfg.precision == FP_F32) inject_typed<float>(c, p, at, pid_next, step, step_dev, adv, s);
+    else inject_typed<double>(c, p, at, pid_next, step, step_dev, adv, s);
     return check_launch(c, "fp_inject");
 }
 

@@ -53,7 +53,8 @@ class FPAMRParams(C.Structure):
 
 class FPParticles(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("vx", C.c_void_p), ("vy", C.c_void_p),
-                ("vz", C.c_void_p), ("pid", C.c_void_p), ("key", C.c_void_p), ("n", C.c_int64)]
+                ("vz", C.c_void_p), ("pid", C.c_void_p), ("key", C.c_void_p), ("n", C.c_int64),
+                ("n_dev", C.c_void_p), ("capacity", C.c_int64)]
 
 
 _lib = None
@@ -84,6 +85,9 @@ def load():
         L.fp_counter_add.argtypes = [vp, vp, u32, vp]
         L.fp_diagnostics.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, vp, vp]
         L.fp_inject.argtypes = [vp, P(FPParticles), i64, vp, u64, vp]
+        L.fp_inject_dev.argtypes = [vp, P(FPParticles), vp, vp, u32, vp]
+        L.fp_capacity_overflows.argtypes = [vp, vp]
+        L.fp_capacity_overflows.restype = i64
         L.fp_inject_slots.argtypes = [vp]
         L.fp_inject_slots.restype = i64
         L.fp_cell_volumes.argtypes = [vp, vp, vp]
@@ -117,7 +121,7 @@ def load():
                   "fp_nn_load", "fp_closure_nn", "fp_nn_outputs", "fp_nn_sensitivity", "fp_nn_features",
                   "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
                   "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
-                  "fp_inject", "fp_cell_volumes", "fp_step_dev", "fp_counter_add", "fp_diagnostics",
+                  "fp_inject", "fp_inject_dev", "fp_cell_volumes", "fp_step_dev", "fp_counter_add", "fp_diagnostics",
                   "fp_amr_init", "fp_amr_adapt", "fp_amr_tree", "fp_wall_sampling",
                   "fp_surface_coefficients", "fp_sample_high", "fp_high_order"):
             getattr(L, f).restype = C.c_int
@@ -178,10 +182,14 @@ def _stream(stream):
 class Particles:
     """Device particle arrays (structure of arrays) of one storage precision."""
 
-    def __init__(self, n, dtype, two_d, device="cuda", capacity=None):
+    def __init__(self, n, dtype, two_d, device="cuda", capacity=None, device_count=False):
+        """device_count: the count lives in a device word (n_dev), which the sort writes
+        and the injection advances; n is then only a launch-shape hint."""
         cap = int(capacity if capacity is not None else n)
         self.capacity = cap
         self.n = int(n)
+        self.n_dev = (torch.tensor([int(n)], dtype=torch.int64, device=device)
+                      if device_count else None)
         self.dtype = dtype
         self.two_d = two_d
         mk = lambda dt: torch.zeros(max(cap, 1), dtype=dt, device=device)
@@ -192,11 +200,11 @@ class Particles:
         self.key = mk(torch.int32)
 
     @classmethod
-    def from_numpy(cls, w, state, capacity=None, device="cuda"):
+    def from_numpy(cls, w, state, capacity=None, device="cuda", device_count=False):
         dt = torch.float32 if w["precision"] == "f32" else torch.float64
         two_d = w["geometry"] != "couette1d"
         n = state["x"].shape[0]
-        p = cls(n, dt, two_d, device, capacity)
+        p = cls(n, dt, two_d, device, capacity, device_count)
         npdt = np.float32 if dt == torch.float32 else np.float64
         for k in ("x", "vx", "vy", "vz"):
             getattr(p, k)[:n].copy_(torch.from_numpy(np.ascontiguousarray(state[k], dtype=npdt)))
@@ -213,10 +221,16 @@ class Particles:
         s.y = self.y.data_ptr() if self.y is not None else None
         s.pid, s.key = self.pid.data_ptr(), self.key.data_ptr()
         s.n = self.n
+        s.n_dev = self.n_dev.data_ptr() if self.n_dev is not None else None
+        s.capacity = self.capacity
         return s
 
+    def count(self):
+        """The particle count (a host read of the device word when there is one)."""
+        return int(self.n_dev.cpu()[0]) if self.n_dev is not None else self.n
+
     def numpy(self):
-        n = self.n
+        n = self.count()
         out = {k: getattr(self, k)[:n].double().cpu().numpy() for k in ("x", "vx", "vy", "vz")}
         out["y"] = self.y[:n].double().cpu().numpy() if self.y is not None else np.zeros(n)
         out["pid"] = self.pid[:n].cpu().numpy().view(np.uint32).copy()
@@ -303,6 +317,13 @@ class Context:
         self._check(self.lib.fp_inject(self.h, C.byref(a), int(at), _ptr(pid_next), int(step),
                                        _stream(stream)), "fp_inject")
 
+    def inject_dev(self, p, pid_next, step_dev, flags=0, stream=None):
+        self._check(self.lib.fp_inject_dev(self.h, C.byref(p.struct()), _ptr(pid_next), _ptr(step_dev),
+                                           int(flags), _stream(stream)), "fp_inject_dev")
+
+    def capacity_overflows(self, stream=None):
+        return int(self.lib.fp_capacity_overflows(self.h, _stream(stream)))
+
     def inject_slots(self):
         return int(self.lib.fp_inject_slots(self.h))
 
@@ -387,8 +408,9 @@ class AMRSimulation:
     finest level, max_level levels below the base grid): every adapt_every steps
     fp_amr_adapt on the sampling sums of the leaves since the last adaptation, then
     sort (fp_bin: the re-sort needs the uniform grid) -> moments -> sums (and sample) ->
-    closure -> collide + move -> inflow injection.  One host read of the live count per
-    step, one synchronous adaptation every adapt_every steps."""
+    closure -> collide + move -> inflow injection.  The particle count and the step
+    number live on the device (as in OpenSimulation); the adaptation every adapt_every
+    steps is synchronous (it reads the new leaf count back)."""
 
     def __init__(self, w, state, max_level, prm, adapt_every, capacity=None, device="cuda"):
         self.w, self.prm, self.adapt_every = w, dict(prm), int(adapt_every)
@@ -397,8 +419,9 @@ class AMRSimulation:
         self.ctx = Context(w, cap)
         self.ctx.amr_init(max_level)
         self.slots = self.ctx.inject_slots()
-        self.a = Particles.from_numpy(w, state, capacity=cap, device=device)
-        self.b = Particles(0, self.a.dtype, True, device, capacity=cap)
+        self.a = Particles.from_numpy(w, state, capacity=cap, device=device, device_count=True)
+        self.b = Particles(0, self.a.dtype, True, device, capacity=cap, device_count=True)
+        self.a.n = self.b.n = min(n0 + self.slots, cap)   # launch-shape hint
         nf = int(w["nx"]) * int(w["ny"])   # at most this many leaves
         self.offs = [torch.zeros(nf + 1, dtype=torch.int32, device=device) for _ in range(2)]
         self.mom = torch.zeros((nf, MOM_STRIDE), dtype=torch.float64, device=device)
@@ -408,7 +431,7 @@ class AMRSimulation:
         self.acc = torch.zeros((nf, SAMP_STRIDE), dtype=torch.float64, device=device)
         self.pid_next = torch.tensor([int(state.get("pid_next", n0))], dtype=torch.int64,
                                      device=device).to(torch.int32)
-        self.n_total = n0
+        self.step_ctr = torch.zeros(1, dtype=torch.int32, device=device)
         self.since = None
         self.ctx.step(self.a, None, None, None, 0, STEP_KEYS)   # leaf keys from positions
 
@@ -421,7 +444,6 @@ class AMRSimulation:
         return self.offs[0][:self.ncell + 1]
 
     def adapt(self, steps):
-        self.a.n = self.n_total
         self.ctx.amr_adapt(self.prm, self.acc, self.samp, self.a, steps)
 
     def step(self, s, sample=False, closure=None):
@@ -430,14 +452,9 @@ class AMRSimulation:
         elif self.adapt_every > 0 and s - self.since >= self.adapt_every:
             self.adapt(s - self.since)
             self.since = s
-        self.a.n = self.n_total
-        self.b.n = self.n_total
         self.ctx.bin(self.a, self.b, self.offs[1])
         self.offs.reverse()
         self.a, self.b = self.b, self.a
-        nc = self.ncell
-        live = int(self.offs[0][nc])
-        self.a.n = live
         self.ctx.moments(self.a, self.offs[0], self.mom)
         self.ctx.sample(self.mom, self.acc)
         if sample:
@@ -446,9 +463,10 @@ class AMRSimulation:
             self.ctx.closure_solve(self.mom, self.rec, self.status)
         else:
             closure(self.mom, self.rec, self.status)
-        self.ctx.step(self.a, self.offs[0], self.mom, self.rec, s, STEP_COLLIDE | STEP_MOVE)
-        self.ctx.inject(self.a, live, self.pid_next, s)
-        self.n_total = live + self.slots
+        self.step_ctr.fill_(s)
+        self.ctx.step_dev(self.a, self.offs[0], self.mom, self.rec, self.step_ctr,
+                          STEP_COLLIDE | STEP_MOVE)
+        self.ctx.inject_dev(self.a, self.pid_next, self.step_ctr)
 
     def run(self, step0, nsteps, n_skip=None):
         n_skip = self.w.get("n_skip", 0) if n_skip is None else n_skip
@@ -467,10 +485,13 @@ class AMRSimulation:
         torch.cuda.synchronize()
         return st.cpu().numpy(), age.cpu().numpy(), lm.cpu().numpy(), ln[:self.ncell].cpu().numpy()
 
+    def kept(self):
+        """Particles kept by the last sort (host read)."""
+        return int(self.offs[0][self.ncell])
+
     def live(self):
         """Particles after the last move and injection, deleted and unused slots removed
         (host copy, for checks)."""
-        self.a.n = self.n_total
         out = self.a.numpy()
         keep = out["key"] < self.ncell
         return {k: v[keep] for k, v in out.items()}
@@ -628,9 +649,11 @@ class GraphSimulation(Simulation):
 
 
 class OpenSimulation:
-    """Loop of the open cylinder domain: bin -> moments -> [sample] -> closure ->
-    collide + move (deleting particles that leave the box) -> inflow injection.  The
-    number of particles kept by the sort is read back once per step (one host sync)."""
+    """Loop of the open cylinder domain: sort -> moments -> [sample] -> closure -> collide +
+    move (deleting particles that leave the box) -> inflow injection.  The particle count
+    lives on the device (each particle buffer has its own count word: the sort writes the
+    number it keeps, the injection appends behind it and advances it) and so does the step
+    number, so a step needs no host read; GraphOpenSimulation captures it."""
 
     def __init__(self, w, state, capacity=None, device="cuda"):
         self.w = w
@@ -638,8 +661,10 @@ class OpenSimulation:
         cap = int(capacity if capacity is not None else 2 * n0 + 1_000_000)
         self.ctx = Context(w, cap)
         self.slots = self.ctx.inject_slots()
-        self.a = Particles.from_numpy(w, state, capacity=cap, device=device)
-        self.b = Particles(0, self.a.dtype, True, device, capacity=cap)
+        self.a = Particles.from_numpy(w, state, capacity=cap, device=device, device_count=True)
+        self.b = Particles(0, self.a.dtype, True, device, capacity=cap, device_count=True)
+        # launch-shape hint of both buffers (the count itself is on the device)
+        self.a.n = self.b.n = min(n0 + self.slots, cap)
         nc = self.ctx.ncell
         self.offs = [torch.zeros(nc + 1, dtype=torch.int32, device=device) for _ in range(2)]
         self.sorted = False
@@ -649,7 +674,7 @@ class OpenSimulation:
         self.samp = torch.zeros((nc, SAMP_STRIDE), dtype=torch.float64, device=device)
         self.pid_next = torch.tensor([int(state.get("pid_next", n0))], dtype=torch.int64,
                                      device=device).to(torch.int32)
-        self.n_total = n0
+        self.step_ctr = torch.zeros(1, dtype=torch.int32, device=device)
         if "key" not in state:
             self.ctx.step(self.a, None, None, None, 0, STEP_KEYS)
 
@@ -657,9 +682,8 @@ class OpenSimulation:
     def offsets(self):
         return self.offs[0]
 
-    def step(self, s, sample=False, closure=None):
-        self.a.n = self.n_total
-        self.b.n = self.n_total
+    def _body(self, sample, closure):
+        """One step at the device step number; advances it."""
         # after the first step the live particles are grouped by their previous cells and
         # the injected ones follow them: the re-sort applies
         fused = self.sorted
@@ -671,8 +695,6 @@ class OpenSimulation:
         self.offs.reverse()
         self.sorted = True
         self.a, self.b = self.b, self.a
-        live = int(self.offsets[-1])
-        self.a.n = live
         if not fused:
             self.ctx.moments(self.a, self.offsets, self.mom)
             if sample:
@@ -681,19 +703,60 @@ class OpenSimulation:
             self.ctx.closure_solve(self.mom, self.rec, self.status)
         else:
             closure(self.mom, self.rec, self.status)
-        self.ctx.step(self.a, self.offsets, self.mom, self.rec, s, STEP_COLLIDE | STEP_MOVE)
-        self.ctx.inject(self.a, live, self.pid_next, s)
-        self.n_total = live + self.slots
+        self.ctx.step_dev(self.a, self.offsets, self.mom, self.rec, self.step_ctr,
+                          STEP_COLLIDE | STEP_MOVE)
+        self.ctx.inject_dev(self.a, self.pid_next, self.step_ctr, STEP_ADVANCE)
+
+    def step(self, s, sample=False, closure=None):
+        self.step_ctr.fill_(s)
+        self._body(sample, closure)
 
     def run(self, step0, nsteps, n_skip=None):
         n_skip = self.w.get("n_skip", 0) if n_skip is None else n_skip
         for s in range(step0, step0 + nsteps):
             self.step(s, sample=s >= n_skip)
 
+    def kept(self):
+        """Particles kept by the last sort (host read)."""
+        return int(self.offsets[-1])
+
     def live(self):
         """Particles after the last move and injection, deleted and unused slots removed
         (host copy, for checks)."""
-        self.a.n = self.n_total
         out = self.a.numpy()
         keep = out["key"] < self.ctx.ncell
         return {k: v[keep] for k, v in out.items()}
+
+
+class GraphOpenSimulation(OpenSimulation):
+    """OpenSimulation whose step is captured once in a HIP graph and replayed: two steps
+    back to back (the particle buffers and their count words return to their places), the
+    step number and the particle count advanced on the device."""
+
+    def __init__(self, w, state, capacity=None, device="cuda"):
+        super().__init__(w, state, capacity, device)
+        self.graphs = {}
+
+    def _graph(self, sample):
+        if sample not in self.graphs:
+            if not self.sorted:
+                raise RuntimeError("run one eager step before capturing (the first sort is general)")
+            g = torch.cuda.CUDAGraph()
+            torch.cuda.synchronize()
+            saved = (self.step_ctr.clone(), self.samp.clone(), self.pid_next.clone(),
+                     self.a.n_dev.clone(), self.b.n_dev.clone())
+            with torch.cuda.graph(g):
+                for _ in range(2):
+                    self._body(sample, None)
+            torch.cuda.synchronize()
+            # capture executes nothing; restore anyway
+            for t, v in zip((self.step_ctr, self.samp, self.pid_next, self.a.n_dev, self.b.n_dev), saved):
+                t.copy_(v)
+            self.graphs[sample] = g
+        return self.graphs[sample]
+
+    def run_pairs(self, npairs, sample=False):
+        """Advance 2 * npairs steps by graph replays (from the device step number)."""
+        g = self._graph(sample)
+        for _ in range(npairs):
+            g.replay()

@@ -239,14 +239,14 @@ def test_full_size_tree_properties():
     for s in range(120):
         sim.step(s, sample=True)
     for k in range(2):
-        sim.a.n = sim.n_total
-        keys = sim.a.key[:sim.n_total].clone()
+        n = sim.a.count()
+        keys = sim.a.key[:n].clone()
         live0 = int((keys < sim.ncell).sum())
         samp0 = sim.samp[:sim.ncell].sum(0).cpu().numpy()
         nleaf0 = sim.ncell
         sim.adapt(60)
         torch.cuda.synchronize()
-        live1 = int((sim.a.key[:sim.n_total] < sim.ncell).sum())
+        live1 = int((sim.a.key[:n] < sim.ncell).sum())
         assert live1 == live0
         samp1 = sim.samp[:sim.ncell].sum(0).cpu().numpy()
         np.testing.assert_allclose(samp1[:13], samp0[:13], rtol=1e-9)

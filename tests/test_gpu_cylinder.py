@@ -225,3 +225,64 @@ def test_surface_sampling_matches_oracle():
     box = F.Context(I.cavity(ncell=8, ppc=4), 10)
     with pytest.raises(RuntimeError):
         box.wall_sampling(sums)
+
+
+def test_open_graph_replay_matches_eager_bitwise():
+    """The open-domain step with the particle count and the step number on the device,
+    captured once in a HIP graph (two steps) and replayed, equals the eager loop bit for
+    bit on every replay (particles, count words, ids, sums), with eager work and
+    synchronisations between the replays; no host read inside a step."""
+    F = fp()
+    w = small("f32", mach=10.0)
+    s = I.freestream_state(w, seed=6)
+    eager = F.OpenSimulation(w, s)
+    graph = F.GraphOpenSimulation(w, s)
+    for k in range(2):
+        eager.step(k, sample=True)
+        graph.step(k, sample=True)
+    step = 2
+    for rep in range(4):
+        sample = rep % 2 == 0
+        graph.run_pairs(1, sample=sample)
+        for _ in range(2):
+            eager.step(step, sample=sample)
+            step += 1
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()
+        assert eager.a.count() == graph.a.count() and eager.kept() == graph.kept(), rep
+        ga, ea = graph.live(), eager.live()
+        for k in ea:
+            np.testing.assert_array_equal(ga[k], ea[k], err_msg=f"replay {rep} {k}")
+        assert torch.equal(graph.samp, eager.samp)
+        assert torch.equal(graph.pid_next, eager.pid_next)
+        assert int(graph.step_ctr.cpu()[0]) == step
+        del junk
+    # the count word after the injection is the kept count plus the injection slots
+    assert graph.a.count() == graph.kept() + graph.slots
+
+
+def test_inject_dev_without_room_writes_nothing_and_counts_it():
+    """fp_inject_dev with too little capacity left: nothing written, the count word and
+    the ids unchanged, the overflow counted on the device; with room it appends at the
+    count word and advances it (and the step counter with FP_STEP_ADVANCE)."""
+    F = fp()
+    w = small("f32", mach=10.0)
+    s = I.freestream_state(w, seed=8)
+    n0 = s["x"].shape[0]
+    probe = F.Context(w, n0 + 10)
+    slots = probe.inject_slots()
+    cap = n0 + slots // 2
+    sim = F.OpenSimulation(w, s, capacity=cap)
+    sim.step(0)
+    torch.cuda.synchronize()
+    kept = sim.kept()
+    assert kept + slots > cap
+    assert sim.a.count() == kept and sim.ctx.capacity_overflows() == 1
+    assert int(sim.pid_next.cpu()[0]) == n0
+    # with room: a context and buffers large enough
+    sim2 = F.OpenSimulation(w, s)
+    sim2.step(0)
+    torch.cuda.synchronize()
+    assert sim2.a.count() == sim2.kept() + slots and sim2.ctx.capacity_overflows() == 0
+    assert int(sim2.step_ctr.cpu()[0]) == 1
+    assert int(sim2.pid_next.cpu()[0]) > n0
