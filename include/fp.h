@@ -390,6 +390,20 @@ int fp_nn_load(fp_ctx* ctx, fp_nn* net, const float* params, hipStream_t s);
  * fp_closure_solve.  Same rec layout. */
 int fp_closure_nn(fp_ctx* ctx, const fp_nn* net, const double* mom, double* rec,
                   int32_t* status, double tol_abs, double tol_rel, double relax, hipStream_t s);
+/* fp_closure_nn for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same results, bit for bit, but the network outputs pass between the two kernels through a
+ * fixed library array of FP_NN_NOALLOC_CELLS x 16 floats (16 MiB, one per GPU, held until
+ * the process ends; its device address is looked up by fp_nn_create) instead of the
+ * handle's buffer.  The call itself allocates nothing.  FP_EINVAL if the context has more
+ * than FP_NN_NOALLOC_CELLS cells.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, other contexts) race and must be serialised by
+ * the caller; each call writes every entry it reads, so nothing needs clearing.
+ * fp_nn_outputs still returns the outputs of the last fp_closure_nn, not of this call. */
+#define FP_NN_NOALLOC_CELLS 262144
+int fp_closure_nn_noalloc(fp_ctx* ctx, const fp_nn* net, const double* mom, double* rec,
+                          int32_t* status, double tol_abs, double tol_rel, double relax,
+                          hipStream_t s);
 /* Coefficient-sensitivity probe (Sec. "Heuristic coefficient-sensitivity probe"): npass
  * >= 1 forward passes of the network on every cell's moments (mom [ncell][32], device)
  * with inference-time dropout of rate p in [0, 1) on the three hidden layers (inverted:

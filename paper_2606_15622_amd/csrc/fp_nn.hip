@@ -18,6 +18,9 @@
 // are stored fragment-major ([tile][k-step][lane][8]) and live in LDS.
 #include "fp_closure_dev.h"
 
+#include <mutex>
+#include <string>
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -682,9 +685,46 @@ static bool nalloc(T** p, size_t count) {
     return hipMalloc((void**)p, sizeof(T) * (count ? count : 1)) == hipSuccess;
 }
 
+// ---- scratch of fp_closure_nn_noalloc --------------------------------------------------
+// The standardised network outputs pass from the network kernel to the check kernel through
+// this file-scope array instead of the handle's buffer: every GPU the library runs on holds
+// one copy of FP_NN_NOALLOC_CELLS x 16 floats (16 MiB) until the process ends.  In host code
+// the name `scratch` is a host-side stand-in, not a device address: fp_nn_create looks up
+// the address of the current device's copy once per device (hipGetSymbolAddress) and keeps
+// it in scratch_dev[device]; host code uses only that pointer.
+static __device__ __align__(256) float scratch[(size_t)FP_NN_NOALLOC_CELLS * NO];
+constexpr int SCRATCH_DEVICES = 64;
+static std::mutex scratch_mu;
+static float* scratch_dev[SCRATCH_DEVICES] = {};
+
+// With the context's device current: look up that device's copy of the array once.
+static int scratch_setup(fp_ctx* c) {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (c->device < 0 || c->device >= SCRATCH_DEVICES) return FP_EINVAL;
+    if (scratch_dev[c->device]) return FP_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FP_EDEVICE;
+    scratch_dev[c->device] = (float*)ptr;
+    return FP_OK;
+}
+
+static float* scratch_of(const fp_ctx* c) {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    return (c->device >= 0 && c->device < SCRATCH_DEVICES) ? scratch_dev[c->device] : nullptr;
+}
+
 extern "C" int fp_nn_create(fp_ctx* c, int64_t max_batch, fp_nn** out) {
     if (!c || !out || max_batch < 0 || max_batch > ((int64_t)1 << 26)) return FP_EINVAL;
     *out = nullptr;
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return set_err(c, FP_EDEVICE, "fp_nn_create: hipGetDevice failed");
+        if (cur != c->device && hipSetDevice(c->device) != hipSuccess)
+            return set_err(c, FP_EDEVICE, "fp_nn_create: hipSetDevice failed");
+        const int rc = scratch_setup(c);
+        if (cur != c->device) (void)hipSetDevice(cur);
+        if (rc) return set_err(c, rc, "fp_nn_create: no address for the no-allocation scratch");
+    }
     fp_nn* n = new (std::nothrow) fp_nn();
     if (!n) return FP_ENOMEM;
     n->ctx = c;
@@ -731,22 +771,43 @@ int launch_closure_nn(fp_ctx* c, const float* ynn, const float* ysec, double tol
                       hipStream_t s);
 }
 
-extern "C" int fp_closure_nn(fp_ctx* c, const fp_nn* n, const double* mom, double* rec,
-                             int32_t* status, double tol_abs, double tol_rel, double relax,
-                             hipStream_t s) {
+// network kernel into ybuf ([ncell][16] floats), then the check / de-normalisation kernel
+static int closure_nn(fp_ctx* c, const fp_nn* n, const double* mom, double* rec, int32_t* status,
+                      double tol_abs, double tol_rel, double relax, float* ybuf, const char* what,
+                      hipStream_t s) {
     if (!c || !n || !mom || !rec || !status || n->ctx != c || !(tol_abs >= 0) || !(tol_rel >= 0) ||
         !(relax > 0.0 && relax <= 1.0))
-        return set_err(c, FP_EINVAL, "fp_closure_nn: bad argument");
+        return set_err(c, FP_EINVAL, std::string(what) + ": bad argument");
     if (c->cfg.moment_order == 3 && tol_abs != INFINITY)
-        return set_err(c, FP_EINVAL, "fp_closure_nn: the check needs moments through fifth order");
+        return set_err(c, FP_EINVAL, std::string(what) + ": the check needs moments through fifth order");
     const int32_t ntiles = (c->ncell + 31) / 32;
     int grid = (ntiles + NN_BLOCK / 64 - 1) / (NN_BLOCK / 64);
     if (grid > 256) grid = 256;   // one workgroup per CU, each loops over its tiles
     hipLaunchKernelGGL(nn_infer_kernel, dim3(grid), dim3(NN_BLOCK), 0, s, c->ncell, mom,
-                       c->cfg.eps_hat, (const __bf16*)n->img, (const float*)n->sec, n->ybuf);
-    int rc = check_launch(c, "fp_closure_nn (network)");
+                       c->cfg.eps_hat, (const __bf16*)n->img, (const float*)n->sec, ybuf);
+    int rc = check_launch(c, what);
     if (rc) return rc;
-    return launch_closure_nn(c, n->ybuf, n->sec + SEC_YM, tol_abs, tol_rel, relax, mom, rec, status, s);
+    return launch_closure_nn(c, ybuf, n->sec + SEC_YM, tol_abs, tol_rel, relax, mom, rec, status, s);
+}
+
+extern "C" int fp_closure_nn(fp_ctx* c, const fp_nn* n, const double* mom, double* rec,
+                             int32_t* status, double tol_abs, double tol_rel, double relax,
+                             hipStream_t s) {
+    if (!c || !n) return set_err(c, FP_EINVAL, "fp_closure_nn: bad argument");
+    return closure_nn(c, n, mom, rec, status, tol_abs, tol_rel, relax, n->ybuf, "fp_closure_nn", s);
+}
+
+extern "C" int fp_closure_nn_noalloc(fp_ctx* c, const fp_nn* n, const double* mom, double* rec,
+                                     int32_t* status, double tol_abs, double tol_rel, double relax,
+                                     hipStream_t s) {
+    if (!c || !n) return set_err(c, FP_EINVAL, "fp_closure_nn_noalloc: bad argument");
+    if (c->ncell > FP_NN_NOALLOC_CELLS)
+        return set_err(c, FP_EINVAL, "fp_closure_nn_noalloc: more cells than FP_NN_NOALLOC_CELLS (" +
+                                         std::to_string(c->ncell) + " > " +
+                                         std::to_string(FP_NN_NOALLOC_CELLS) + ")");
+    float* y = scratch_of(c);
+    if (!y) return set_err(c, FP_EINVAL, "fp_closure_nn_noalloc: no scratch on this device");
+    return closure_nn(c, n, mom, rec, status, tol_abs, tol_rel, relax, y, "fp_closure_nn_noalloc", s);
 }
 
 extern "C" int fp_nn_sensitivity(fp_ctx* c, const fp_nn* n, const double* mom, int32_t npass,

@@ -95,6 +95,8 @@ def load():
         L.fp_nn_destroy.argtypes = [vp]
         L.fp_nn_load.argtypes = [vp, vp, vp, vp]
         L.fp_closure_nn.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
+        L.fp_closure_nn_noalloc.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
+                                            vp]
         L.fp_nn_outputs.argtypes = [vp, vp, vp, vp]
         L.fp_nn_sensitivity.argtypes = [vp, vp, vp, i32, C.c_double, u64, vp, vp]
         L.fp_sample_high.argtypes = [vp, vp, vp, vp]
@@ -118,7 +120,7 @@ def load():
         L.fp_closure_solve_backward.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fp_moments_backward.argtypes = [vp, P(FPParticles), vp, vp, vp, vp, vp, vp, vp]
         for f in ("fp_bin", "fp_rebin", "fp_moments", "fp_closure_solve", "fp_step", "fp_sample", "fp_nn_create",
-                  "fp_nn_load", "fp_closure_nn", "fp_nn_outputs", "fp_nn_sensitivity", "fp_nn_features",
+                  "fp_nn_load", "fp_closure_nn", "fp_closure_nn_noalloc", "fp_nn_outputs", "fp_nn_sensitivity", "fp_nn_features",
                   "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
                   "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
                   "fp_inject", "fp_inject_dev", "fp_cell_volumes", "fp_step_dev", "fp_counter_add", "fp_diagnostics",
@@ -528,6 +530,12 @@ class Network:
         c = self.ctx
         c._check(c.lib.fp_closure_nn(c.h, self.h, _ptr(mom), _ptr(rec), _ptr(status), float(tol_abs),
                                      float(tol_rel), float(relax), _stream(stream)), "fp_closure_nn")
+
+    def closure_noalloc(self, mom, rec, status, tol_abs, tol_rel, relax=1.0, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_closure_nn_noalloc(c.h, self.h, _ptr(mom), _ptr(rec), _ptr(status),
+                                             float(tol_abs), float(tol_rel), float(relax),
+                                             _stream(stream)), "fp_closure_nn_noalloc")
 
     def sensitivity(self, mom, npass, p, seed, sens, stream=None):
         c = self.ctx
