@@ -256,8 +256,11 @@ int fp_high_order(fp_ctx* ctx, const double* hsamp, double* out, hipStream_t s);
  * caller-owned, zeroed by the caller): hits, normal momentum v_out.n - v_in.n, tangential
  * momentum towards the rear (v_in - v_out).t, energy (|v_in|^2 - |v_out|^2)/2, per unit
  * molecular mass, n the outward normal, t the tangent along decreasing theta, in bins of
- * the surface angle theta = |atan2(n_y, n_x)| (0 at the rear point, pi at the front
- * stagnation point; both halves of the circle share a bin).  FP64 atomic adds (their
+ * the surface angle theta (0 at the rear point, pi at the front stagnation point; both
+ * halves of the circle share a bin): a hit goes to bin b when
+ * cos((b + 1) pi / nbins) < n_x <= cos(b pi / nbins), decided by comparing cos(theta) = n_x
+ * with edges the host computes once (so every implementation bins a hit point alike,
+ * which the last bits of an arctangent would not guarantee).  FP64 atomic adds (their
  * order, and so the last bits of the sums, vary from run to run).  sums = NULL stops;
  * the caller keeps sums allocated until then (the context holds only the pointer).  A HIP
  * graph captured meanwhile keeps the pointer.  FP_EINVAL for other geometries or
@@ -417,6 +420,10 @@ int fp_closure_nn_noalloc(fp_ctx* ctx, const fp_nn* net, const double* mom, doub
  * never drops units.  FP_EINVAL for a bad argument. */
 int fp_nn_sensitivity(fp_ctx* ctx, const fp_nn* net, const double* mom, int32_t npass,
                       double p, uint64_t seed, double* sens, hipStream_t s);
+/* The network alone (no check, no de-normalisation): standardised outputs of every cell's
+ * moments into y[ncell][16] floats (device, caller-owned); rows 9..15 zero, cells with
+ * N <= 1 or theta <= 0 evaluated on zero features. */
+int fp_nn_infer(fp_ctx* ctx, const fp_nn* net, const double* mom, float* y, hipStream_t s);
 /* Copy the standardised network outputs of the last fp_closure_nn ([ncell][16]). */
 int fp_nn_outputs(fp_ctx* ctx, const fp_nn* net, float* y, hipStream_t s);
 /* Raw (unstandardised) features of n moment records: feats[n][32] floats. */
@@ -437,6 +444,66 @@ int fp_nn_adam(fp_ctx* ctx, float* params, const float* grad, float* m, float* v
 int fp_nn_train_step(fp_ctx* ctx, fp_nn* net, float* params, float* m, float* v, int64_t t,
                      float lr, const float* feats, const float* targets, const double* sys,
                      int64_t B, int32_t loss_kind, float* loss, hipStream_t s);
+
+/* ---- the paper's LITE surrogate -------------------------------------------------------
+ * Secs. "Phase 1-2", "Neural Network Architecture" and "Phase 3": a 16-256-256-256-256-9
+ * network with ReLU hidden layers and a linear output, on 16 low-order inputs of the cell
+ *   [rho, T, U_x, U_y, U_z, Pi_11, Pi_12, Pi_13, Pi_22, Pi_23, Pi_33, q_x, q_y, q_z, DM2, nu]
+ * with rho = N fnum / V m, T = theta m / k_B, Pi_ij = rho (P_ij - theta delta_ij),
+ * q_i = rho S_i / 2, DM2 = <|c|^2> = 3 theta, nu = 1 / tau (eq. tau), predicting the
+ * coefficients of the update record [Ct (6), Gamma (3)] in solver units; inputs and
+ * outputs standardised.  It needs moments through third order only: on a context with
+ * moment_order 3 (the high-order gather skipped) it runs unchecked.  BF16 MFMA with FP32
+ * accumulation; inference in one kernel with the layers' weights staged through LDS.
+ *
+ * Parameter vector: FP_LITE_PARAMS floats, device memory, owned by the caller:
+ *   W1[256][16] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] W4[256][256] b4[256]
+ *   W5[16][256] b5[16] x_mean[16] x_std[16] y_mean[16] y_std[16]
+ * (W[out][in] row-major; output rows 9..15 are padding and should be zero; the first
+ * FP_LITE_TRAIN floats are trained, the scalers fixed).  The paper's 204,041 trainable
+ * parameters are this prefix without the padded output rows. */
+#define FP_LITE_PARAMS 205904
+#define FP_LITE_TRAIN 205840
+#define FP_LITE_FEATURES 16
+typedef struct fp_lite fp_lite;
+/* Create a LITE network on ctx with training scratch for batches up to max_batch (0:
+ * inference only).  Synchronous. */
+int fp_lite_create(fp_ctx* ctx, int64_t max_batch, fp_lite** out);
+void fp_lite_destroy(fp_lite* net);
+/* Convert params (FP_LITE_PARAMS floats, device) into the network's BF16 image. */
+int fp_lite_load(fp_ctx* ctx, fp_lite* net, const float* params, hipStream_t s);
+/* Standardised network outputs of every cell's moments: y[ncell][16] floats (rows 9..15
+ * zero; cells with N <= 1 or theta <= 0 are evaluated on zero inputs). */
+int fp_lite_infer(fp_ctx* ctx, const fp_lite* net, const double* mom, float* y, hipStream_t s);
+/* Learned closure of every cell with the LITE network: same contract, checks, statuses,
+ * fallback and relax as fp_closure_nn (Algorithm "Accelerated ML Simulation Loop"). */
+int fp_closure_lite(fp_ctx* ctx, const fp_lite* net, const double* mom, double* rec,
+                    int32_t* status, double tol_abs, double tol_rel, double relax, hipStream_t s);
+/* Raw inputs of n moment records: feats[n][16] floats; nvol[n] (device, optional): real
+ * molecules per particle over the cell volume of each record (NULL: fnum_over_vol). */
+int fp_lite_features(fp_ctx* ctx, const double* mom, const double* nvol, int64_t n, float* feats,
+                     hipStream_t s);
+/* Raw targets [Ct (6), Gamma (3), 0 (7)] of n update records: targets[n][16] floats. */
+int fp_lite_targets(fp_ctx* ctx, const double* rec, int64_t n, float* targets, hipStream_t s);
+/* Gradient of the mean over the batch of the squared error of the standardised targets
+ * (the paper's MSE) w.r.t. the trainable parameters: grad[FP_LITE_PARAMS] (trainable
+ * prefix written) and *loss (device float); fixed-order reductions, bitwise reproducible. */
+int fp_lite_grad(fp_ctx* ctx, fp_lite* net, const float* params, const float* feats,
+                 const float* targets, int64_t B, float* grad, float* loss, hipStream_t s);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8) step t >= 1 on the trainable prefix. */
+int fp_lite_adam(fp_ctx* ctx, float* params, const float* grad, float* m, float* v, int64_t t,
+                 float lr, hipStream_t s);
+/* fp_lite_grad followed by fp_lite_adam (Sec. "Phase 1-2": Adam on the MSE). */
+int fp_lite_train_step(fp_ctx* ctx, fp_lite* net, float* params, float* m, float* v, int64_t t,
+                       float lr, const float* feats, const float* targets, int64_t B, float* loss,
+                       hipStream_t s);
+
+/* Per-column mean and population standard deviation of x[n][k] (device floats; k <= 4096)
+ * into mean[k], stdev[k] (device doubles): the standardising scalers of the networks'
+ * inputs and targets (Sec. "Phase 3": means and scales; Sec. "Phase 1-2": StandardScaler).
+ * FP64 sums in a fixed order: bitwise reproducible. */
+int fp_column_stats(fp_ctx* ctx, const float* x, int64_t n, int32_t k, double* mean, double* stdev,
+                    hipStream_t s);
 
 /* ---- differentiation (project extension) -------------------------------------------
  * Reverse mode through fp_moments and fp_closure_solve for the map

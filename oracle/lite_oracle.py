@@ -172,16 +172,25 @@ def adam(p_flat, g_flat, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     return p, m, v
 
 
+def standardise(f, P, emulate_fp32=False):
+    """(f - x_mean) / x_std; with emulate_fp32 the inputs are first stored as FP32 and the
+    standardisation is done in FP32, as the GPU forms its network input."""
+    if not emulate_fp32:
+        return (f - P["x_mean"]) / P["x_std"]
+    f32 = np.asarray(f).astype(np.float32)
+    return ((f32 - P["x_mean"].astype(np.float32)) / P["x_std"].astype(np.float32)).astype(np.float64)
+
+
 def coefficients(w, p_flat, mom, nvol=None, emulate_bf16=True):
     """The LITE closure of moment records: (Ct [n][6], Gamma [n][3], valid [n]) from the
     de-standardised network outputs; cells without features (N <= 1 or theta <= 0) are
-    not valid."""
+    not valid.  With emulate_bf16 the network input is also formed in FP32 (standardise)."""
     P = unpack(p_flat)
     mom = np.asarray(mom, dtype=np.float64)
     valid = (mom[:, 0] > 1.0) & (mom[:, 4] > 0.0)
     f = np.zeros((mom.shape[0], NF))
     if valid.any():
         f[valid] = features(w, mom[valid], None if nvol is None else np.asarray(nvol)[valid])
-    y, _ = forward(P, (f - P["x_mean"]) / P["x_std"], emulate_bf16)
+    y, _ = forward(P, standardise(f, P, emulate_bf16), emulate_bf16)
     d = y * P["y_std"] + P["y_mean"]
     return d[:, 0:6], d[:, 6:9], valid

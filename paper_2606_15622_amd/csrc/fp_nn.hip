@@ -810,6 +810,17 @@ extern "C" int fp_closure_nn_noalloc(fp_ctx* c, const fp_nn* n, const double* mo
     return closure_nn(c, n, mom, rec, status, tol_abs, tol_rel, relax, y, "fp_closure_nn_noalloc", s);
 }
 
+extern "C" int fp_nn_infer(fp_ctx* c, const fp_nn* n, const double* mom, float* y, hipStream_t s) {
+    if (!c || !n || !mom || !y || n->ctx != c) return set_err(c, FP_EINVAL, "fp_nn_infer: bad argument");
+    if (c->ncell == 0) return FP_OK;
+    const int32_t ntiles = (c->ncell + 31) / 32;
+    int grid = (ntiles + NN_BLOCK / 64 - 1) / (NN_BLOCK / 64);
+    if (grid > 256) grid = 256;
+    hipLaunchKernelGGL(nn_infer_kernel, dim3(grid), dim3(NN_BLOCK), 0, s, c->ncell, mom, c->cfg.eps_hat,
+                       (const __bf16*)n->img, (const float*)n->sec, y);
+    return check_launch(c, "fp_nn_infer");
+}
+
 extern "C" int fp_nn_sensitivity(fp_ctx* c, const fp_nn* n, const double* mom, int32_t npass,
                                  double p, uint64_t seed, double* sens, hipStream_t s) {
     if (!c || !n || !mom || !sens || n->ctx != c || npass < 1 || !(p >= 0.0 && p < 1.0))

@@ -23,6 +23,7 @@ FP_EXACT, FP_PAPER = 0, 1
 STEP_COLLIDE, STEP_MOVE, STEP_KEYS, STEP_ADVANCE = 1, 2, 4, 8
 MOM_STRIDE, REC_STRIDE, SAMP_STRIDE, DIAG_STRIDE = 32, 16, 16, 24
 NN_PARAMS, NN_TRAIN, NN_FEATURES, NN_OUTPUTS = 39408, 39312, 32, 16
+LITE_PARAMS, LITE_TRAIN, LITE_FEATURES = 205904, 205840, 16
 LOSS_MSE, LOSS_RESIDUAL = 0, 1
 
 
@@ -98,6 +99,7 @@ def load():
         L.fp_closure_nn_noalloc.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                             vp]
         L.fp_nn_outputs.argtypes = [vp, vp, vp, vp]
+        L.fp_nn_infer.argtypes = [vp, vp, vp, vp, vp]
         L.fp_nn_sensitivity.argtypes = [vp, vp, vp, i32, C.c_double, u64, vp, vp]
         L.fp_sample_high.argtypes = [vp, vp, vp, vp]
         L.fp_high_order.argtypes = [vp, vp, vp, vp]
@@ -117,15 +119,29 @@ def load():
         L.fp_nn_train_step.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float, vp, vp, vp, i64, i32,
                                        vp, vp]
         L.fp_nn_targets.argtypes = [vp, vp, i64, vp, vp]
+        L.fp_column_stats.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+        L.fp_lite_create.argtypes = [vp, i64, P(vp)]
+        L.fp_lite_destroy.argtypes = [vp]
+        L.fp_lite_load.argtypes = [vp, vp, vp, vp]
+        L.fp_lite_infer.argtypes = [vp, vp, vp, vp, vp]
+        L.fp_closure_lite.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, vp]
+        L.fp_lite_features.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.fp_lite_targets.argtypes = [vp, vp, i64, vp, vp]
+        L.fp_lite_grad.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp]
+        L.fp_lite_adam.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float, vp]
+        L.fp_lite_train_step.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float, vp, vp, i64, vp, vp]
         L.fp_closure_solve_backward.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fp_moments_backward.argtypes = [vp, P(FPParticles), vp, vp, vp, vp, vp, vp, vp]
         for f in ("fp_bin", "fp_rebin", "fp_moments", "fp_closure_solve", "fp_step", "fp_sample", "fp_nn_create",
-                  "fp_nn_load", "fp_closure_nn", "fp_closure_nn_noalloc", "fp_nn_outputs", "fp_nn_sensitivity", "fp_nn_features",
+                  "fp_nn_load", "fp_closure_nn", "fp_closure_nn_noalloc", "fp_nn_outputs", "fp_nn_infer", "fp_nn_sensitivity", "fp_nn_features",
                   "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
                   "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
                   "fp_inject", "fp_inject_dev", "fp_cell_volumes", "fp_step_dev", "fp_counter_add", "fp_diagnostics",
                   "fp_amr_init", "fp_amr_adapt", "fp_amr_tree", "fp_wall_sampling",
-                  "fp_surface_coefficients", "fp_sample_high", "fp_high_order"):
+                  "fp_surface_coefficients", "fp_sample_high", "fp_high_order", "fp_lite_create",
+                  "fp_lite_load", "fp_lite_infer", "fp_closure_lite", "fp_lite_features",
+                  "fp_lite_targets", "fp_lite_grad", "fp_lite_adam", "fp_lite_train_step",
+                  "fp_column_stats"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -400,6 +416,23 @@ class Context:
                                                  _ptr(mombar), _ptr(gx), _ptr(gy), _ptr(gz),
                                                  _stream(stream)), "fp_moments_backward")
 
+    def column_stats(self, x, mean, std, stream=None):
+        n, k = x.shape
+        self._check(self.lib.fp_column_stats(self.h, _ptr(x), int(n), int(k), _ptr(mean), _ptr(std),
+                                             _stream(stream)), "fp_column_stats")
+
+    def lite_features(self, mom, n, feats, nvol=None, stream=None):
+        self._check(self.lib.fp_lite_features(self.h, _ptr(mom), _ptr(nvol), int(n), _ptr(feats),
+                                              _stream(stream)), "fp_lite_features")
+
+    def lite_targets(self, rec, n, targets, stream=None):
+        self._check(self.lib.fp_lite_targets(self.h, _ptr(rec), int(n), _ptr(targets), _stream(stream)),
+                    "fp_lite_targets")
+
+    def lite_adam(self, params, grad, m, v, t, lr, stream=None):
+        self._check(self.lib.fp_lite_adam(self.h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t),
+                                          float(lr), _stream(stream)), "fp_lite_adam")
+
     def nn_adam(self, params, grad, m, v, t, lr, stream=None):
         self._check(self.lib.fp_nn_adam(self.h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t),
                                         float(lr), _stream(stream)), "fp_nn_adam")
@@ -546,6 +579,10 @@ class Network:
         c = self.ctx
         c._check(c.lib.fp_nn_outputs(c.h, self.h, _ptr(y), _stream(stream)), "fp_nn_outputs")
 
+    def infer(self, mom, y, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_nn_infer(c.h, self.h, _ptr(mom), _ptr(y), _stream(stream)), "fp_nn_infer")
+
     def grad(self, params, feats, targets, sys, B, loss_kind, grad, loss, stream=None):
         c = self.ctx
         c._check(c.lib.fp_nn_grad(c.h, self.h, _ptr(params), _ptr(feats), _ptr(targets), _ptr(sys),
@@ -557,6 +594,55 @@ class Network:
         c._check(c.lib.fp_nn_train_step(c.h, self.h, _ptr(params), _ptr(m), _ptr(v), int(t),
                                         float(lr), _ptr(feats), _ptr(targets), _ptr(sys), int(B),
                                         int(loss_kind), _ptr(loss), _stream(stream)), "fp_nn_train_step")
+
+
+class LiteNetwork:
+    """An fp_lite handle: the paper's 16-256x4-9 ReLU surrogate (BF16 image for inference
+    plus training scratch)."""
+
+    def __init__(self, ctx: Context, max_batch: int = 0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        rc = ctx.lib.fp_lite_create(ctx.h, int(max_batch), C.byref(h))
+        if rc != FP_OK:
+            raise RuntimeError(f"fp_lite_create failed ({rc})")
+        self.h = h
+        self.max_batch = int(max_batch)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.fp_lite_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, params, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_lite_load(c.h, self.h, _ptr(params), _stream(stream)), "fp_lite_load")
+
+    def infer(self, mom, y, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_lite_infer(c.h, self.h, _ptr(mom), _ptr(y), _stream(stream)), "fp_lite_infer")
+
+    def closure(self, mom, rec, status, tol_abs, tol_rel, relax=1.0, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_closure_lite(c.h, self.h, _ptr(mom), _ptr(rec), _ptr(status), float(tol_abs),
+                                       float(tol_rel), float(relax), _stream(stream)), "fp_closure_lite")
+
+    def grad(self, params, feats, targets, B, grad, loss, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_lite_grad(c.h, self.h, _ptr(params), _ptr(feats), _ptr(targets), int(B),
+                                    _ptr(grad), _ptr(loss), _stream(stream)), "fp_lite_grad")
+
+    def train_step(self, params, m, v, t, lr, feats, targets, B, loss, stream=None):
+        c = self.ctx
+        c._check(c.lib.fp_lite_train_step(c.h, self.h, _ptr(params), _ptr(m), _ptr(v), int(t), float(lr),
+                                          _ptr(feats), _ptr(targets), int(B), _ptr(loss), _stream(stream)),
+                 "fp_lite_train_step")
 
 
 class Simulation:
@@ -578,6 +664,8 @@ class Simulation:
         self.rec = torch.zeros((nc, REC_STRIDE), dtype=torch.float64, device=device)
         self.status = torch.zeros(nc, dtype=torch.int32, device=device)
         self.samp = torch.zeros((nc, SAMP_STRIDE), dtype=torch.float64, device=device)
+        # the closure of the step: None = the exact closure, or a callable(mom, rec, status)
+        self.closure_fn = None
         if "key" not in state:
             self.ctx.step(self.a, None, None, None, 0, STEP_KEYS)
 
@@ -585,6 +673,12 @@ class Simulation:
     def offsets(self):
         """Cell start indices of the particles in a (after the last sort)."""
         return self.offs[0]
+
+    def closure(self):
+        if self.closure_fn is None:
+            self.ctx.closure_solve(self.mom, self.rec, self.status)
+        else:
+            self.closure_fn(self.mom, self.rec, self.status)
 
     def sort(self, perm=None, mom=None, samp=None):
         """a -> b sorted by key (fp_rebin from the previous grouping after the first
@@ -606,7 +700,7 @@ class Simulation:
 
     def step(self, s, sample=False):
         self.sort(mom=self.mom, samp=self.samp if sample else None)
-        self.ctx.closure_solve(self.mom, self.rec, self.status)
+        self.closure()
         self.ctx.step(self.a, self.offsets, self.mom, self.rec, s, STEP_COLLIDE | STEP_MOVE)
 
     def run(self, step0, nsteps, n_skip=None):
@@ -629,7 +723,7 @@ class GraphSimulation(Simulation):
     def _body(self, sample):
         for _ in range(2):
             self.sort(mom=self.mom, samp=self.samp if sample else None)
-            self.ctx.closure_solve(self.mom, self.rec, self.status)
+            self.closure()
             self.ctx.step_dev(self.a, self.offsets, self.mom, self.rec, self.step_ctr,
                               STEP_COLLIDE | STEP_MOVE | STEP_ADVANCE)
 

@@ -84,7 +84,10 @@ def test_inference_matches_bf16_oracle():
     net.closure(md, rec, st, 1e30, 0.0)
     y = torch.zeros((nc, 16), dtype=torch.float32, device="cuda")
     net.outputs(y)
+    y2 = torch.full((nc, 16), 7.0, dtype=torch.float32, device="cuda")
+    net.infer(md, y2)                   # the network kernel alone: the same outputs
     torch.cuda.synchronize()
+    assert torch.equal(y, y2)
     yg = y.double().cpu().numpy()
     p32 = M.unpack(pflat.astype(np.float64))
     xs = (M.features(mom, 0.01) - p32["x_mean"]) / p32["x_std"]
