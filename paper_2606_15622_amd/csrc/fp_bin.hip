@@ -163,9 +163,12 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_final_kernel(
 }
 
 // ---- per-cell ordering of contributions and gather --------------------------------------
+// the general sort's gather runs one wave per workgroup (GBLK lanes; one cell of 64 lanes
+// or 64 / G cells): its barriers wait for the wave itself, never for other cells
 template <int G>
 struct GatherShape {
-    static constexpr int GROUPS = BIN_BLOCK / G;
+    static constexpr int BLK = G > 64 ? G : 64;
+    static constexpr int GROUPS = BLK / G;
     static constexpr int CAPC = 6 * G;   // contributions per cell held in LDS
 };
 
@@ -193,7 +196,7 @@ __device__ __forceinline__ int select_bit(uint64_t m, int r) {
 }
 
 template <typename T, int G>
-__global__ __launch_bounds__(BIN_BLOCK) void bin_gather_kernel(
+__global__ __launch_bounds__(GatherShape<G>::BLK) void bin_gather_kernel(
     int32_t ncell, const int32_t* __restrict__ offsets, const int32_t* __restrict__ coff,
     const int32_t* __restrict__ cwave, const uint64_t* __restrict__ cmask,
     int32_t* __restrict__ cnt, int32_t* __restrict__ ccnt, int32_t* __restrict__ ccur,
@@ -209,8 +212,8 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_gather_kernel(
     __shared__ uint64_t s_m[S::GROUPS][S::CAPC];
 
     // counters of the count and place passes are spent: leave them zero for the next call
-    for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i <= ncell;
-         i += (int64_t)gridDim.x * BIN_BLOCK) {
+    for (int64_t i = (int64_t)blockIdx.x * S::BLK + threadIdx.x; i <= ncell;
+         i += (int64_t)gridDim.x * S::BLK) {
         cnt[i] = 0;
         ccnt[i] = 0;
         ccur[i] = 0;
@@ -297,7 +300,7 @@ static void gather_launch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
     const int groups = GatherShape<G>::GROUPS;
     const int grid = (c->ncell + groups - 1) / groups;
     const bool two_d = c->cfg.geometry != FP_COUETTE1D;
-    hipLaunchKernelGGL((bin_gather_kernel<T, G>), dim3(grid), dim3(BIN_BLOCK), 0, s, c->ncell,
+    hipLaunchKernelGGL((bin_gather_kernel<T, G>), dim3(grid), dim3(GatherShape<G>::BLK), 0, s, c->ncell,
                        offsets, c->coff, c->cwave, c->cmask, c->cnt, c->ccnt, c->ccur, c->gidx,
                        (const T*)src->x,
                        two_d ? (const T*)src->y : (const T*)nullptr, (const T*)src->vx,
@@ -835,11 +838,14 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_kernel(
 // quantities fp_moments computes from the sorted particles): the group has just written
 // every particle of its cell.  In this form the group also places its own far arrivals
 // (no separate far blocks) and then reads its fresh slots back (L1/L2-resident) for the
-// two moment passes.
+// two moment passes.  Its workgroups are one wave (GM_BLOCK lanes, 64 / G cells, or one
+// cell of 64 lanes): the group's barriers (far staging, bucket prefix, slot read-back, the
+// moment reduction in LDS) then wait for the wave itself and never for other cells.
 constexpr int GM_U = 4;
+constexpr int GM_BLOCK = 64;
 
-template <typename T, int G, int NVX>
-__global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
+template <typename T, int G, int NVX, int BLK = GM_BLOCK>
+__global__ __launch_bounds__(BLK) void rebin_gather_mom_kernel(
     int32_t ncell, int32_t nx, int32_t ny, int64_t n, const int64_t* __restrict__ n_dev,
     int64_t* __restrict__ kept, int64_t cap,
     const int32_t* __restrict__ src_off, const int32_t* __restrict__ bend,
@@ -849,19 +855,20 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
     int32_t* __restrict__ farn, Rec<T> r, double* __restrict__ mom, double* __restrict__ samp) {
     if (n_dev) n = *n_dev;
     if (kept && blockIdx.x == 0 && threadIdx.x == 0) *kept = offsets[ncell];
-    constexpr int GROUPS = BIN_BLOCK / G;
+    constexpr int GROUPS = BLK / G;
     __shared__ int32_t s_run[GROUPS][9][4];   // start in bidx, length, far before, range start
     __shared__ int32_t s_pre[GROUPS][10];     // bucket starts in the cell's concatenation
-    __shared__ MomShared<BIN_BLOCK, G> sm;
+    __shared__ MomShared<BLK, G> sm;
     // far arrivals of a cell staged in LDS, up to FCAP of them (their ranks compare every
     // arrival with all others and with the nine source ranges), in the space of the
     // moment reduction, which is used only after the gather's last barrier: the
     // workgroup's LDS stays below 32 KB (five workgroups per CU)
-    constexpr int FCAP = 2048 / GROUPS;
+    constexpr int FCAP = (2048 / GROUPS) < (int)(sizeof(sm.red) / (sizeof(int32_t) * GROUPS))
+                             ? (2048 / GROUPS) : (int)(sizeof(sm.red) / (sizeof(int32_t) * GROUPS));
     static_assert(sizeof(int32_t) * GROUPS * FCAP <= sizeof(sm.red), "far staging space");
     int32_t(*s_far)[FCAP] = reinterpret_cast<int32_t(*)[FCAP]>(&sm.red[0][0]);
-    for (int64_t i = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; i <= ncell;
-         i += (int64_t)gridDim.x * BIN_BLOCK) {
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i <= ncell;
+         i += (int64_t)gridDim.x * BLK) {
         cnt[i] = 0;
         fcnt[i] = 0;
         fcur[i] = 0;
@@ -1046,14 +1053,14 @@ __global__ __launch_bounds__(BIN_BLOCK) void rebin_gather_mom_kernel(
             mom_accum<NVX>((double)r.dvx[base + q] - U0, (double)r.dvy[base + q] - U1,
                            (double)r.dvz[base + q] - U2, acc);
     }
-    mom_finish<BIN_BLOCK, G, NVX>(sm, acc, grp, lg, in, ncnt, U0, U1, U2,
+    mom_finish<BLK, G, NVX>(sm, acc, grp, lg, in, ncnt, U0, U1, U2,
                              mom + (int64_t)(in ? k : 0) * MOM);
     if (samp && in && lg == 0) {
         // time-average sums from the record's entries, rebuilt from the final sums in LDS
         // (the values mom_finish stored) instead of reading the record back
         double m[M_T + 10];
 #pragma unroll
-        for (int e = 0; e < M_T + 10; ++e) m[e] = mom_entry<BIN_BLOCK, G, NVX>(sm, grp, ncnt, U0, U1, U2, e);
+        for (int e = 0; e < M_T + 10; ++e) m[e] = mom_entry<BLK, G, NVX>(sm, grp, ncnt, U0, U1, U2, e);
         sample_add(m, samp + (int64_t)k * SAMP);
     }
 }
@@ -1087,14 +1094,16 @@ static void rebin_gather_launch(fp_ctx* c, const fp_particles* src, const int32_
              dst->key,          perm};
     const int32_t cblocks = (nc + BIN_BLOCK / G - 1) / (BIN_BLOCK / G);
     if (mom) {
+        constexpr int BLK = G > GM_BLOCK ? G : GM_BLOCK;
+        const int32_t mblocks = (nc + BLK / G - 1) / (BLK / G);
         if (c->cfg.moment_order == 3)
-            hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G, NV_LOW>), dim3(cblocks), dim3(BIN_BLOCK), 0, s,
+            hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G, NV_LOW, BLK>), dim3(mblocks), dim3(BLK), 0, s,
                                nc, nx, ny, n, (const int64_t*)src->n_dev, dst->n_dev, cap, src_off,
                                (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
                                (const int32_t*)offsets, (const int32_t*)c->coff, (const int32_t*)c->gidx,
                                c->cnt, c->ccnt, c->ccur, c->farn, r, mom, samp);
         else
-            hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G, NV>), dim3(cblocks), dim3(BIN_BLOCK), 0, s,
+            hipLaunchKernelGGL((rebin_gather_mom_kernel<T, G, NV, BLK>), dim3(mblocks), dim3(BLK), 0, s,
                                nc, nx, ny, n, (const int64_t*)src->n_dev, dst->n_dev, cap, src_off,
                                (const int32_t*)c->ncnt, (const int32_t*)c->bidx,
                                (const int32_t*)offsets, (const int32_t*)c->coff, (const int32_t*)c->gidx,
