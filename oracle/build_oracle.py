@@ -1,7 +1,8 @@
 """Build the C oracle into ``oracle/libfporacle.so`` (test infrastructure only).
 
 Plain gcc, -O2, no fast-math and no floating-point contraction, so every product and
-sum is a separately rounded IEEE double operation.
+sum is a separately rounded IEEE double operation; OpenMP for the loops whose outputs
+belong to one iteration each (results independent of the thread count).
 """
 import os
 import subprocess
@@ -14,7 +15,7 @@ LIB = os.path.join(HERE, "libfporacle.so")
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "fp_oracle.c")
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", LIB + ".tmp", src, "-lm"]
+           "-fno-fast-math", "-fopenmp", "-Wall", "-o", LIB + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

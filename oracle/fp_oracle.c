@@ -17,13 +17,31 @@
  *   or_update         eqs. update_vel, update_N, update_alpha
  *   or_move           eq. update_pos with diffuse isothermal walls
  *   or_run            the order of Algorithm "Baseline Physics Simulation Loop"
- * Plain loops, no blocking or fusion; sums run in particle order.
+ * Plain loops, no blocking or fusion; sums run in particle order.  Loops whose every
+ * output belongs to one iteration (a cell, a particle) may be split across threads
+ * (OpenMP); the arithmetic of each output is unchanged, so no result depends on the
+ * number of threads.
  */
 #include "fp_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* threads of the parallel loops (n <= 0: the OpenMP default); returns the count in use */
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 #define OR_PI 3.14159265358979323846
 
@@ -88,6 +106,7 @@ void or_keys(const or_config* cfg, int64_t n, const double* x, const double* y, 
 {
     double inv_dx = 1.0 / cfg->dx;
     double inv_dy = 1.0 / cfg->dy;
+    #pragma omp parallel for schedule(static) if (n > 4096)
     for (int64_t p = 0; p < n; ++p) {
         int32_t kx = axis_index(x[p], cfg->x0, inv_dx, cfg->nx);
         int32_t ky = 0;
@@ -141,6 +160,7 @@ enum { M_N = 0, M_U = 1, M_TH = 4, M_P = 5, M_T = 11, M_R = 21, M_W = 27, M_H = 
 void or_moments(int32_t ncell, const int32_t* offsets, const double* vx, const double* vy,
                 const double* vz, double* mom)
 {
+    #pragma omp parallel for schedule(dynamic, 16) if (ncell > 64)
     for (int32_t cell = 0; cell < ncell; ++cell) {
         double* m = mom + (int64_t)cell * OR_MOM_STRIDE;
         for (int i = 0; i < OR_MOM_STRIDE; ++i) m[i] = 0.0;
@@ -277,6 +297,7 @@ static int solve9(double* A, double* b, double* y, double tol)
 void or_closure(const or_config* cfg, int32_t ncell, const double* mom, const double* nvol,
                 double* rec, int32_t* status)
 {
+    #pragma omp parallel for schedule(dynamic, 16) if (ncell > 64)
     for (int32_t cell = 0; cell < ncell; ++cell) {
         const double* m = mom + (int64_t)cell * OR_MOM_STRIDE;
         double* r = rec + (int64_t)cell * OR_REC_STRIDE;
@@ -435,6 +456,7 @@ void or_update(const or_config* cfg, int32_t ncell, const int32_t* offsets, doub
 {
     int64_t n = offsets[ncell];
     double* cs = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    #pragma omp parallel for schedule(dynamic, 16) if (ncell > 64)
     for (int32_t cell = 0; cell < ncell; ++cell) {
         const double* m = mom + (int64_t)cell * OR_MOM_STRIDE;
         const double* r = rec + (int64_t)cell * OR_REC_STRIDE;
@@ -651,6 +673,7 @@ void or_move_wall(const or_config* cfg, int64_t n, double* x, double* y, double*
     int two_d = (cfg->geometry == OR_CAVITY2D);
     double lo[2] = {cfg->x0, cfg->y0};
     double hi[2] = {cfg->x0 + cfg->lx, cfg->y0 + cfg->ly};
+#pragma omp parallel for schedule(static) if (n > 4096)
     for (int64_t p = 0; p < n; ++p) {
         double pos[2] = {x[p], two_d ? y[p] : 0.0};
         double v[3] = {vx[p], vy[p], vz[p]};
@@ -756,6 +779,7 @@ int64_t or_inject(const or_config* cfg, uint32_t step, uint32_t* pid_next, int64
 void or_sample(int32_t ncell, const int32_t* offsets, const double* vx, const double* vy,
                const double* vz, double* samp)
 {
+    #pragma omp parallel for schedule(dynamic, 16) if (ncell > 64)
     for (int32_t cell = 0; cell < ncell; ++cell) {
         double* s = samp + (int64_t)cell * OR_SAMP_STRIDE;
         for (int32_t p = offsets[cell]; p < offsets[cell + 1]; ++p) {
@@ -774,6 +798,7 @@ void or_sample(int32_t ncell, const int32_t* offsets, const double* vx, const do
 /* ------------------------------------------------------------------------------------ */
 static void permute_d(double* a, const int64_t* perm, int64_t n, double* tmp)
 {
+#pragma omp parallel for schedule(static) if (n > 4096)
     for (int64_t j = 0; j < n; ++j) tmp[j] = a[perm[j]];
     memcpy(a, tmp, sizeof(double) * (size_t)n);
 }

@@ -149,6 +149,10 @@ int or_run_open(const or_config* cfg, int64_t capacity, int64_t* n, double* x, d
                 uint32_t* pid_next, uint32_t step0, int32_t nsteps, uint32_t n_skip,
                 double* mom, double* rec, int32_t* status, double* samp);
 
+/* Threads of the loops split across threads (n <= 0 keeps the OpenMP default); returns
+ * the number in use (1 without OpenMP). */
+int or_set_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

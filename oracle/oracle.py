@@ -80,6 +80,8 @@ def _declare(L):
     L.or_move_wall.argtypes = [cfgp, i64, P(d), P(d), P(d), P(d), P(d), P(u32), P(i32), u32,
                                P(d), i32]
     L.or_sample.argtypes = [i32, P(i32), P(d), P(d), P(d), P(d)]
+    L.or_set_threads.argtypes = [C.c_int]
+    L.or_set_threads.restype = C.c_int
     L.or_run.argtypes = [cfgp, i64, P(d), P(d), P(d), P(d), P(d), P(u32), P(i32), u32, i32,
                          u32, P(d), P(d), P(i32), P(d)]
     L.or_run.restype = C.c_int
@@ -92,6 +94,11 @@ def _p(a, ctype):
 def _f64(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a
+
+
+def set_threads(n=0):
+    """Threads of the oracle's parallel loops (0: the OpenMP default); returns the count."""
+    return int(lib().or_set_threads(int(n)))
 
 
 def make_config(w: dict) -> OrConfig:

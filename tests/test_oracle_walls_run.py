@@ -87,3 +87,22 @@ def test_f32_storage_rounds_stored_values():
     out, _, _, _, _ = O.run(w, s, 0, 3)
     for k in ("x", "y", "vx", "vy", "vz"):
         np.testing.assert_array_equal(out[k], out[k].astype(np.float32).astype(np.float64))
+
+
+def test_oracle_results_do_not_depend_on_the_thread_count():
+    """The oracle's cell and particle loops may run on several threads; every output
+    belongs to one iteration, so one thread and four give the same bits."""
+    w = I.cavity(kn=0.5, ncell=30, ppc=80, precision="f32", seed=4, lid=200.0)
+    s = I.maxwellian_state(w)
+    s["key"] = O.keys(w, s["x"], s["y"])
+    outs = []
+    for nt in (1, 4):
+        O.set_threads(nt)
+        outs.append(O.run(w, s, 0, 6, n_skip=0))
+    O.set_threads(0)
+    for a, b in zip(outs[0], outs[1]):
+        if isinstance(a, dict):
+            for k in a:
+                np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+        else:
+            np.testing.assert_array_equal(a, b)
