@@ -1,24 +1,29 @@
 """Learned closure pipeline on one GPU (the surrogate of Secs. "Phase 0"-"Phase 3").
 
-LITE (Sec. "Phase 3", step 2): moments through third order only, the network
-unchecked (LearnedSimulation(lite=True)), optionally the Gamma block weighted in the
-loss (fit_scalers(gamma_weight); Sec. "Case Study 2: 2D Lid-Driven Cavity") and the
-coefficients under-relaxed in time (relax; Sec. "Extension to External Aerodynamics").
+Two networks: the 27-feature closure network on theta-normalised moments (checked against
+the cell's own 9x9 system, exact fallback) and the paper's LITE network (16 low-order
+inputs, 16-256x4-9 ReLU; moments through third order only, the high-order gather skipped,
+unchecked: LearnedSimulation(lite_params=...)), optionally with the Gamma block weighted
+in the loss (the q-weighted loss of Sec. "Case Study 2: 2D Lid-Driven Cavity", realised by
+the target scaler) and the coefficients under-relaxed in time (relax; Sec. "Extension to
+External Aerodynamics").
 
 harvest()      runs the exact-closure loop and keeps the moment records of solved cells
                (the paper's Phase 0 saves the physics solver's inputs and outputs);
 dataset()      features, targets and normalised systems by the library's kernels;
-fit_scalers()  per-column mean and standard deviation (the paper's StandardScaler);
+fit_scalers()  per-column mean and standard deviation (the paper's StandardScaler) by
+               the library's column-statistics kernel;
 train()        Adam on the MSE of standardised targets (or the closure residual) with a
                random 10 % split used only for early stopping (patience) and keeping the
                best parameters (the paper's EarlyStopping / ModelCheckpoint);
 LearnedSimulation  the loop of Algorithm "Accelerated ML Simulation Loop": the exact
                build+solve replaced by fp_closure_nn, with the per-cell residual check
                falling back to the exact solve on the device.
-Every arithmetic step runs in libfpgpu kernels; torch provides buffers, index
-shuffles and the scaler statistics.
+Every arithmetic step runs in libfpgpu kernels; torch provides buffers and index
+shuffles, and the host adjusts the 32 scaler values (floors, the Gamma weight).
 """
 import math
+import time
 
 import numpy as np
 import torch
@@ -27,6 +32,12 @@ from . import fpgpu as F
 
 NF, NO = F.NN_FEATURES, F.NN_OUTPUTS
 LOW_END = 21   # moment record entries of a third-order gather: N, U, theta, P, T
+
+
+def _stats_workload():
+    from . import inputs as I
+    return I.couette(ncell=1)
+
 
 
 def harvest(w, state, n_transient, n_samples, every=1, seed_offset=0):
@@ -74,21 +85,72 @@ def dataset(w, mom, lite=False):
     return feats[ok].contiguous(), tg[ok].contiguous(), sys[ok].contiguous()
 
 
-def fit_scalers(feats, tg, gamma_weight=1.0):
-    """Standardising scalers.  gamma_weight > 1 gives the heat-flux block Gamma that
-    weight in the MSE of standardised targets (the q-weighted loss): dividing its target
-    scale by sqrt(gamma_weight) multiplies its standardised errors by that factor, for
-    every batch and with no change to the loss kernels."""
-    xm = feats.double().mean(0)
-    xs = feats.double().std(0)
-    ym = tg.double().mean(0)
-    ys = tg.double().std(0)
-    xs = torch.where(xs > 1e-6, xs, torch.ones_like(xs))
-    ys = torch.where(ys > 1e-9, ys, torch.ones_like(ys))
+def column_stats(x):
+    """Per-column mean and population standard deviation of a device matrix (numpy FP64),
+    by the library's kernel."""
+    ctx = F.Context(_stats_workload(), 1)
+    mean = torch.zeros(x.shape[1], dtype=torch.float64, device=x.device)
+    std = torch.zeros_like(mean)
+    ctx.column_stats(x.contiguous(), mean, std)
+    return mean.cpu().numpy(), std.cpu().numpy()
+
+
+def scalers_from_stats(xm, xs, ym, ys, gamma_weight=1.0, n_out=9):
+    """The standardising scalers from column statistics (host arithmetic on at most 32
+    numbers): floors for constant columns, padding outputs mapped to identity, and the
+    q-weighted loss: dividing the Gamma block's scale by sqrt(gamma_weight) multiplies its
+    standardised errors by that factor, for every batch and with no change to the loss
+    kernels."""
+    xm, xs = np.array(xm, dtype=np.float64), np.array(xs, dtype=np.float64)
+    ym, ys = np.array(ym, dtype=np.float64), np.array(ys, dtype=np.float64)
+    xs = np.where(xs > 1e-6 * np.maximum(np.abs(xm), 1.0), xs, 1.0)
+    ys = np.where(ys > 0.0, ys, 1.0)
     ys[6:9] = ys[6:9] / math.sqrt(gamma_weight)
-    ym[9:] = 0.0
-    ys[9:] = 1.0
-    return xm.float(), xs.float(), ym.float(), ys.float()
+    ym[n_out:] = 0.0
+    ys[n_out:] = 1.0
+    return tuple(torch.tensor(v, dtype=torch.float32) for v in (xm, xs, ym, ys))
+
+
+def fit_scalers(feats, tg, gamma_weight=1.0):
+    """Standardising scalers of a training set (device matrices): column statistics by
+    the library's kernel, then scalers_from_stats."""
+    xm, xs = column_stats(feats)
+    ym, ys = column_stats(tg)
+    return scalers_from_stats(xm, xs, ym, ys, gamma_weight)
+
+
+def lite_dataset(w, mom, nvol=None):
+    """(feats [n][16] f32, targets [n][16] f32) of the LITE network from full moment records
+    (the targets come from the exact closure of the full records; the inputs use only their
+    first, low-order entries)."""
+    n = mom.shape[0]
+    wd = dict(w)
+    wd.update(geometry="couette1d", nx=n, ny=1, lx=float(w["dx"]) * n, ly=1.0, dy=1.0)
+    ctx = F.Context(wd, 1)
+    rec = torch.zeros((n, F.REC_STRIDE), dtype=torch.float64, device=mom.device)
+    st = torch.zeros(n, dtype=torch.int32, device=mom.device)
+    ctx.closure_solve(mom, rec, st)
+    feats = torch.zeros((n, F.LITE_FEATURES), dtype=torch.float32, device=mom.device)
+    tg = torch.zeros((n, NO), dtype=torch.float32, device=mom.device)
+    ctx.lite_features(mom, n, feats, nvol)
+    ctx.lite_targets(rec, n, tg)
+    ok = st == F.CELL_OK
+    return feats[ok].contiguous(), tg[ok].contiguous()
+
+
+def init_lite_params(scalers, seed=0, device="cuda"):
+    """Glorot-uniform weights (the Keras default), zero biases, then the scalers (flat
+    layout of the LITE network in fp.h); the padded output rows 9..15 stay zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((256, 16), (256, 256), (256, 256), (256, 256), (16, 256)):
+        lim = math.sqrt(6.0 / (fan_in + (9 if fan_out == 16 else fan_out)))
+        Wm = rng.uniform(-lim, lim, (fan_out, fan_in))
+        if fan_out == 16:
+            Wm[9:, :] = 0.0
+        parts += [Wm.ravel(), np.zeros(fan_out)]
+    p = torch.tensor(np.concatenate(parts), dtype=torch.float32, device=device)
+    return torch.cat([p] + [t.to(device) for t in scalers])
 
 
 def init_params(scalers, seed=0, device="cuda"):
@@ -108,8 +170,9 @@ def init_params(scalers, seed=0, device="cuda"):
 
 
 def train(w, params, feats, tg, sys=None, loss_kind=F.LOSS_MSE, epochs=100, batch=4096,
-          lr=1e-4, patience=10, val_frac=0.1, seed=0, log=None):
-    """Adam training by the library's MFMA kernels; returns (best params, history)."""
+          lr=1e-4, patience=10, val_frac=0.1, seed=0, log=None, lite=False):
+    """Adam training by the library's MFMA kernels (the 27-feature network, or the LITE
+    network with lite=True: MSE only); returns (best params, history)."""
     dev = feats.device
     n = feats.shape[0]
     g = torch.Generator(device="cpu").manual_seed(seed)
@@ -117,11 +180,28 @@ def train(w, params, feats, tg, sys=None, loss_kind=F.LOSS_MSE, epochs=100, batc
     nval = max(int(n * val_frac), 1)
     vi, ti = perm[:nval], perm[nval:]
     ctx = F.Context(dict(w, geometry="couette1d", nx=1, ny=1), 1)
-    net = F.Network(ctx, max(batch, nval))
+    if lite:
+        net = F.LiteNetwork(ctx, max(batch, nval))
+        nparams = F.LITE_PARAMS
+
+        def step(t, fe, tgb, syb, nb, loss):
+            net.train_step(params, m, v, t, lr, fe, tgb, nb, loss)
+
+        def vgrad(fe, tgb, syb, nb, grad, loss):
+            net.grad(params, fe, tgb, nb, grad, loss)
+    else:
+        net = F.Network(ctx, max(batch, nval))
+        nparams = F.NN_PARAMS
+
+        def step(t, fe, tgb, syb, nb, loss):
+            net.train_step(params, m, v, t, lr, fe, tgb, syb, nb, loss_kind, loss)
+
+        def vgrad(fe, tgb, syb, nb, grad, loss):
+            net.grad(params, fe, tgb, syb, nb, loss_kind, grad, loss)
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
-    grad = torch.zeros(F.NN_PARAMS, dtype=torch.float32, device=dev)
+    grad = torch.zeros(nparams, dtype=torch.float32, device=dev)
     vfe, vtg = feats[vi].contiguous(), tg[vi].contiguous()
     vsy = sys[vi].contiguous() if sys is not None else None
     best, best_p, bad, t = float("inf"), params.clone(), 0, 0
@@ -131,10 +211,9 @@ def train(w, params, feats, tg, sys=None, loss_kind=F.LOSS_MSE, epochs=100, batc
         for b0 in range(0, order.shape[0], batch):
             idx = order[b0:b0 + batch]
             t += 1
-            net.train_step(params, m, v, t, lr, feats[idx].contiguous(), tg[idx].contiguous(),
-                           sys[idx].contiguous() if sys is not None else None, idx.shape[0],
-                           loss_kind, loss)
-        net.grad(params, vfe, vtg, vsy, nval, loss_kind, grad, loss)
+            step(t, feats[idx].contiguous(), tg[idx].contiguous(),
+                 sys[idx].contiguous() if sys is not None else None, idx.shape[0], loss)
+        vgrad(vfe, vtg, vsy, nval, grad, loss)
         vl = float(loss)
         hist.append(vl)
         if log:
@@ -148,35 +227,34 @@ def train(w, params, feats, tg, sys=None, loss_kind=F.LOSS_MSE, epochs=100, batc
     return best_p, hist
 
 
-class LearnedSimulation(F.Simulation):
-    """The loop with the learned closure (or the Langevin drift when net is None and
-    langevin is set), everything else as in Simulation."""
+class LearnedSimulation(F.GraphSimulation):
+    """The loop with a learned closure (the 27-feature network with params, the paper's
+    LITE network with lite_params) or the Langevin drift (langevin), everything else as in
+    Simulation; the step can be captured in a HIP graph (run_pairs) like the exact loop's."""
 
     def __init__(self, w, state, params=None, tol_abs=0.05, tol_rel=0.05, langevin=False,
-                 lite=False, relax=1.0, device="cuda"):
+                 lite=False, relax=1.0, lite_params=None, step0=0, device="cuda"):
         """lite: moments through third order only (the high-order gather skipped) and the
-        network unchecked (there is no system to check against); relax: temporal
-        under-relaxation of the network's coefficients."""
+        network unchecked (there is no system to check against); it is implied by
+        lite_params.  relax: temporal under-relaxation of the network's coefficients."""
         if langevin:
             w = dict(w, n_min=1 << 30)
-        if lite:
+        if lite or lite_params is not None:
             w = dict(w, moment_order=3)
             tol_abs, tol_rel = math.inf, 0.0
-        super().__init__(w, state, device)
+        super().__init__(w, state, step0=step0, device=device)
         self.net = None
-        if params is not None:
+        if lite_params is not None:
+            self.net = F.LiteNetwork(self.ctx, 0)
+            self.net.load(lite_params)
+        elif params is not None:
             self.net = F.Network(self.ctx, 0)
             self.net.load(params)
         self.tol = (tol_abs, tol_rel, relax)
         self.rec[:, 14] = float(F.CELL_EMPTY)   # no previous coefficients to relax towards
-
-    def step(self, s, sample=False):
-        self.sort(mom=self.mom, samp=self.samp if sample else None)
         if self.net is not None:
-            self.net.closure(self.mom, self.rec, self.status, *self.tol)
-        else:
-            self.ctx.closure_solve(self.mom, self.rec, self.status)
-        self.ctx.step(self.a, self.offsets, self.mom, self.rec, s, F.STEP_COLLIDE | F.STEP_MOVE)
+            net, tol = self.net, self.tol
+            self.closure_fn = lambda mom, rec, st: net.closure(mom, rec, st, *tol)
 
 
 def fields(w, samp):
@@ -285,6 +363,169 @@ def finetune(w, params, mom, batch=200_000, epochs=20, lr=1e-4, seed=0, log=None
     feats, tg, sys = dataset(w, mom, lite=lite)
     return train(w, params, feats, tg, sys=sys, loss_kind=F.LOSS_RESIDUAL, epochs=epochs,
                  batch=batch, lr=lr, patience=epochs, seed=seed, log=log)
+
+
+def cavity_training_records(kn=0.15, lids=(50.0, 100.0, 200.0, 400.0, 600.0), n_transient=1000,
+                            n_samples=500, every=25, seed=100):
+    """Moment records of solved cells of 100 x 100 cavity runs (1e6 particles each) at one
+    Knudsen number and several lid speeds: the paper's cavity training conditions (Kn 0.15,
+    lids 50 to 600 m/s; Sec. "Case Study 2", Table cavity_train_test_conditions)."""
+    from . import inputs as I
+    moms = []
+    for i, lid in enumerate(lids):
+        w = I.cavity(kn=kn, ncell=100, ppc=100, precision="f32", seed=seed + i, lid=lid)
+        moms.append(harvest(w, I.maxwellian_state(w), n_transient, n_samples, every=every))
+    return torch.cat(moms, 0)
+
+
+def _events_ms(fn, reps):
+    """Mean duration (ms) of fn() by HIP events on the launch stream, after one warm call."""
+    fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def closure_batch_timings(w, mom, params, lite_params, ncells=1_000_000, reps=10):
+    """Closure kernels on a batch of ncells cavity moment records (repeated to size): the
+    exact closure, the checked and the unchecked 27-feature network, the LITE network
+    (unchecked), and the two networks' MFMA kernels alone (fp_nn_infer / fp_lite_infer);
+    mean times by HIP events, cell-closures/s, the checked network's fallback fraction."""
+    mom = mom.repeat(ncells // mom.shape[0] + 1, 1)[:ncells].contiguous()
+    n = mom.shape[0]
+    wd = dict(w, geometry="couette1d", nx=n, ny=1, lx=float(w["dx"]) * n, ly=1.0, dy=1.0)
+    ctx = F.Context(wd, 1)
+    net = F.Network(ctx, 0)
+    net.load(params)
+    lnet = F.LiteNetwork(ctx, 0)
+    lnet.load(lite_params)
+    rec = torch.zeros((n, F.REC_STRIDE), dtype=torch.float64, device=mom.device)
+    st = torch.zeros(n, dtype=torch.int32, device=mom.device)
+    y = torch.zeros((n, NO), dtype=torch.float32, device=mom.device)
+    t = {
+        "exact": _events_ms(lambda: ctx.closure_solve(mom, rec, st), reps),
+        "learned_checked": _events_ms(lambda: net.closure(mom, rec, st, 0.05, 0.05), reps),
+    }
+    fb = float((st == F.CELL_NN_FALLBACK).sum().item()) / n
+    t["learned_unchecked"] = _events_ms(lambda: net.closure(mom, rec, st, math.inf, 0.0), reps)
+    t["lite_unchecked"] = _events_ms(lambda: lnet.closure(mom, rec, st, math.inf, 0.0), reps)
+    t["nn_infer"] = _events_ms(lambda: net.infer(mom, y), reps)
+    t["lite_infer"] = _events_ms(lambda: lnet.infer(mom, y), reps)
+    out = {"cells": n, "ms": {k: round(v, 4) for k, v in t.items()},
+           "cell_closures_per_s": {k: round(n / (v * 1e-3), 1) for k, v in t.items()},
+           "learned_checked_fallback_fraction": round(fb, 5)}
+    # MFMA work per cell (algorithmic, the padded shapes the kernels multiply):
+    # 27-feature network 2 (32 128 + 128 128 + 128 128 + 128 16) = 77,824 FLOP;
+    # LITE network 2 (16 256 + 3 256 256 + 256 16) = 409,600 FLOP
+    for k, flop in (("nn_infer", 77_824), ("lite_infer", 409_600)):
+        ach = flop * n / (t[k] * 1e-3) / 1e12
+        out[f"{k}_mfma"] = {"bound": "mfma", "flop_per_cell": flop, "achieved": round(ach, 1),
+                            "peak": 2500.0, "unit": "TFLOP/s", "frac": round(ach / 2500.0, 4)}
+    return out
+
+
+def loop_speeds(variants, steps=200, warmup=20, kn=1.0, lid=50.0, seed=1):
+    """particle-steps/s of the whole loop on the 100 x 100 cavity (1e6 particles) for each
+    closure variant, timed around HIP-graph replays of two captured steps."""
+    from . import inputs as I
+    out = {}
+    w = I.cavity(kn=kn, ncell=100, ppc=100, precision="f32", seed=seed, lid=lid)
+    for name, kw in variants:
+        sim = LearnedSimulation(w, I.maxwellian_state(w), step0=warmup, **kw)
+        for s in range(warmup):
+            sim.step(s, sample=True)
+        sim.run_pairs(1, sample=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run_pairs(steps // 2, sample=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[name] = {"particle_steps_per_s": round(1e6 * (steps // 2) * 2 / t, 1),
+                     "ms_per_step": round(t / ((steps // 2) * 2) * 1e3, 5)}
+        st = sim.status
+        nn = int((st == F.CELL_NN).sum())
+        fbk = int((st == F.CELL_NN_FALLBACK).sum())
+        if nn + fbk:
+            out[name]["fallback_fraction_last_step"] = round(fbk / (nn + fbk), 5)
+        del sim
+    return out
+
+
+def field_errors(variants, kn, lid, steps=5000, avg=2000, seed=1, floor_seed=2):
+    """Relative L2 (as the paper's field-error tables) of the time-averaged |U|, T, rho/rho0
+    and p/p0 of each closure variant against the exact closure with the same seed (common
+    random numbers), next to the exact closure with another seed (the noise floor).  Steps
+    by graph replay; the averaging window is the last `avg` steps."""
+    from . import inputs as I
+    w = I.cavity(kn=kn, ncell=100, ppc=100, precision="f32", seed=seed, lid=lid,
+                 n_steps=steps, n_skip=steps - avg)
+    runs = {}
+    cases = [("exact", seed, {}), ("exact_other_seed", floor_seed, {})] + \
+            [(name, seed, kw) for name, kw in variants]
+    for name, sd, kw in cases:
+        ww = dict(w, seed=sd)
+        sim = LearnedSimulation(ww, I.maxwellian_state(ww), **kw)
+        skip = steps - avg
+        for s in range(2):
+            sim.step(s, sample=False)
+        sim.step_ctr.fill_(2)
+        sim.run_pairs((skip - 2) // 2, sample=False)
+        sim.run_pairs(avg // 2, sample=True)
+        torch.cuda.synchronize()
+        runs[name] = fields(ww, sim.samp)
+        del sim
+    ref = runs["exact"]
+    return {name: {k: round(rel_l2(runs[name][k], ref[k]), 6) for k in ("U", "T", "rho", "p")}
+            for name in runs if name != "exact"}
+
+
+def benchmark(epochs=15, lite_epochs=10, accuracy_cases=((1.0, 800.0), (0.5, 800.0), (0.15, 800.0)),
+              log=None):
+    """The learned half of the metric on one GPU: both networks trained in the run by the
+    library's kernels on cavity records of the paper's training conditions (Kn 0.15, lids
+    50 to 600 m/s), then (1) in-loop speed on the 100 x 100 cavity at Kn 1.0 and 50 m/s for
+    the exact closure, the checked and the unchecked network, LITE and the Langevin drift;
+    (2) closure-kernel throughput and MFMA fraction on 1e6 cells; (3) field errors on the
+    held-out 800 m/s cavities against the exact closure and its seed-to-seed floor."""
+    from . import inputs as I
+    res = {}
+    t0 = time.perf_counter()
+    mom = cavity_training_records()
+    wc = I.cavity(kn=0.15, ncell=100, ppc=100, precision="f32")
+    feats, tg, sys = dataset(wc, mom)
+    lfeats, ltg = lite_dataset(wc, mom)
+    t1 = time.perf_counter()
+    p27, h27 = train(wc, init_params(fit_scalers(feats, tg), seed=0), feats, tg, epochs=epochs,
+                     lr=1e-3, patience=4, log=log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    plite, hl = train(wc, init_lite_params(fit_scalers(lfeats, ltg, gamma_weight=4.0), seed=1),
+                      lfeats, ltg, epochs=lite_epochs, lr=1e-3, patience=4, log=log, lite=True)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    res["training"] = {
+        "data": "cavity 100x100 (1e6 particles), Kn 0.15, lids 50/100/200/400/600 m/s, "
+                "records of solved cells every 25 steps after 1000",
+        "pairs": int(feats.shape[0]), "harvest_s": round(t1 - t0, 2),
+        "net27": {"epochs": len(h27), "best_val_loss": round(min(h27), 6), "train_s": round(t2 - t1, 2)},
+        "lite": {"epochs": len(hl), "best_val_loss": round(min(hl), 6), "train_s": round(t3 - t2, 2),
+                 "gamma_weight": 4.0}}
+    variants = [("learned_checked", {"params": p27, "tol_abs": 0.05, "tol_rel": 0.05}),
+                ("learned_unchecked", {"params": p27, "tol_abs": math.inf, "tol_rel": 0.0}),
+                ("lite", {"lite_params": plite}),
+                ("langevin", {"langevin": True})]
+    res["loop"] = loop_speeds([("exact", {})] + variants)
+    res["closure_batch"] = closure_batch_timings(wc, mom, p27, plite)
+    res["field_errors"] = {}
+    for kn, lid in accuracy_cases:
+        res["field_errors"][f"kn{kn}_lid{int(lid)}"] = field_errors(variants, kn, lid)
+    res["seconds"] = round(time.perf_counter() - t0, 1)
+    return res
 
 
 def main(argv=None):

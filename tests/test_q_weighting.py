@@ -2,7 +2,8 @@
 standardised targets, Sec. "Case Study 2: 2D Lid-Driven Cavity") is
 realised by the target scaler alone: dividing the Gamma block's scale by sqrt(w) makes
 the plain MSE of the re-standardised targets equal to the weighted MSE of the original
-ones, for any prediction.  Host-side check of that identity and of fit_scalers."""
+ones, for any prediction.  Host-side check of that identity and of scalers_from_stats
+(the column statistics themselves come from the library's kernel on the GPU)."""
 import math
 
 import numpy as np
@@ -17,8 +18,10 @@ def test_scaler_realises_the_weighted_mse():
     tg = torch.tensor(rng.standard_normal((500, 16)) * 3.0 + 1.0, dtype=torch.float32)
     tg[:, 9:] = 0.0
     w = 4.0
-    _, _, ym, ys = L.fit_scalers(feats, tg)
-    _, _, ymw, ysw = L.fit_scalers(feats, tg, gamma_weight=w)
+    xm, xs = feats.double().mean(0).numpy(), feats.double().std(0).numpy()
+    tm, ts = tg.double().mean(0).numpy(), tg.double().std(0).numpy()
+    _, _, ym, ys = L.scalers_from_stats(xm, xs, tm, ts)
+    _, _, ymw, ysw = L.scalers_from_stats(xm, xs, tm, ts, gamma_weight=w)
     np.testing.assert_allclose(ysw[6:9].numpy(), ys[6:9].numpy() / math.sqrt(w), rtol=1e-6)
     np.testing.assert_array_equal(ysw[:6].numpy(), ys[:6].numpy())
     np.testing.assert_array_equal(ymw.numpy(), ym.numpy())
