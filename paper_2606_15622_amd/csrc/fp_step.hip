@@ -313,7 +313,9 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
     const uint32_t step = stepp ? stepp[0] : step_arg;
     if (stepc && blockIdx.x == 0 && threadIdx.x == 0) stepc[0] = step;   // for flight_rest
     const int64_t gt = (int64_t)blockIdx.x * ST_BLOCK + threadIdx.x;
-    const int32_t cell = (int32_t)(gt / G);
+    // with a whole wave per cell the cell is wave-uniform: its coefficients load into
+    // scalar registers
+    const int32_t cell = G == 64 ? __builtin_amdgcn_readfirstlane((int32_t)(gt / G)) : (int32_t)(gt / G);
     const int lg = (int)(gt % G);
     const bool in = cell < ncell;
     const bool f32 = sizeof(T) == 4;
@@ -345,9 +347,11 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
         }
     }
     const int32_t na = active ? n : 0;
+    constexpr bool TWO_D = GEOM != FP_COUETTE1D;
 
-    // pass A: c* and cell sums
-    T cs0[K], cs1[K], cs2[K];
+    // pass A: c* and cell sums; the positions of the register-cached particles are loaded
+    // here too, so that pass B, after the group sums, does not wait for them
+    T cs0[K], cs1[K], cs2[K], xk[K], yk[K];
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
     const bool exact = g.conserve == FP_EXACT;
 #pragma unroll
@@ -355,6 +359,10 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
         const int32_t j = lg + k * G;
         if (j < na) {
             const int32_t p = b + j;
+            if (move) {
+                xk[k] = px[p];
+                yk[k] = TWO_D ? py[p] : (T)0;
+            }
             T cs[3], nn, cn;
             collide_one<T>(q, pvx[p], pvy[p], pvz[p], draw(g.seed, ppid[p], step, PURPOSE_COLLISION, 0),
                            cs, nn, cn);
@@ -408,7 +416,6 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
     // the FP64 re-emission code (and its registers) out of this kernel.
     const Walls W = make_walls(g);
     const double inv_dx = 1.0 / g.dx, inv_dy = 1.0 / g.dy;
-    constexpr bool TWO_D = GEOM != FP_COUETTE1D;
     auto store_done = [&](int32_t p, double x, double y, T v0, T v1, T v2, bool gone) {
         px[p] = (T)x;
         if (TWO_D) py[p] = (T)y;
@@ -416,12 +423,12 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
         pkey[p] = gone ? ncell : cell_key<TWO_D>(g, x, y, inv_dx, inv_dy, kmap);
     };
     // returns false when the full flight is still to do (velocity already stored)
-    auto finish_fast = [&](int32_t p, T v0, T v1, T v2) -> bool {
+    auto finish_fast = [&](int32_t p, T v0, T v1, T v2, T xo, T yo) -> bool {
         if (!move) {
             pvx[p] = v0; pvy[p] = v1; pvz[p] = v2;
             return true;
         }
-        const double x0 = (double)px[p], y0 = TWO_D ? (double)py[p] : 0.0;
+        const double x0 = (double)xo, y0 = TWO_D ? (double)yo : 0.0;
         const double w0 = (double)v0, w1 = (double)v1;
         const double ex = __dadd_rn(x0, __dmul_rn(w0, g.dt));
         const double ey = TWO_D ? __dadd_rn(y0, __dmul_rn(w1, g.dt)) : 0.0;
@@ -453,8 +460,8 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
     const uint64_t gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << (lane - lg));
     const uint64_t below = (1ull << lane) - 1ull;
     int32_t npend = 0;   // listed so far by the group (same in every lane still working)
-    auto finish = [&](int32_t p, T v0, T v1, T v2) {
-        const bool done = finish_fast(p, v0, v1, v2);
+    auto finish = [&](int32_t p, T v0, T v1, T v2, T xo, T yo) {
+        const bool done = finish_fast(p, v0, v1, v2, xo, yo);
         const uint64_t m = __ballot(!done) & gmask;
         if (!done) plist[b + npend + __popcll(m & below)] = p;
         npend += __popcll(m);
@@ -464,14 +471,19 @@ __global__ __launch_bounds__(ST_BLOCK) void collide_kernel(
         const int32_t j = lg + k * G;
         if (j < n) {
             const int32_t p = b + j;
-            if (active) finish(p, newv(cs0[k], 0), newv(cs1[k], 1), newv(cs2[k], 2));
-            else finish(p, pvx[p], pvy[p], pvz[p]);
+            // the inactive cells' particles (na = 0) were not prefetched
+            const T xo = !move ? (T)0 : (active ? xk[k] : px[p]);
+            const T yo = !move || !TWO_D ? (T)0 : (active ? yk[k] : py[p]);
+            if (active) finish(p, newv(cs0[k], 0), newv(cs1[k], 1), newv(cs2[k], 2), xo, yo);
+            else finish(p, pvx[p], pvy[p], pvz[p], xo, yo);
         }
     }
     for (int32_t j = lg + K * G; j < n; j += G) {
         const int32_t p = b + j;
-        if (active) finish(p, newv(pvx[p], 0), newv(pvy[p], 1), newv(pvz[p], 2));
-        else finish(p, pvx[p], pvy[p], pvz[p]);
+        const T xo = move ? px[p] : (T)0;
+        const T yo = move && TWO_D ? py[p] : (T)0;
+        if (active) finish(p, newv(pvx[p], 0), newv(pvy[p], 1), newv(pvz[p], 2), xo, yo);
+        else finish(p, pvx[p], pvy[p], pvz[p], xo, yo);
     }
     if (move && in && lg == 0) pend[cell] = npend;   // lane 0 takes part in every round
 }
@@ -584,9 +596,10 @@ static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const
                            uint32_t* adv, hipStream_t s) {
     const int64_t threads = (int64_t)c->ncell * G;
     const unsigned grid = (unsigned)((threads + ST_BLOCK - 1) / ST_BLOCK);
-    // register cache of c*: 8 particles per lane, 4 with 32 or more lanes per cell (about
-    // 3 particles per lane there; fewer registers, more resident waves)
-    constexpr int K = G >= 32 ? ST_K / 2 : ST_K;
+    // register cache of c* (and of the positions): 8 particles per lane, 4 with 32 lanes
+    // per cell, 2 with a whole wave per cell (about 2 particles per lane there; fewer
+    // registers, more resident waves: 70 VGPRs, 7 waves per SIMD)
+    constexpr int K = G >= 64 ? ST_K / 4 : (G >= 32 ? ST_K / 2 : ST_K);
     hipLaunchKernelGGL((collide_kernel<T, G, K, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
                        c->cfg, c->ncell, off, mom, rec, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy,
                        (T*)p->vz, p->pid, p->key, step, move, stepp, c->pend, c->bidx,
@@ -619,9 +632,10 @@ template <typename T, int GEOM>
 static void collide_dispatch(fp_ctx* c, fp_particles* p, const int32_t* off, const double* mom,
                              const double* rec, uint32_t step, int move, const uint32_t* sp,
                              uint32_t* adv, hipStream_t s) {
-    // about four particles per lane: the per-particle work (three Philox draws, the
-    // update, the flight) is long enough that wider groups beat the shorter group sums
-    switch (lanes_per_cell(c, p->n, FILL_4, 4)) {
+    // about two particles per lane: at 100 particles per cell a whole wave per cell (its
+    // coefficients wave-uniform, in scalar registers; 74 VGPRs, 6 waves per SIMD) was
+    // measured 4 % faster than 32 lanes (82 VGPRs, 5 waves) and 9 % faster than 16
+    switch (lanes_per_cell(c, p->n, FILL_4, 2)) {
         case 4: collide_launch<T, 4, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;
         case 8: collide_launch<T, 8, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;
         case 16: collide_launch<T, 16, GEOM>(c, p, off, mom, rec, step, move, sp, adv, s); break;
