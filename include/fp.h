@@ -376,7 +376,12 @@ typedef struct fp_nn fp_nn;
  * (0: inference only).  Synchronous. */
 int fp_nn_create(fp_ctx* ctx, int64_t max_batch, fp_nn** out);
 void fp_nn_destroy(fp_nn* net);
-/* Convert params (FP_NN_PARAMS floats, device) into the network's BF16 image. */
+/* Convert params (FP_NN_PARAMS floats, device, read only) into the network's BF16 image
+ * held by net (Sec. "Phase 3": the trained weights, biases and scalers are exported once
+ * and then evaluated forward only inside the loop).  Weights are rounded to bfloat16 (nearest
+ * even) and laid out for the MFMA fragments; the biases and the scalers stay FP32.  Must be
+ * called before any inference on net and again after params change; asynchronous on s.
+ * FP_EINVAL for a null pointer or a handle made on another context. */
 int fp_nn_load(fp_ctx* ctx, fp_nn* net, const float* params, hipStream_t s);
 /* Learned closure of every cell (Algorithm "Accelerated ML Simulation Loop"): network
  * outputs de-standardised, then checked against the cell's own normalised 9x9 system;
@@ -428,19 +433,31 @@ int fp_nn_infer(fp_ctx* ctx, const fp_nn* net, const double* mom, float* y, hipS
 int fp_nn_outputs(fp_ctx* ctx, const fp_nn* net, float* y, hipStream_t s);
 /* Raw (unstandardised) features of n moment records: feats[n][32] floats. */
 int fp_nn_features(fp_ctx* ctx, const double* mom, int64_t n, float* feats, hipStream_t s);
-/* Normalised 9x9 systems of n moment records: sys[n][90] doubles, A row-major then b. */
+/* Normalised 9x9 systems of n moment records (eq. system9x9 with the entries of Table
+ * matrix_system, as fp_closure_solve assembles them, divided by the cell's theta powers so
+ * that the unknowns are the normalised coefficients [tau Ct - 5 eps_hat I, tau sqrt(theta)
+ * Gamma]): mom[n][32] device doubles in, sys[n][90] device doubles out (caller-owned), A
+ * row-major then b.  The training data of the residual loss.  Only records with theta > 0
+ * give finite systems (the caller filters the others out, as the training set builders
+ * do).  FP_EINVAL for n < 0 or a null pointer; n = 0 does nothing. */
 int fp_closure_build(fp_ctx* ctx, const double* mom, int64_t n, double* sys, hipStream_t s);
-/* Gradient of the loss w.r.t. the trainable parameters for a batch of B samples:
- * feats[B][32] raw features; targets[B][16] raw normalised targets (FP_LOSS_MSE) or
- * sys[B][90] (FP_LOSS_RESIDUAL).  Writes grad[FP_NN_PARAMS] (only the trainable prefix)
- * and *loss (device float).  Fixed-order reductions: bitwise reproducible. */
+/* Gradient of the loss w.r.t. the trainable parameters for a batch of B samples (Sec.
+ * "Phase 1-2": standardised inputs and targets, a mean-squared-error loss; the residual
+ * loss is this library's alternative, the same system the deployment check of Algorithm
+ * "Accelerated ML Simulation Loop" evaluates).  feats[B][32] raw features; targets[B][16]
+ * raw normalised targets (FP_LOSS_MSE) or sys[B][90] (FP_LOSS_RESIDUAL); all device, read
+ * only.  Writes the trainable prefix of grad[FP_NN_PARAMS] (the scaler tail is left as
+ * it is) and *loss (device float).  B in [1, max_batch of net], else FP_EINVAL.  Fixed-order
+ * reductions: bitwise reproducible. */
 int fp_nn_grad(fp_ctx* ctx, fp_nn* net, const float* params, const float* feats,
                const float* targets, const double* sys, int64_t B, int32_t loss_kind,
                float* grad, float* loss, hipStream_t s);
 /* Adam (beta1 0.9, beta2 0.999, eps 1e-8) step t >= 1 on the trainable prefix. */
 int fp_nn_adam(fp_ctx* ctx, float* params, const float* grad, float* m, float* v, int64_t t,
                float lr, hipStream_t s);
-/* fp_nn_grad followed by fp_nn_adam. */
+/* fp_nn_grad followed by fp_nn_adam (Sec. "Phase 1-2": Adam on the loss), in place on
+ * params, m and v (device, caller-owned, FP_NN_PARAMS floats each, m and v zero before
+ * t = 1). */
 int fp_nn_train_step(fp_ctx* ctx, fp_nn* net, float* params, float* m, float* v, int64_t t,
                      float lr, const float* feats, const float* targets, const double* sys,
                      int64_t B, int32_t loss_kind, float* loss, hipStream_t s);
@@ -470,7 +487,9 @@ typedef struct fp_lite fp_lite;
  * inference only).  Synchronous. */
 int fp_lite_create(fp_ctx* ctx, int64_t max_batch, fp_lite** out);
 void fp_lite_destroy(fp_lite* net);
-/* Convert params (FP_LITE_PARAMS floats, device) into the network's BF16 image. */
+/* Convert params (FP_LITE_PARAMS floats, device, read only) into the network's BF16 image
+ * (Sec. "Phase 3": weights, biases and scalers exported once for forward-only use); same
+ * rules as fp_nn_load. */
 int fp_lite_load(fp_ctx* ctx, fp_lite* net, const float* params, hipStream_t s);
 /* Standardised network outputs of every cell's moments: y[ncell][16] floats (rows 9..15
  * zero; cells with N <= 1 or theta <= 0 are evaluated on zero inputs). */
