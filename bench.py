@@ -138,10 +138,10 @@ def run_workload(torch, F, I, w, steps, warmup, graph=True, kernel_times=True):
     return dict(n=n, nc=nc, t=t, steps=steps, kern=kern, ok_cells=int((st == F.CELL_OK).sum()))
 
 
-def counter_traffic(name):
-    """HBM bytes per launch from a committed counter summary under profiles/ (lines
-    "key: value"): traffic_bytes_per_launch, valid only while every source it lists
-    ("source: <path> <sha256>") is unchanged; otherwise None."""
+def profile_value(name, key):
+    """A per-launch figure from a committed counter summary under profiles/ (lines
+    "key: value"), valid only while every source it lists ("source: <path> <sha256>") is
+    unchanged; otherwise None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
@@ -152,9 +152,34 @@ def counter_traffic(name):
             _, rel, digest = line.split()
             f = os.path.join(ROOT, rel)
             ok = ok and os.path.exists(f) and hashlib.sha256(open(f, "rb").read()).hexdigest() == digest
-        elif line.startswith("traffic_bytes_per_launch:"):
+        elif line.startswith(key + ":"):
             val = int(float(line.split()[1]))
     return val if ok else None
+
+
+def counter_traffic(name):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)."""
+    return profile_value(name, "traffic_bytes_per_launch")
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz SIMD-cycles per second; a wave64 VALU
+# instruction keeps a SIMD busy 4 cycles at full rate (16 cycles for the quarter-rate
+# transcendental, 64-bit integer multiply and similar instructions)
+VALU_PEAK_CYCLES = 256 * 4 * 2.4e9
+
+
+def roofline_alu(res, kind, profile):
+    """The entry point against its VALU issue bound: its VALU-busy SIMD cycles per launch
+    (SQ_ACTIVE_INST_VALU from the committed counter summary) over the live mean launch
+    time, against the chip's SIMD-cycles per second."""
+    cyc = profile_value(profile, "valu_busy_cycles_per_launch")
+    if cyc is None:
+        return None
+    ms = res["kern"][kind]["ms"]
+    ach = cyc / (ms * 1e-3)
+    return {"bound": "alu", "achieved": round(ach / 1e12, 4), "peak": round(VALU_PEAK_CYCLES / 1e12, 4),
+            "unit": "T VALU-busy SIMD-cycles/s", "frac": round(ach / VALU_PEAK_CYCLES, 4), "kernel": kind,
+            "valu_busy_cycles_per_launch": cyc, "avg_ms": ms}
 
 
 def roofline_of(res, kind="step", traffic_file=None):
@@ -372,6 +397,9 @@ def main():
             "roofline_step": roofline_of(rs, "step", "step_cavity448x448x100_counters.txt"),
             "roofline_sort_moments": roofline_of(rs, "sort_moments",
                                                  "sort_moments_cavity448x448x100_counters.txt"),
+            "roofline_step_alu": roofline_alu(rs, "step", "step_cavity448x448x100_alu.txt"),
+            "roofline_sort_moments_alu": roofline_alu(rs, "sort_moments",
+                                                      "sort_moments_cavity448x448x100_alu.txt"),
         }
         # the roofline is taken where the state leaves the 256 MB last-level cache: the
         # dominant entry point of the 2e7-particle cavity (the 1e6 one fits in it)

@@ -556,7 +556,19 @@ def main(argv=None):
     ap.add_argument("--timing", default=None, metavar="PARAMS.npy",
                     help="only time the exact and learned closures on 1e6 cells with these "
                          "parameters (a file written by --save)")
+    ap.add_argument("--timing-random", action="store_true",
+                    help="only time the closure kernels (exact, both networks) on 1e6 cavity "
+                         "records with randomly initialised networks (for kernel profiles)")
     a = ap.parse_args(argv)
+    if a.timing_random:
+        mom = cavity_training_records(lids=(400.0,), n_transient=200, n_samples=100, every=25)
+        wc = I.cavity(kn=0.15, ncell=100, ppc=100, precision="f32")
+        feats, tg, _ = dataset(wc, mom)
+        lfeats, ltg = lite_dataset(wc, mom)
+        p27 = init_params(fit_scalers(feats, tg), seed=0)
+        plite = init_lite_params(fit_scalers(lfeats, ltg), seed=1)
+        print(json.dumps(closure_batch_timings(wc, mom, p27, plite)))
+        return
     if a.timing:
         p = torch.from_numpy(np.load(a.timing)).to("cuda")
         print(json.dumps(closure_timings(I.cavity(kn=1.0, ncell=100, ppc=100), p, reps=5)))

@@ -6,6 +6,9 @@
     python -m paper_2606_15622_amd.prof_summary copy
         a plain device copy of 256 MiB (three times), the known-size reference for the
         FETCH_SIZE / WRITE_SIZE counters
+    python -m paper_2606_15622_amd.prof_summary alu SQ.csv [SQ2.csv ...] --match REGEX@GRID [...]
+            --source FILE
+        VALU-busy cycles of an entry point (SQ_ACTIVE_INST_VALU), for the ALU roofline
     python -m paper_2606_15622_amd.prof_summary counters --fetch F.csv --write W.csv
             --copy-fetch CF.csv --copy-write CW.csv --match REGEX@GRID [--match ...]
             --source FILE [--source FILE ...] [--title T] [--command C]
@@ -165,6 +168,56 @@ def instruction_mix(a):
     return "\n".join(out)
 
 
+def alu(a):
+    """VALU work of an entry point from one rocprofv3 --pmc run of SQ counters (SQ_WAVES,
+    SQ_ACTIVE_INST_VALU, SQ_INSTS_VALU and the VALU classes): per kernel at its grid the
+    waves, VALU instructions and VALU-busy cycles per wave (SQ_ACTIVE_INST_VALU counts
+    quad-cycles), and per launch of the entry point the VALU-busy SIMD cycles summed over
+    its kernels; the listed sources are hashed as for the traffic summary."""
+    import hashlib
+    # several passes (rocprofv3 collects a limited set of SQ counters per run): each
+    # counter is averaged over the dispatches of the pass that collected it
+    rows = defaultdict(lambda: defaultdict(list))
+    for path in a.csv:
+        for r in csv.DictReader(open(path)):
+            rows[(r["Kernel_Name"], int(r["Grid_Size"]))][r["Counter_Name"]].append(
+                float(r["Counter_Value"]))
+    avg = lambda v: sum(v) / len(v) if v else 0.0
+    out = []
+    if a.title:
+        out.append(f"# {a.title}")
+    if a.command:
+        out.append(f"# command: {a.command}")
+    out.append("# SQ counters summed over the chip per dispatch, averaged over dispatches; instructions are "
+               "wave instructions; busy = SQ_ACTIVE_INST_VALU x 4 (quad-cycles)")
+    tot = 0.0
+    for m in a.match:
+        kre, grid = m.rsplit("@", 1)[0], int(m.rsplit("@", 1)[1])
+        for (name, g), c in sorted(rows.items()):
+            if g != grid or not re.search(kre, name):
+                continue
+            w = avg(c.get("SQ_WAVES", []))
+            busy = avg(c.get("SQ_ACTIVE_INST_VALU", [])) * 4.0
+            per = lambda k: avg(c.get(k, [])) / w if w else 0.0
+            line = (f"kernel: {short(name)} grid {grid} waves {w:.0f} "
+                    f"valu_per_wave {per('SQ_INSTS_VALU'):.1f} salu_per_wave {per('SQ_INSTS_SALU'):.1f} "
+                    f"lds_per_wave {per('SQ_INSTS_LDS'):.1f} vmem_per_wave "
+                    f"{per('SQ_INSTS_VMEM_RD') + per('SQ_INSTS_VMEM_WR'):.1f}")
+            for key, cs in (("trans_f32", ["SQ_INSTS_VALU_TRANS_F32"]), ("int32", ["SQ_INSTS_VALU_INT32"]),
+                            ("int64", ["SQ_INSTS_VALU_INT64"]), ("fma_f32", ["SQ_INSTS_VALU_FMA_F32"]),
+                            ("f64", ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64",
+                                     "SQ_INSTS_VALU_MUL_F64"])):
+                if all(k in c for k in cs):
+                    line += f" {key}_per_wave {sum(per(k) for k in cs):.1f}"
+            out.append(line + f" busy_cycles_per_wave {busy / w if w else 0.0:.1f} busy_cycles {busy:.0f}")
+            tot += busy
+    out.append(f"valu_busy_cycles_per_launch: {tot:.0f}")
+    for src in a.source:
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        out.append(f"source: {src} {digest}")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -186,7 +239,16 @@ def main():
     c.add_argument("--source", action="append", default=[])
     c.add_argument("--title", default="")
     c.add_argument("--command", default="")
+    v = sub.add_parser("alu")
+    v.add_argument("csv", nargs="+")
+    v.add_argument("--match", action="append", required=True, help="REGEX@GRID (repeatable)")
+    v.add_argument("--source", action="append", default=[])
+    v.add_argument("--title", default="")
+    v.add_argument("--command", default="")
     a = ap.parse_args()
+    if a.cmd == "alu":
+        print(alu(a))
+        return
     if a.cmd == "trace":
         print(summarize(a.trace, a.title, a.command))
     elif a.cmd == "copy":
