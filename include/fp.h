@@ -166,7 +166,10 @@ int fp_bin(fp_ctx* ctx, const fp_particles* src, fp_particles* dst, int32_t* off
  * receives the moment records of the sorted cells, as fp_moments of dst would compute
  * them (up to the order of the sums), gathered in the same pass.  samp (optional, needs
  * mom) then receives the time-average sums of those records exactly as fp_sample would
- * add them. */
+ * add them.  On a context with an adaptive tree the leaves count as one row of cells (the
+ * leaves before and after a leaf in depth-first order are its side neighbours; any other
+ * move takes the general path), and the call is refused (FP_EINVAL) until an fp_bin has
+ * sorted by the current leaves, i.e. after fp_amr_init and after every fp_amr_adapt. */
 int fp_rebin(fp_ctx* ctx, const fp_particles* src, const int32_t* src_offsets,
              fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom, double* samp,
              hipStream_t s);

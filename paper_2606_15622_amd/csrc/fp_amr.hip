@@ -491,6 +491,7 @@ extern "C" int fp_amr_init(fp_ctx* c, int32_t max_level) {
     if (c->cfg.nx % m != 0 || c->cfg.ny % m != 0)
         return set_err(c, FP_EINVAL, "fp_amr_init: nx and ny must be multiples of 2^max_level");
     c->amr_L = max_level;
+    ++c->amr_epoch;
     c->amr_nbx = c->cfg.nx / m;
     c->amr_nby = c->cfg.ny / m;
     const TreeDims t = dims(c);
@@ -531,6 +532,7 @@ extern "C" int fp_amr_adapt(fp_ctx* c, const fp_amr_params* prm, double* acc, do
     const int64_t nodes = t.off[t.L + 1];
     const int64_t nfine = (int64_t)c->cfg.nx * c->cfg.ny;
     const int32_t old_ncell = c->ncell;
+    ++c->amr_epoch;   // the leaves are renumbered: the next sort must be a full fp_bin
     const double fnum = c->cfg.fnum, mass = c->cfg.mass;
     // decisions on the tree as it is
     hipLaunchKernelGGL(amr_zero8_kernel, dim3(blocks(nodes)), dim3(AMR_BLOCK), 0, s, nodes, c->amr_flag);

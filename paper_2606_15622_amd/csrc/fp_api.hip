@@ -249,7 +249,9 @@ extern "C" int fp_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int
         return set_err(c, FP_EINVAL, "fp_bin: src and dst share their device count");
     if (src->vx == dst->vx || src->x == dst->x || src->pid == dst->pid)
         return set_err(c, FP_EINVAL, "fp_bin: src and dst alias");
-    return launch_bin(c, src, dst, offsets, perm, s);
+    const int rc = launch_bin(c, src, dst, offsets, perm, s);
+    if (rc == FP_OK) c->sort_epoch = c->amr_epoch;
+    return rc;
 }
 
 extern "C" int fp_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_offsets,
@@ -258,8 +260,8 @@ extern "C" int fp_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_o
     if (!c || !offsets || !src_offsets || !particles_ok(c, src, true) || !dst || (samp && !mom))
         return set_err(c, FP_EINVAL, "fp_rebin: bad argument");
     if (samp && samp == mom) return set_err(c, FP_EINVAL, "fp_rebin: samp and mom alias");
-    if (c->amr_L >= 0)
-        return set_err(c, FP_EINVAL, "fp_rebin: the re-sort needs the uniform grid (adaptive tree: fp_bin)");
+    if (c->amr_L >= 0 && c->sort_epoch != c->amr_epoch)
+        return set_err(c, FP_EINVAL, "fp_rebin: the leaves changed since the last sort (fp_bin first)");
     if (slots_of(src) > 0 && (!dst->vx || !dst->vy || !dst->vz || !dst->pid || !dst->key || !dst->x ||
                               (c->cfg.geometry != FP_COUETTE1D && !dst->y)))
         return set_err(c, FP_EINVAL, "fp_rebin: bad destination");

@@ -1065,16 +1065,26 @@ __global__ __launch_bounds__(BLK) void rebin_gather_mom_kernel(
     }
 }
 
+// Grid of the re-sort's neighbourhoods: the uniform grid, or on the adaptive tree the
+// leaves as one row (the leaves just before and after in depth-first order are the side
+// buckets; a particle bound for any other leaf takes the far path)
+static void rebin_grid(const fp_ctx* c, int32_t& nx, int32_t& ny) {
+    nx = c->amr_L >= 0 ? c->ncell : c->cfg.nx;
+    ny = c->amr_L >= 0 ? 1 : c->cfg.ny;
+}
+
 // pass 1 with G lanes per old cell
 template <int G>
 static void rebin_count_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
                                hipStream_t s) {
     const int32_t nc = c->ncell;
+    int32_t nx, ny;
+    rebin_grid(c, nx, ny);
     const int32_t cblocks = (int32_t)(((int64_t)nc * G + BIN_BLOCK - 1) / BIN_BLOCK);
     // cnt, ccnt (far counts), ccur and farn are zero on entry: the previous sort call left
     // them so
     hipLaunchKernelGGL((rebin_count_kernel<G>), dim3(cblocks + FAR_BLOCKS), dim3(BIN_BLOCK), 0, s, nc,
-                       c->cfg.nx, src->n, (const int64_t*)src->n_dev, c->cfg.capacity, cblocks, src_off,
+                       nx, src->n, (const int64_t*)src->n_dev, c->cfg.capacity, cblocks, src_off,
                        (const int32_t*)src->key,
                        c->ncnt, c->bidx, c->cnt, c->ccnt, c->farn, c->cmask, c->errcount);
 }
@@ -1084,7 +1094,9 @@ template <typename T, int G>
 static void rebin_gather_launch(fp_ctx* c, const fp_particles* src, const int32_t* src_off,
                                 fp_particles* dst, int32_t* offsets, int32_t* perm, double* mom,
                                 double* samp, hipStream_t s) {
-    const int32_t nc = c->ncell, nx = c->cfg.nx, ny = c->cfg.ny;
+    const int32_t nc = c->ncell;
+    int32_t nx, ny;
+    rebin_grid(c, nx, ny);
     const int64_t n = src->n, cap = c->cfg.capacity;
     const bool two_d = c->cfg.geometry != FP_COUETTE1D;
     Rec<T> r{(const T*)src->x,  two_d ? (const T*)src->y : nullptr, (const T*)src->vx,

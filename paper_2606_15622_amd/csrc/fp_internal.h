@@ -54,6 +54,9 @@ struct fp_ctx {
     // adaptive quadtree (fp_amr_init; the grid of cfg is the finest level): ncell is then
     // the number of leaves and every key is looked up in leafmap
     int32_t amr_L = -1;          // levels below the base grid, -1: no tree
+    // leaf numbering generation (fp_amr_init and every fp_amr_adapt advance it) and the one
+    // the last fp_bin / fp_rebin sorted by: fp_rebin on a tree needs them equal
+    int32_t amr_epoch = 0, sort_epoch = -1;
     int32_t amr_nbx = 0, amr_nby = 0;
     int8_t* amr_state = nullptr; // [nodes] absent / leaf / refined, level-major
     int8_t* amr_flag = nullptr;  // [nodes] 1 split, 2 merge (one adaptation)

@@ -442,10 +442,14 @@ class AMRSimulation:
     """Loop of the open cylinder domain on an adaptive quadtree (the grid of w is the
     finest level, max_level levels below the base grid): every adapt_every steps
     fp_amr_adapt on the sampling sums of the leaves since the last adaptation, then
-    sort (fp_bin: the re-sort needs the uniform grid) -> moments -> sums (and sample) ->
-    closure -> collide + move -> inflow injection.  The particle count and the step
-    number live on the device (as in OpenSimulation); the adaptation every adapt_every
-    steps is synchronous (it reads the new leaf count back)."""
+    sort -> moments -> sums (and sample) -> closure -> collide + move -> inflow injection.
+    The sort is a full fp_bin every step: fp_rebin also sorts on a tree (between
+    adaptations), but there it treats the leaves as one row, and on the cylinder about a
+    third of the particles that change leaf land in a leaf that is not next to their old
+    one in depth-first order; that general path makes the re-sort slower than fp_bin
+    (2.6 against 1.4 ms per step at 7.6e5 leaves).  The particle count and the step number
+    live on the device (as in OpenSimulation); the adaptation every adapt_every steps is
+    synchronous (it reads the new leaf count back)."""
 
     def __init__(self, w, state, max_level, prm, adapt_every, capacity=None, device="cuda"):
         self.w, self.prm, self.adapt_every = w, dict(prm), int(adapt_every)

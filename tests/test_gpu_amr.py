@@ -196,12 +196,13 @@ def test_open_run_with_tree_matches_oracle(L, every):
     np.testing.assert_allclose(sim.samp[:nl].cpu().numpy(), osamp, rtol=1e-9, atol=1e-9 * np.abs(osamp).max())
 
 
-def test_rebin_is_refused_with_a_tree():
+def test_rebin_is_refused_with_a_tree_before_a_sort_by_its_leaves():
     F = fp()
     w = small("f32")
     sim = F.AMRSimulation(w, I.freestream_state(w, seed=1), 1, dict(
         tau_grad=0.1, tau_coarse=0.05, shock_factor=1.2, p_inf=1.0, n_max=1e9, n_grad=40.0,
         eps=1e-300, age_min=10), 0)
+    # no sort by the tree's leaves yet: the re-sort is refused
     with pytest.raises(RuntimeError):
         sim.ctx.rebin(sim.a, sim.offs[0], sim.b, sim.offs[1])
     with pytest.raises(RuntimeError):
@@ -215,11 +216,64 @@ def test_rebin_is_refused_with_a_tree():
                            n_grad=1e30, eps=1e-300, age_min=10), acc, None, None, 1)
     assert sim.ctx.ncell > n0                   # every cell with gas above N_max split
     assert float(acc[:sim.ctx.ncell].abs().sum()) == 0.0
+    # the leaves were renumbered: still refused until a full sort
+    with pytest.raises(RuntimeError):
+        sim.ctx.rebin(sim.a, sim.offs[0], sim.b, sim.offs[1])
     for w2, L in ((small("f32"), 5), (small("f32"), 3), (I.cavity(ncell=16, ppc=4), 1)):
         ctx = F.Context(w2, 1000)     # level above 4; 60 cells not a multiple of 8; no cylinder
         with pytest.raises(RuntimeError):
             ctx.amr_init(L)
         assert ctx.ncell == w2["nx"] * w2["ny"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_rebin_on_the_tree_matches_the_full_sort(prec):
+    """fp_rebin on the tree between adaptations (the leaves as one row of cells): the
+    particles come out exactly as from fp_bin of the same input, the moments within the
+    rounding of the sums' order of those of fp_moments, and the sums exactly those that
+    fp_sample adds for the re-sort's own moments; after an adaptation it is refused."""
+    F = fp()
+    w = small(prec, mach=10.0)
+    prm = dict(tau_grad=0.10, tau_coarse=0.05, shock_factor=1.2, p_inf=p_inf(w), n_max=1e9,
+               n_grad=40.0, eps=1e-300, age_min=4)
+    sim = F.AMRSimulation(w, I.freestream_state(w, seed=6), 2, prm, 0)
+    for s in range(6):
+        sim.step(s)
+    sim.adapt(6)                                  # split around the body
+    for s in range(6, 10):
+        sim.step(s)
+    torch.cuda.synchronize()
+    nc = sim.ncell
+    a = sim.a
+    cap = a.capacity
+    ref = F.Particles(0, a.dtype, True, "cuda", capacity=cap, device_count=True)
+    ref.n = a.n
+    out = F.Particles(0, a.dtype, True, "cuda", capacity=cap, device_count=True)
+    out.n = a.n
+    offs_ref = torch.zeros_like(sim.offs[1])
+    offs_out = torch.zeros_like(sim.offs[1])
+    mom_ref = torch.zeros_like(sim.mom)
+    mom_out = torch.zeros_like(sim.mom)
+    samp_out = torch.full_like(sim.samp, 0.25)
+    samp_chk = torch.full_like(sim.samp, 0.25)
+    sim.ctx.bin(a, ref, offs_ref)
+    sim.ctx.moments(ref, offs_ref, mom_ref)
+    sim.ctx.rebin(a, sim.offs[0], out, offs_out, mom=mom_out, samp=samp_out)
+    sim.ctx.sample(mom_out, samp_chk)
+    torch.cuda.synchronize()
+    n = int(ref.count())
+    assert int(out.count()) == n > 0
+    np.testing.assert_array_equal(offs_out[:nc + 1].cpu().numpy(), offs_ref[:nc + 1].cpu().numpy())
+    for k in ("x", "y", "vx", "vy", "vz", "pid", "key"):
+        np.testing.assert_array_equal(getattr(out, k)[:n].cpu().numpy(), getattr(ref, k)[:n].cpu().numpy(), k)
+    mr, mo = mom_ref[:nc].cpu().numpy(), mom_out[:nc].cpu().numpy()
+    scale = np.abs(mr).max(0) + 1e-300
+    assert np.all(np.abs(mo - mr) <= 1e-12 * scale), float((np.abs(mo - mr) / scale).max())
+    np.testing.assert_array_equal(samp_out[:nc].cpu().numpy(), samp_chk[:nc].cpu().numpy())
+    assert sim.ctx.error_count() == 0
+    sim.adapt(4)
+    with pytest.raises(RuntimeError):
+        sim.ctx.rebin(sim.a, sim.offs[0], sim.b, sim.offs[1])
 
 
 def test_full_size_tree_properties():
