@@ -85,7 +85,7 @@ typedef struct fp_config {
                                 low-order moments (fp_closure_nn unchecked); fp_closure_solve
                                 and the checked fp_closure_nn then refuse the records */
     int32_t reserved0;       /* 0 */
-    int64_t capacity;        /* largest particle count any call will see */
+    int64_t capacity;        /* largest particle count any call will see, <= 2^29 - 64 */
     double x0, y0;           /* domain origin [m] */
     double lx, ly;           /* domain extent [m] */
     double dx, dy;           /* cell size [m] */

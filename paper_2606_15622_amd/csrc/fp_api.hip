@@ -34,7 +34,8 @@ static int validate(const fp_config* g, std::string& why) {
     if (g->conserve != FP_EXACT && g->conserve != FP_PAPER) return why = "conserve", 0;
     if (g->nx < 1 || g->ny < 1 || (int64_t)g->nx * g->ny > (1 << 28)) return why = "grid", 0;
     if (g->geometry == FP_COUETTE1D && g->ny != 1) return why = "1-D grid needs ny = 1", 0;
-    if (g->capacity < 0 || g->capacity > ((int64_t)1 << 31) - 64) return why = "capacity", 0;
+    // at most 2^29 - 64 slots: byte offsets into the FP64 particle arrays stay below 2^32
+    if (g->capacity < 0 || g->capacity > ((int64_t)1 << 29) - 64) return why = "capacity", 0;
     if (g->max_bounces < 0 || g->max_bounces > 1000) return why = "max_bounces", 0;
     if (g->lanes != 0 && g->lanes != 4 && g->lanes != 8 && g->lanes != 16 && g->lanes != 32 &&
         g->lanes != 64)

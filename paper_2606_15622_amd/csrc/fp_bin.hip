@@ -858,6 +858,7 @@ __global__ __launch_bounds__(BLK) void rebin_gather_mom_kernel(
     constexpr int GROUPS = BLK / G;
     __shared__ int32_t s_run[GROUPS][9][4];   // start in bidx, length, far before, range start
     __shared__ int32_t s_pre[GROUPS][10];     // bucket starts in the cell's concatenation
+    __shared__ double s_samp[GROUPS][14];     // the cells' time-average sums
     __shared__ MomShared<BLK, G> sm;
     // far arrivals of a cell staged in LDS, up to FCAP of them (their ranks compare every
     // arrival with all others and with the nine source ranges), in the space of the
@@ -888,31 +889,60 @@ __global__ __launch_bounds__(BLK) void rebin_gather_mom_kernel(
         f0 = min(foff[k], fend);
         f1 = min(foff[k + 1], fend);
     }
-    const int32_t nf = f1 - f0;
-    const bool far_lds = nf <= FCAP;   // group-uniform
-    if (far_lds)
-        for (int32_t t = lg; t < nf; t += G) s_far[grp][t] = fsrc[f0 + t];
-    __syncthreads();
-    auto far_at = [&](int32_t t) __attribute__((always_inline)) {
-        return far_lds ? s_far[grp][t] : fsrc[f0 + t];
-    };
-    for (int q = lg; q < 9; q += G) {
-        int32_t st = 0, len = 0, fb = 0, s0 = INT32_MAX;
+    // the cell's 14 time-average sums, sum e on lane e % G, loaded now (parked in LDS
+    // across the gather and the moments) and updated at the end
+    constexpr int SQ = (14 + G - 1) / G;
+    const bool samp_cell = samp && in;
+    double samp_ld[SQ];
+#pragma unroll
+    for (int u = 0; u < SQ; ++u) {
+        const int e = lg + u * G;
+        samp_ld[u] = samp_cell && e < 14 ? samp[(int64_t)k * SAMP + e] : 0.0;
+    }
+    // the nine buckets' descriptors (bucket start and length in the old cell's range, the
+    // range start), loaded before the far staging's barrier
+    constexpr int QN = (9 + G - 1) / G;
+    int32_t q_st[QN], q_len[QN], q_s0[QN];
+#pragma unroll
+    for (int u = 0; u < QN; ++u) {
+        const int q = lg + u * G;
+        q_st[u] = 0;
+        q_len[u] = 0;
+        q_s0[u] = INT32_MAX;   // a neighbour outside the grid
         const int32_t sy = ky - 1 + q / 3, sx = kx - 1 + q % 3;
-        if (in && sx >= 0 && sx < nx && sy >= 0 && sy < ny) {
+        if (q < 9 && in && sx >= 0 && sx < nx && sy >= 0 && sy < ny) {
             const int32_t c2 = sy * nx + sx;
             const int d = (ky - sy + 1) * 3 + (kx - sx + 1);
             const int32_t* e2 = bend + (int64_t)c2 * 9;
             const int32_t b0 = d > 0 ? e2[d - 1] : 0;
-            s0 = max(src_off[c2], 0);
-            st = s0 + b0;
-            len = e2[d] - b0;
-            for (int32_t f = 0; f < nf; ++f) fb += far_at(f) < s0 ? 1 : 0;
+            q_s0[u] = max(src_off[c2], 0);
+            q_st[u] = q_s0[u] + b0;
+            q_len[u] = e2[d] - b0;
         }
-        s_run[grp][q][0] = st;
-        s_run[grp][q][1] = len;
-        s_run[grp][q][2] = fb;
-        s_run[grp][q][3] = s0;   // INT32_MAX for a neighbour outside the grid
+    }
+    const int32_t nf = f1 - f0;
+    const bool far_lds = nf <= FCAP;   // group-uniform
+    if (far_lds)
+        for (int32_t t = lg; t < nf; t += G) s_far[grp][t] = fsrc[f0 + t];
+#pragma unroll
+    for (int u = 0; u < SQ; ++u)
+        if (samp_cell && lg + u * G < 14) s_samp[grp][lg + u * G] = samp_ld[u];
+    __syncthreads();
+    auto far_at = [&](int32_t t) __attribute__((always_inline)) {
+        return far_lds ? s_far[grp][t] : fsrc[f0 + t];
+    };
+#pragma unroll
+    for (int u = 0; u < QN; ++u) {
+        const int q = lg + u * G;
+        if (q < 9) {
+            int32_t fb = 0;
+            if (q_s0[u] != INT32_MAX)
+                for (int32_t f = 0; f < nf; ++f) fb += far_at(f) < q_s0[u] ? 1 : 0;
+            s_run[grp][q][0] = q_st[u];
+            s_run[grp][q][1] = q_len[u];
+            s_run[grp][q][2] = fb;
+            s_run[grp][q][3] = q_s0[u];
+        }
     }
     __syncthreads();
     if (lg == 0) {
@@ -935,7 +965,7 @@ __global__ __launch_bounds__(BLK) void rebin_gather_mom_kernel(
 #pragma unroll
         for (int tt = 1; tt < 9; ++tt) t += q >= rs[tt] ? 1 : 0;
         fb = s_run[grp][t][2];
-        j = bidx[s_run[grp][t][0] + q - s_pre[grp][t]];
+        j = ld_off(bidx, s_run[grp][t][0] + q - s_pre[grp][t]);
     };
     // one round: U positions per lane, all loads first; velocities returned
     auto round = [&](int32_t q0, T (&ox)[GM_U], T (&oy)[GM_U], T (&oz)[GM_U])
@@ -959,26 +989,26 @@ __global__ __launch_bounds__(BLK) void rebin_gather_mom_kernel(
             ox[u] = oy[u] = oz[u] = (T)0;
             if (src[u] >= 0) {
                 const int32_t j = src[u];
-                rx[u] = r.sx[j];
-                ry[u] = r.sy ? r.sy[j] : (T)0;
-                ox[u] = r.svx[j];
-                oy[u] = r.svy[j];
-                oz[u] = r.svz[j];
-                rp[u] = r.spid[j];
+                rx[u] = ld_off(r.sx, j);
+                ry[u] = r.sy ? ld_off(r.sy, j) : (T)0;
+                ox[u] = ld_off(r.svx, j);
+                oy[u] = ld_off(r.svy, j);
+                oz[u] = ld_off(r.svz, j);
+                rp[u] = ld_off(r.spid, j);
             }
         }
 #pragma unroll
         for (int u = 0; u < GM_U; ++u) {
             const int32_t d = dst[u];
             if (src[u] >= 0 && d >= 0 && d < lim) {
-                r.dx[d] = rx[u];
-                if (r.dy) r.dy[d] = ry[u];
-                r.dvx[d] = ox[u];
-                r.dvy[d] = oy[u];
-                r.dvz[d] = oz[u];
-                r.dpid[d] = rp[u];
-                r.dkey[d] = k;
-                if (r.perm) r.perm[d] = src[u];
+                st_off(r.dx, d, rx[u]);
+                if (r.dy) st_off(r.dy, d, ry[u]);
+                st_off(r.dvx, d, ox[u]);
+                st_off(r.dvy, d, oy[u]);
+                st_off(r.dvz, d, oz[u]);
+                st_off(r.dpid, d, rp[u]);
+                st_off(r.dkey, d, k);
+                if (r.perm) st_off(r.perm, d, src[u]);
             }
         }
     };
@@ -1040,28 +1070,51 @@ __global__ __launch_bounds__(BLK) void rebin_gather_mom_kernel(
     s2 = group_sum<G>(s2);
     const double inv_n = ncnt > 0 ? 1.0 / (double)ncnt : 0.0;
     const double U0 = s0 * inv_n, U1 = s1 * inv_n, U2 = s2 * inv_n;
-    double acc[NVX];
+    // the monomials in rounds of MR (each reduced before the next: fewer live registers)
+    auto accum = [&](auto r0c, auto& part) __attribute__((always_inline)) {
+        constexpr int R0 = decltype(r0c)::value;
+        if (regs) {
+            // an empty asm that "changes" the cached velocities, so that every round
+            // converts and centres them afresh instead of keeping the FP64 values of all
+            // particles live across the rounds
 #pragma unroll
-    for (int i = 0; i < NVX; ++i) acc[i] = 0.0;
-    if (regs) {
+            for (int u = 0; u < GM_U; ++u) asm volatile("" : "+v"(kvx[u]), "+v"(kvy[u]), "+v"(kvz[u]));
 #pragma unroll
-        for (int u = 0; u < GM_U; ++u)
-            if (u * G + lg < ncnt)
-                mom_accum<NVX>((double)kvx[u] - U0, (double)kvy[u] - U1, (double)kvz[u] - U2, acc);
-    } else {
-        for (int32_t q = lg; q < ncnt; q += G)
-            mom_accum<NVX>((double)r.dvx[base + q] - U0, (double)r.dvy[base + q] - U1,
-                           (double)r.dvz[base + q] - U2, acc);
-    }
-    mom_finish<BLK, G, NVX>(sm, acc, grp, lg, in, ncnt, U0, U1, U2,
-                             mom + (int64_t)(in ? k : 0) * MOM);
-    if (samp && in && lg == 0) {
-        // time-average sums from the record's entries, rebuilt from the final sums in LDS
-        // (the values mom_finish stored) instead of reading the record back
+            for (int u = 0; u < GM_U; ++u)
+                if (u * G + lg < ncnt)
+                    mom_accum_range<R0>((double)kvx[u] - U0, (double)kvy[u] - U1, (double)kvz[u] - U2,
+                                        part);
+        } else {
+            for (int32_t q = lg; q < ncnt; q += G)
+                mom_accum_range<R0>((double)ld_off(r.dvx, base + q) - U0,
+                                    (double)ld_off(r.dvy, base + q) - U1,
+                                    (double)ld_off(r.dvz, base + q) - U2, part);
+        }
+    };
+    mom_finish_rounds<BLK, G, NVX>(sm, accum, grp, lg, in, ncnt, U0, U1, U2,
+                                   mom + (int64_t)(in ? k : 0) * MOM);
+    if (samp_cell && lg < 14) {
+        // the lane's time-average sums from the record's entries, rebuilt from the final
+        // sums in LDS (the values mom_finish stored) instead of reading the record back;
+        // every term with a compile-time entry index (no indexed access to m), the lane's
+        // own ones kept
         double m[M_T + 10];
 #pragma unroll
         for (int e = 0; e < M_T + 10; ++e) m[e] = mom_entry<BLK, G, NVX>(sm, grp, ncnt, U0, U1, U2, e);
-        sample_add(m, samp + (int64_t)k * SAMP);
+        double t[SQ];
+#pragma unroll
+        for (int u = 0; u < SQ; ++u) t[u] = 0.0;
+#pragma unroll
+        for (int e = 0; e < 14; ++e) {
+            const double v = sample_term(m, e);
+#pragma unroll
+            for (int u = 0; u < SQ; ++u) t[u] = lg + u * G == e ? v : t[u];
+        }
+#pragma unroll
+        for (int u = 0; u < SQ; ++u) {
+            const int e = lg + u * G;
+            if (e < 14) samp[(int64_t)k * SAMP + e] = s_samp[grp][e] + t[u];
+        }
     }
 }
 

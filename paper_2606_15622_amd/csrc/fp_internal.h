@@ -225,6 +225,21 @@ inline int lanes_per_cell(const fp_ctx* c, int64_t n, int64_t min_threads = 0, i
 // resident waves on each of the 1024 SIMDs)
 constexpr int64_t FILL_4 = 1024 * 4 * 64, FILL_8 = 1024 * 8 * 64;
 
+// Element j of a device array as its base plus a 32-bit byte offset: with the base in
+// SGPRs (a kernel argument) the compiler uses the global load/store form that takes one
+// VGPR for the offset, shared by the arrays of one element size, instead of a 64-bit
+// address per array and element.  The context's capacity limit keeps every particle
+// array's byte offsets below 2^32.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* base, int32_t j) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                       (uint32_t)j * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T* base, int32_t j, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)j * (uint32_t)sizeof(T)) = v;
+}
+
 // slots a call's per-particle grid covers: the host count, or with a device count
 // (p->n_dev) the capacity of the arrays
 inline int64_t slots_of(const fp_particles* p) {

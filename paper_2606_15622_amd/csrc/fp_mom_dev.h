@@ -5,6 +5,8 @@
 #pragma once
 #include "fp_internal.h"
 
+#include <type_traits>
+
 namespace fpg {
 
 constexpr int NV = 26;   // accumulated monomials: P (6), T (10), R (6), W (3), H
@@ -14,28 +16,43 @@ constexpr int MR = 13;   // values per LDS reduction round
 // acc[0..5] P (11 12 13 22 23 33), acc[6..15] T (111 112 113 122 123 133 222 223 233 333),
 // acc[16..21] R, acc[22..24] W, acc[25] H; FP64 products and sums.  With NVX = NV_LOW
 // only P and T are accumulated (the same operations, in the same order).
+// The values acc[LO .. LO + N) of the above into o[0 .. N): the same operations in the same
+// order as for the whole set, so that a gather may accumulate the monomials in rounds (fewer
+// live accumulators) with sums bit for bit those of one pass.
+template <int LO, int N>
+__device__ __forceinline__ void mom_accum_range(double a, double bb, double d, double (&o)[N]) {
+    const double aa = a * a, ab = a * bb, ad = a * d, b2 = bb * bb, bd = bb * d, dd = d * d;
+#define FP_MA_ADD(i, x) \
+    if constexpr ((i) >= LO && (i) < LO + N) o[(i) - LO] += (x)
+#define FP_MA_FMA(i, x, y) \
+    if constexpr ((i) >= LO && (i) < LO + N) o[(i) - LO] = fma((x), (y), o[(i) - LO])
+    FP_MA_ADD(0, aa); FP_MA_ADD(1, ab); FP_MA_ADD(2, ad);
+    FP_MA_ADD(3, b2); FP_MA_ADD(4, bd); FP_MA_ADD(5, dd);
+    FP_MA_FMA(6, aa, a);
+    FP_MA_FMA(7, aa, bb);
+    FP_MA_FMA(8, aa, d);
+    FP_MA_FMA(9, b2, a);
+    FP_MA_FMA(10, ab, d);
+    FP_MA_FMA(11, dd, a);
+    FP_MA_FMA(12, b2, bb);
+    FP_MA_FMA(13, b2, d);
+    FP_MA_FMA(14, dd, bb);
+    FP_MA_FMA(15, dd, d);
+    if constexpr (LO + N > 16) {
+        const double c2 = aa + b2 + dd;
+        FP_MA_FMA(16, aa, c2); FP_MA_FMA(17, ab, c2); FP_MA_FMA(18, ad, c2);
+        FP_MA_FMA(19, b2, c2); FP_MA_FMA(20, bd, c2); FP_MA_FMA(21, dd, c2);
+        const double c4 = c2 * c2;
+        FP_MA_FMA(22, c4, a); FP_MA_FMA(23, c4, bb); FP_MA_FMA(24, c4, d);
+        FP_MA_FMA(25, c4, c2);
+    }
+#undef FP_MA_ADD
+#undef FP_MA_FMA
+}
+
 template <int NVX = NV>
 __device__ __forceinline__ void mom_accum(double a, double bb, double d, double (&acc)[NVX]) {
-    const double aa = a * a, ab = a * bb, ad = a * d, b2 = bb * bb, bd = bb * d, dd = d * d;
-    acc[0] += aa; acc[1] += ab; acc[2] += ad; acc[3] += b2; acc[4] += bd; acc[5] += dd;
-    acc[6] = fma(aa, a, acc[6]);
-    acc[7] = fma(aa, bb, acc[7]);
-    acc[8] = fma(aa, d, acc[8]);
-    acc[9] = fma(b2, a, acc[9]);
-    acc[10] = fma(ab, d, acc[10]);
-    acc[11] = fma(dd, a, acc[11]);
-    acc[12] = fma(b2, bb, acc[12]);
-    acc[13] = fma(b2, d, acc[13]);
-    acc[14] = fma(dd, bb, acc[14]);
-    acc[15] = fma(dd, d, acc[15]);
-    if constexpr (NVX == NV) {
-        const double c2 = aa + b2 + dd;
-        acc[16] = fma(aa, c2, acc[16]); acc[17] = fma(ab, c2, acc[17]); acc[18] = fma(ad, c2, acc[18]);
-        acc[19] = fma(b2, c2, acc[19]); acc[20] = fma(bd, c2, acc[20]); acc[21] = fma(dd, c2, acc[21]);
-        const double c4 = c2 * c2;
-        acc[22] = fma(c4, a, acc[22]); acc[23] = fma(c4, bb, acc[23]); acc[24] = fma(c4, d, acc[24]);
-        acc[25] = fma(c4, c2, acc[25]);
-    }
+    mom_accum_range<0, NVX>(a, bb, d, acc);
 }
 
 // LDS for the cross-lane sums of one workgroup of BLOCK threads in groups of G lanes
@@ -79,6 +96,39 @@ __device__ __forceinline__ void mom_finish(MomShared<BLOCK, G>& sm, const double
         }
         __syncthreads();
     }
+    if (in)
+        for (int e = lg; e < MOM; e += G) rec[e] = mom_entry<BLOCK, G, NVX>(sm, grp, n, U0, U1, U2, e);
+}
+
+// mom_finish with the monomials accumulated round by round: accum(r0, part) adds the
+// values r0 .. r0 + size(part) of every particle of the lane into part (zero on entry,
+// mom_accum_range<r0>), r0 an std::integral_constant; each round is reduced through LDS
+// before the next one is accumulated, so at most MR accumulators are live.  The same sums,
+// bit for bit, as accumulating all NVX values first.  Every thread of the block must call.
+template <int BLOCK, int G, int NVX, typename Accum>
+__device__ __forceinline__ void mom_finish_rounds(MomShared<BLOCK, G>& sm, Accum&& accum, int grp,
+                                                  int lg, bool in, int32_t n, double U0,
+                                                  double U1, double U2, double* __restrict__ rec) {
+    auto round = [&](auto r0c) __attribute__((always_inline)) {
+        constexpr int R0 = decltype(r0c)::value;
+        constexpr int NR = NVX - R0 < MR ? NVX - R0 : MR;
+        double part[NR];
+#pragma unroll
+        for (int v = 0; v < NR; ++v) part[v] = 0.0;
+        accum(r0c, part);
+#pragma unroll
+        for (int v = 0; v < NR; ++v) sm.red[v][threadIdx.x] = part[v];
+        __syncthreads();
+        for (int v = lg; v < NR; v += G) {
+            double t = 0.0;
+            for (int i = 0; i < G; ++i) t += sm.red[v][grp * G + i];
+            sm.fin[grp][R0 + v] = t;
+        }
+        __syncthreads();
+    };
+    round(std::integral_constant<int, 0>{});
+    if constexpr (NVX > MR) round(std::integral_constant<int, MR>{});
+    if constexpr (NVX > 2 * MR) round(std::integral_constant<int, 2 * MR>{});
     if (in)
         for (int e = lg; e < MOM; e += G) rec[e] = mom_entry<BLOCK, G, NVX>(sm, grp, n, U0, U1, U2, e);
 }
