@@ -1070,29 +1070,21 @@ __global__ __launch_bounds__(BLK) void rebin_gather_mom_kernel(
     s2 = group_sum<G>(s2);
     const double inv_n = ncnt > 0 ? 1.0 / (double)ncnt : 0.0;
     const double U0 = s0 * inv_n, U1 = s1 * inv_n, U2 = s2 * inv_n;
-    // the monomials in rounds of MR (each reduced before the next: fewer live registers)
-    auto accum = [&](auto r0c, auto& part) __attribute__((always_inline)) {
-        constexpr int R0 = decltype(r0c)::value;
-        if (regs) {
-            // an empty asm that "changes" the cached velocities, so that every round
-            // converts and centres them afresh instead of keeping the FP64 values of all
-            // particles live across the rounds
+    double acc[NVX];
 #pragma unroll
-            for (int u = 0; u < GM_U; ++u) asm volatile("" : "+v"(kvx[u]), "+v"(kvy[u]), "+v"(kvz[u]));
+    for (int i = 0; i < NVX; ++i) acc[i] = 0.0;
+    if (regs) {
 #pragma unroll
-            for (int u = 0; u < GM_U; ++u)
-                if (u * G + lg < ncnt)
-                    mom_accum_range<R0>((double)kvx[u] - U0, (double)kvy[u] - U1, (double)kvz[u] - U2,
-                                        part);
-        } else {
-            for (int32_t q = lg; q < ncnt; q += G)
-                mom_accum_range<R0>((double)ld_off(r.dvx, base + q) - U0,
-                                    (double)ld_off(r.dvy, base + q) - U1,
-                                    (double)ld_off(r.dvz, base + q) - U2, part);
-        }
-    };
-    mom_finish_rounds<BLK, G, NVX>(sm, accum, grp, lg, in, ncnt, U0, U1, U2,
-                                   mom + (int64_t)(in ? k : 0) * MOM);
+        for (int u = 0; u < GM_U; ++u)
+            if (u * G + lg < ncnt)
+                mom_accum<NVX>((double)kvx[u] - U0, (double)kvy[u] - U1, (double)kvz[u] - U2, acc);
+    } else {
+        for (int32_t q = lg; q < ncnt; q += G)
+            mom_accum<NVX>((double)ld_off(r.dvx, base + q) - U0, (double)ld_off(r.dvy, base + q) - U1,
+                           (double)ld_off(r.dvz, base + q) - U2, acc);
+    }
+    mom_finish<BLK, G, NVX>(sm, acc, grp, lg, in, ncnt, U0, U1, U2,
+                             mom + (int64_t)(in ? k : 0) * MOM);
     if (samp_cell && lg < 14) {
         // the lane's time-average sums from the record's entries, rebuilt from the final
         // sums in LDS (the values mom_finish stored) instead of reading the record back;

@@ -5,8 +5,6 @@
 #pragma once
 #include "fp_internal.h"
 
-#include <type_traits>
-
 namespace fpg {
 
 constexpr int NV = 26;   // accumulated monomials: P (6), T (10), R (6), W (3), H
@@ -17,8 +15,7 @@ constexpr int MR = 13;   // values per LDS reduction round
 // acc[16..21] R, acc[22..24] W, acc[25] H; FP64 products and sums.  With NVX = NV_LOW
 // only P and T are accumulated (the same operations, in the same order).
 // The values acc[LO .. LO + N) of the above into o[0 .. N): the same operations in the same
-// order as for the whole set, so that a gather may accumulate the monomials in rounds (fewer
-// live accumulators) with sums bit for bit those of one pass.
+// order as for the whole set (a subset of the monomials gives the same sums bit for bit).
 template <int LO, int N>
 __device__ __forceinline__ void mom_accum_range(double a, double bb, double d, double (&o)[N]) {
     const double aa = a * a, ab = a * bb, ad = a * d, b2 = bb * bb, bd = bb * d, dd = d * d;
@@ -96,39 +93,6 @@ __device__ __forceinline__ void mom_finish(MomShared<BLOCK, G>& sm, const double
         }
         __syncthreads();
     }
-    if (in)
-        for (int e = lg; e < MOM; e += G) rec[e] = mom_entry<BLOCK, G, NVX>(sm, grp, n, U0, U1, U2, e);
-}
-
-// mom_finish with the monomials accumulated round by round: accum(r0, part) adds the
-// values r0 .. r0 + size(part) of every particle of the lane into part (zero on entry,
-// mom_accum_range<r0>), r0 an std::integral_constant; each round is reduced through LDS
-// before the next one is accumulated, so at most MR accumulators are live.  The same sums,
-// bit for bit, as accumulating all NVX values first.  Every thread of the block must call.
-template <int BLOCK, int G, int NVX, typename Accum>
-__device__ __forceinline__ void mom_finish_rounds(MomShared<BLOCK, G>& sm, Accum&& accum, int grp,
-                                                  int lg, bool in, int32_t n, double U0,
-                                                  double U1, double U2, double* __restrict__ rec) {
-    auto round = [&](auto r0c) __attribute__((always_inline)) {
-        constexpr int R0 = decltype(r0c)::value;
-        constexpr int NR = NVX - R0 < MR ? NVX - R0 : MR;
-        double part[NR];
-#pragma unroll
-        for (int v = 0; v < NR; ++v) part[v] = 0.0;
-        accum(r0c, part);
-#pragma unroll
-        for (int v = 0; v < NR; ++v) sm.red[v][threadIdx.x] = part[v];
-        __syncthreads();
-        for (int v = lg; v < NR; v += G) {
-            double t = 0.0;
-            for (int i = 0; i < G; ++i) t += sm.red[v][grp * G + i];
-            sm.fin[grp][R0 + v] = t;
-        }
-        __syncthreads();
-    };
-    round(std::integral_constant<int, 0>{});
-    if constexpr (NVX > MR) round(std::integral_constant<int, MR>{});
-    if constexpr (NVX > 2 * MR) round(std::integral_constant<int, 2 * MR>{});
     if (in)
         for (int e = lg; e < MOM; e += G) rec[e] = mom_entry<BLOCK, G, NVX>(sm, grp, n, U0, U1, U2, e);
 }
