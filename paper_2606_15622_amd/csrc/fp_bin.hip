@@ -945,13 +945,13 @@ __global__ __launch_bounds__(BLK) void rebin_gather_mom_kernel(
         }
     }
     __syncthreads();
-    if (lg == 0) {
+    // bucket starts in the cell's concatenation: lane q adds up the lengths before bucket q
+    // (ten lanes at once instead of one lane walking the nine buckets)
+    for (int q = lg; q < 10; q += G) {
         int32_t acc = 0;
-        for (int q = 0; q < 9; ++q) {
-            s_pre[grp][q] = acc;
-            acc += s_run[grp][q][1];
-        }
-        s_pre[grp][9] = acc;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc += t < q ? s_run[grp][t][1] : 0;
+        s_pre[grp][q] = acc;
     }
     __syncthreads();
     int32_t rs[10];

@@ -73,7 +73,9 @@ __device__ __forceinline__ double mom_entry(const MomShared<BLOCK, G>& sm, int g
 }
 
 // Cross-lane sums of acc over the group (lane v adds the partials of value v in lane
-// order, MR values per round), then the record of the cell, one entry per lane:
+// order, MR values per round; with 32 or more lanes per group two stripes of G/2 lanes each
+// add half of the partials and one lane exchange joins the halves: chains of G/2 instead
+// of G dependent adds), then the record of the cell, one entry per lane:
 // N, U, theta, P, T, R, W, H (moments / N; R, W, H zero when only NV_LOW values were
 // accumulated), pad.  Every thread of the block must call.
 template <int BLOCK, int G, int NVX = NV>
@@ -86,10 +88,20 @@ __device__ __forceinline__ void mom_finish(MomShared<BLOCK, G>& sm, const double
         for (int v = 0; v < MR; ++v)
             if (r0 + v < NVX) sm.red[v][threadIdx.x] = acc[r0 + v];
         __syncthreads();
-        for (int v = lg; v < MR && r0 + v < NVX; v += G) {
+        if constexpr (G >= 32) {
+            constexpr int H = G / 2;   // stripe width, at least MR
+            const int v = lg % H, h = lg / H;
             double t = 0.0;
-            for (int i = 0; i < G; ++i) t += sm.red[v][grp * G + i];
-            sm.fin[grp][r0 + v] = t;
+            if (v < MR && r0 + v < NVX)
+                for (int i = 0; i < H; ++i) t += sm.red[v][grp * G + h * H + i];
+            t += __shfl_xor(t, H, 64);
+            if (h == 0 && v < MR && r0 + v < NVX) sm.fin[grp][r0 + v] = t;
+        } else {
+            for (int v = lg; v < MR && r0 + v < NVX; v += G) {
+                double t = 0.0;
+                for (int i = 0; i < G; ++i) t += sm.red[v][grp * G + i];
+                sm.fin[grp][r0 + v] = t;
+            }
         }
         __syncthreads();
     }
