@@ -35,22 +35,25 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_wave_kernel(
             k = ncell;  // dropped
         }                // k == ncell: deleted particle, dropped
     }
-    uint64_t active = __ballot(valid);
+    // the lanes of each distinct key: its lowest lane leads and keeps the mask; the leaders'
+    // atomics then go out together (one round trip per wave, not one per key in turn)
+    uint64_t active = __ballot(valid), mine = 0;
     while (active) {
         const int leader = __builtin_ctzll(active);
         const int32_t kl = __builtin_amdgcn_readlane(k, leader);
         const uint64_t m = __ballot(valid && k == kl);
-        if (lane == leader && kl < ncell) {
-            if (PLACE) {
-                const int32_t slot = coff[kl] + atomicAdd(&ccur[kl], 1);
-                cwave[slot] = wave;
-                cmask[slot] = m;
-            } else {
-                atomicAdd(&cnt[kl], __popcll(m));
-                atomicAdd(&ccnt[kl], 1);
-            }
-        }
+        if (lane == leader) mine = m;
         active &= ~m;
+    }
+    if (mine && k < ncell) {
+        if (PLACE) {
+            const int32_t slot = coff[k] + atomicAdd(&ccur[k], 1);
+            cwave[slot] = wave;
+            cmask[slot] = mine;
+        } else {
+            atomicAdd(&cnt[k], __popcll(mine));
+            atomicAdd(&ccnt[k], 1);
+        }
     }
 }
 

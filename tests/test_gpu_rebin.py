@@ -151,6 +151,7 @@ def test_crowded_and_empty_cells():
     w = I.cavity(ncell=12, precision="f32")
     counts = np.zeros(144, dtype=np.int64)
     counts[[5, 6, 77]] = [3000, 1, 4500]
+    counts[[20, 21, 22, 23]] = [256, 257, 200, 129]   # the re-sort's mask limits
     counts[100:110] = 7
     vx, vy, vz, off0 = I.mixture_cells(counts, seed=8, precision="f32")
     n = int(off0[-1])
