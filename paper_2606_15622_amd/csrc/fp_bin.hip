@@ -268,32 +268,64 @@ __global__ __launch_bounds__(GatherShape<G>::BLK) void bin_gather_kernel(
     }
     __syncthreads();
 
-    // phase C: every lane takes slots; the source of slot s is the r-th lane of the
-    // contribution whose range [base, base + count) holds s
-    for (int32_t s = lg; s < np; s += G) {
-        int32_t p;
+    // phase C: every lane takes slots, U per round (slots s0 + u G + lg); the source of slot
+    // s is the r-th lane of the contribution whose range [base, base + count) holds s, found
+    // for the round's U slots in one pass over the contributions; then all of the round's
+    // loads, then its stores
+    constexpr int U = 4;
+    for (int32_t s0 = 0; s0 < np; s0 += G * U) {
+        int32_t src[U];
         if (lds_c) {
-            int32_t j = 0, r = 0;
+            int32_t jj[U], rr[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) jj[u] = rr[u] = 0;
             for (int32_t i = 0; i < m; ++i) {
-                const int32_t bi = s_base[grp][i];
-                if (s >= bi && s < bi + __popcll(s_m[grp][i])) {
-                    j = i;
-                    r = s - bi;
+                const int32_t bi = s_base[grp][i], ci = __popcll(s_m[grp][i]);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t sl = s0 + u * G + lg;
+                    if (sl >= bi && sl < bi + ci) {
+                        jj[u] = i;
+                        rr[u] = sl - bi;
+                    }
                 }
             }
-            p = (s_w[grp][j] << 6) + select_bit(s_m[grp][j], r);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                src[u] = s0 + u * G + lg < np ? (s_w[grp][jj[u]] << 6) + select_bit(s_m[grp][jj[u]], rr[u]) : -1;
         } else {
-            p = gidx[b + s];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t sl = s0 + u * G + lg;
+                src[u] = sl < np ? gidx[b + sl] : -1;
+            }
         }
-        const int32_t d = b + s;
-        dx[d] = sx[p];
-        if (sy) dy[d] = sy[p];
-        dvx[d] = svx[p];
-        dvy[d] = svy[p];
-        dvz[d] = svz[p];
-        dpid[d] = spid[p];
-        dkey[d] = cell;
-        if (perm) perm[d] = p;
+        T rx[U], ry[U], rvx[U], rvy[U], rvz[U];
+        uint32_t rp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (src[u] < 0) continue;
+            const int32_t q = src[u];
+            rx[u] = sx[q];
+            ry[u] = sy ? sy[q] : (T)0;
+            rvx[u] = svx[q];
+            rvy[u] = svy[q];
+            rvz[u] = svz[q];
+            rp[u] = spid[q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (src[u] < 0) continue;
+            const int32_t d = b + s0 + u * G + lg;
+            dx[d] = rx[u];
+            if (sy) dy[d] = ry[u];
+            dvx[d] = rvx[u];
+            dvy[d] = rvy[u];
+            dvz[d] = rvz[u];
+            dpid[d] = rp[u];
+            dkey[d] = cell;
+            if (perm) perm[d] = src[u];
+        }
     }
 }
 
