@@ -178,6 +178,15 @@ int fp_rebin(fp_ctx* ctx, const fp_particles* src, const int32_t* src_offsets,
  * eq. system9x9 and Table matrix_system; layout mom above). */
 int fp_moments(fp_ctx* ctx, const fp_particles* p, const int32_t* offsets, double* mom,
                hipStream_t s);
+/* fp_moments and fp_sample in one pass (the "average_results" step of Algorithm "Baseline
+ * Physics Simulation Loop" on the freshly gathered moments): mom as fp_moments writes it,
+ * and its raw sums added to samp0 and, when samp1 is not NULL, to samp1, bit for bit as
+ * fp_sample(mom, samp0) and fp_sample(mom, samp1) would add them (layout samp above; a loop
+ * that keeps two sets of sums, e.g. the quadtree's adaptation sums beside the output
+ * averages, reads the records once).  samp0 is required, samp1 must differ from it;
+ * FP_EINVAL otherwise. */
+int fp_moments_sample(fp_ctx* ctx, const fp_particles* p, const int32_t* offsets, double* mom,
+                      double* samp0, double* samp1, hipStream_t s);
 
 /* Exact closure of every cell: the 9x9 moment-matching system (eq. system9x9, Table
  * matrix_system) in theta-normalised form, solved by LU with partial pivoting in FP64;

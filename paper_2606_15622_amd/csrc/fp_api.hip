@@ -278,7 +278,14 @@ extern "C" int fp_moments(fp_ctx* c, const fp_particles* p, const int32_t* offse
                           hipStream_t s) {
     if (!c || !offsets || !mom || !particles_ok(c, p, false))
         return set_err(c, FP_EINVAL, "fp_moments: bad argument");
-    return launch_moments(c, p, offsets, mom, s);
+    return launch_moments(c, p, offsets, mom, nullptr, nullptr, s);
+}
+
+extern "C" int fp_moments_sample(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,
+                                 double* samp0, double* samp1, hipStream_t s) {
+    if (!c || !offsets || !mom || !samp0 || samp1 == samp0 || !particles_ok(c, p, false))
+        return set_err(c, FP_EINVAL, "fp_moments_sample: bad argument");
+    return launch_moments(c, p, offsets, mom, samp0, samp1, s);
 }
 
 extern "C" int fp_closure_solve(fp_ctx* c, const double* mom, double* rec, int32_t* status,

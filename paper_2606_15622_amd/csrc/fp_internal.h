@@ -258,7 +258,7 @@ int launch_high_order(fp_ctx* c, const double* hsamp, double* out, hipStream_t s
 int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_particles* dst,
                  int32_t* offsets, int32_t* perm, double* mom, double* samp, hipStream_t s);
 int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,
-                   hipStream_t s);
+                   double* samp0, double* samp1, hipStream_t s);
 int launch_closure(fp_ctx* c, const double* mom, double* rec, int32_t* status, hipStream_t s);
 int launch_inject(fp_ctx* c, fp_particles* p, int64_t at, uint32_t* pid_next, uint32_t step,
                   const uint32_t* step_dev, uint32_t* advance, hipStream_t s);

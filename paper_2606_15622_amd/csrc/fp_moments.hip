@@ -9,16 +9,23 @@
 // sums: the mean by DPP inside the group, the 26 monomial sums through LDS (lane v adds
 // the partials of value v in lane order); fixed orders, so results are deterministic.
 #include "fp_mom_dev.h"
+#include "fp_sample_dev.h"
 
 namespace fpg {
 
-constexpr int MOM_BLOCK = 256;
+// one-wave workgroups: the moment reduction's LDS (MomShared) then takes 7 KB per wave
+// instead of 33 KB per four, and no longer caps the resident waves
+constexpr int MOM_BLOCK = 64;
 constexpr int MOM_K = 8;
 
+// samp0, samp1 (optional): time-average sums that also receive the cell's record, added
+// exactly as fp_sample adds them (lanes 0..13 of the group, one sum each, rebuilt from the
+// final sums in LDS instead of the stored record)
 template <typename T, int G, int K, int NVX>
 __global__ __launch_bounds__(MOM_BLOCK) void moments_kernel(
     int32_t ncell, const int32_t* __restrict__ offsets, const T* __restrict__ vx,
-    const T* __restrict__ vy, const T* __restrict__ vz, double* __restrict__ mom) {
+    const T* __restrict__ vy, const T* __restrict__ vz, double* __restrict__ mom,
+    double* __restrict__ samp0, double* __restrict__ samp1) {
     const int64_t gt = (int64_t)blockIdx.x * MOM_BLOCK + threadIdx.x;
     const int32_t cell = (int32_t)(gt / G);
     const int lg = (int)(gt % G);
@@ -64,44 +71,71 @@ __global__ __launch_bounds__(MOM_BLOCK) void moments_kernel(
     for (int32_t j = lg + K * G; j < n; j += G)
         mom_accum<NVX>((double)vx[b + j] - U0, (double)vy[b + j] - U1, (double)vz[b + j] - U2, acc);
     __shared__ MomShared<MOM_BLOCK, G> sm;
-    mom_finish<MOM_BLOCK, G, NVX>(sm, acc, (int)(threadIdx.x / G), lg, in, n, U0, U1, U2,
-                             mom + (int64_t)(in ? cell : 0) * MOM);
+    const int grp = (int)(threadIdx.x / G);
+    mom_finish<MOM_BLOCK, G, NVX>(sm, acc, grp, lg, in, n, U0, U1, U2, mom + (int64_t)(in ? cell : 0) * MOM);
+    if (in && (samp0 || samp1)) {
+        // every term with a compile-time entry index (no indexed access to m), the lane's
+        // own ones kept
+        constexpr int SQ = (14 + G - 1) / G;
+        double m[M_T + 10];
+#pragma unroll
+        for (int e = 0; e < M_T + 10; ++e) m[e] = mom_entry<MOM_BLOCK, G, NVX>(sm, grp, n, U0, U1, U2, e);
+        double t[SQ];
+#pragma unroll
+        for (int u = 0; u < SQ; ++u) t[u] = 0.0;
+#pragma unroll
+        for (int e = 0; e < 14; ++e) {
+            const double v = sample_term(m, e);
+#pragma unroll
+            for (int u = 0; u < SQ; ++u) t[u] = lg + u * G == e ? v : t[u];
+        }
+#pragma unroll
+        for (int u = 0; u < SQ; ++u) {
+            const int e = lg + u * G;
+            if (e >= 14) continue;
+            const int64_t at = (int64_t)cell * SAMP + e;
+            if (samp0) samp0[at] = samp0[at] + t[u];
+            if (samp1) samp1[at] = samp1[at] + t[u];
+        }
+    }
 }
 
 template <typename T, int G>
 static void mom_launch(fp_ctx* c, const fp_particles* p, const int32_t* off, double* mom,
-                       hipStream_t s) {
+                       double* samp0, double* samp1, hipStream_t s) {
     const int64_t threads = (int64_t)c->ncell * G;
     const unsigned grid = (unsigned)((threads + MOM_BLOCK - 1) / MOM_BLOCK);
     if (c->cfg.moment_order == 3)
         hipLaunchKernelGGL((moments_kernel<T, G, MOM_K, NV_LOW>), dim3(grid), dim3(MOM_BLOCK), 0, s,
-                           c->ncell, off, (const T*)p->vx, (const T*)p->vy, (const T*)p->vz, mom);
+                           c->ncell, off, (const T*)p->vx, (const T*)p->vy, (const T*)p->vz, mom, samp0,
+                           samp1);
     else
         hipLaunchKernelGGL((moments_kernel<T, G, MOM_K, NV>), dim3(grid), dim3(MOM_BLOCK), 0, s,
-                           c->ncell, off, (const T*)p->vx, (const T*)p->vy, (const T*)p->vz, mom);
+                           c->ncell, off, (const T*)p->vx, (const T*)p->vy, (const T*)p->vz, mom, samp0,
+                           samp1);
 }
 
 template <typename T>
 static void mom_dispatch(fp_ctx* c, const fp_particles* p, const int32_t* off, double* mom,
-                         hipStream_t s) {
+                         double* samp0, double* samp1, hipStream_t s) {
     // about five particles per lane (the smallest width with 4.8 G >= mean count): on
     // cells of 24, 52 and 150 particles 8, 16 and 32 lanes beat their neighbours
     switch (lanes_per_cell(c, p->n, 0, 6)) {
-        case 4: mom_launch<T, 4>(c, p, off, mom, s); break;
-        case 8: mom_launch<T, 8>(c, p, off, mom, s); break;
-        case 16: mom_launch<T, 16>(c, p, off, mom, s); break;
-        case 32: mom_launch<T, 32>(c, p, off, mom, s); break;
-        default: mom_launch<T, 64>(c, p, off, mom, s); break;
+        case 4: mom_launch<T, 4>(c, p, off, mom, samp0, samp1, s); break;
+        case 8: mom_launch<T, 8>(c, p, off, mom, samp0, samp1, s); break;
+        case 16: mom_launch<T, 16>(c, p, off, mom, samp0, samp1, s); break;
+        case 32: mom_launch<T, 32>(c, p, off, mom, samp0, samp1, s); break;
+        default: mom_launch<T, 64>(c, p, off, mom, samp0, samp1, s); break;
     }
 }
 
 int launch_moments(fp_ctx* c, const fp_particles* p, const int32_t* offsets, double* mom,
-                   hipStream_t s) {
+                   double* samp0, double* samp1, hipStream_t s) {
     if (c->cfg.precision == FP_F32)
-        mom_dispatch<float>(c, p, offsets, mom, s);
+        mom_dispatch<float>(c, p, offsets, mom, samp0, samp1, s);
     else
-        mom_dispatch<double>(c, p, offsets, mom, s);
-    return check_launch(c, "fp_moments");
+        mom_dispatch<double>(c, p, offsets, mom, samp0, samp1, s);
+    return check_launch(c, samp0 || samp1 ? "fp_moments_sample" : "fp_moments");
 }
 
 }  // namespace fpg

@@ -15,7 +15,7 @@
 namespace fpg {
 
 constexpr int ST_BLOCK = 256;
-constexpr int ST_K = 8;
+constexpr int ST_K = 2;   // register-cached particles per lane in collide_kernel
 
 struct Walls {
     double lo[2], hi[2];
@@ -596,10 +596,11 @@ static void collide_launch(fp_ctx* c, fp_particles* p, const int32_t* off, const
                            uint32_t* adv, hipStream_t s) {
     const int64_t threads = (int64_t)c->ncell * G;
     const unsigned grid = (unsigned)((threads + ST_BLOCK - 1) / ST_BLOCK);
-    // register cache of c* (and of the positions): 8 particles per lane, 4 with 32 lanes
-    // per cell, 2 with a whole wave per cell (about 2 particles per lane there; fewer
-    // registers, more resident waves: 70 VGPRs, 7 waves per SIMD)
-    constexpr int K = G >= 64 ? ST_K / 4 : (G >= 32 ? ST_K / 2 : ST_K);
+    // register cache of c* (and of the positions): ST_K particles per lane, as many as the
+    // lane widths of collide_dispatch give a lane on average; particles beyond it keep c* in
+    // the velocity arrays.  A larger cache costs registers and resident waves (8 per lane
+    // on the quadtree's 24-particle leaves at 16 lanes: 1.88 against 1.81 ms per step)
+    constexpr int K = ST_K;
     hipLaunchKernelGGL((collide_kernel<T, G, K, GEOM>), dim3(grid), dim3(ST_BLOCK), 0, s,
                        c->cfg, c->ncell, off, mom, rec, (T*)p->x, (T*)p->y, (T*)p->vx, (T*)p->vy,
                        (T*)p->vz, p->pid, p->key, step, move, stepp, c->pend, c->bidx,

@@ -79,6 +79,7 @@ def load():
         L.fp_bin.argtypes = [vp, P(FPParticles), P(FPParticles), vp, vp, vp]
         L.fp_rebin.argtypes = [vp, P(FPParticles), vp, P(FPParticles), vp, vp, vp, vp, vp]
         L.fp_moments.argtypes = [vp, P(FPParticles), vp, vp, vp]
+        L.fp_moments_sample.argtypes = [vp, P(FPParticles), vp, vp, vp, vp, vp]
         L.fp_closure_solve.argtypes = [vp, vp, vp, vp, vp]
         L.fp_step.argtypes = [vp, P(FPParticles), vp, vp, vp, u64, u32, vp]
         L.fp_sample.argtypes = [vp, vp, vp, vp]
@@ -132,7 +133,7 @@ def load():
         L.fp_lite_train_step.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float, vp, vp, i64, vp, vp]
         L.fp_closure_solve_backward.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fp_moments_backward.argtypes = [vp, P(FPParticles), vp, vp, vp, vp, vp, vp, vp]
-        for f in ("fp_bin", "fp_rebin", "fp_moments", "fp_closure_solve", "fp_step", "fp_sample", "fp_nn_create",
+        for f in ("fp_bin", "fp_rebin", "fp_moments", "fp_moments_sample", "fp_closure_solve", "fp_step", "fp_sample", "fp_nn_create",
                   "fp_nn_load", "fp_closure_nn", "fp_closure_nn_noalloc", "fp_nn_outputs", "fp_nn_infer", "fp_nn_sensitivity", "fp_nn_features",
                   "fp_closure_build", "fp_nn_grad", "fp_nn_adam", "fp_nn_train_step",
                   "fp_nn_targets", "fp_closure_solve_backward", "fp_moments_backward",
@@ -303,6 +304,12 @@ class Context:
         a = p.struct()
         self._check(self.lib.fp_moments(self.h, C.byref(a), _ptr(offsets), _ptr(mom),
                                         _stream(stream)), "fp_moments")
+
+    def moments_sample(self, p, offsets, mom, samp0, samp1=None, stream=None):
+        a = p.struct()
+        self._check(self.lib.fp_moments_sample(self.h, C.byref(a), _ptr(offsets), _ptr(mom), _ptr(samp0),
+                                               _ptr(samp1),
+                                               _stream(stream)), "fp_moments_sample")
 
     def closure_solve(self, mom, rec, status, stream=None):
         self._check(self.lib.fp_closure_solve(self.h, _ptr(mom), _ptr(rec), _ptr(status),
@@ -494,10 +501,8 @@ class AMRSimulation:
         self.ctx.bin(self.a, self.b, self.offs[1])
         self.offs.reverse()
         self.a, self.b = self.b, self.a
-        self.ctx.moments(self.a, self.offs[0], self.mom)
-        self.ctx.sample(self.mom, self.acc)
-        if sample:
-            self.ctx.sample(self.mom, self.samp)
+        # moments, the adaptation sums and (when sampling) the output sums in one pass
+        self.ctx.moments_sample(self.a, self.offs[0], self.mom, self.acc, self.samp if sample else None)
         if closure is None:
             self.ctx.closure_solve(self.mom, self.rec, self.status)
         else:
@@ -688,8 +693,8 @@ class Simulation:
         """a -> b sorted by key (fp_rebin from the previous grouping after the first
         step, fp_bin before), then swap a and b; offsets describe the new a.  With mom,
         the moments of the sorted cells are written too, and with samp their time-average
-        sums are added (by the re-sort itself, or by fp_moments and fp_sample after the
-        first sort)."""
+        sums are added (by the re-sort itself, or by fp_moments_sample after the first
+        sort)."""
         if self.sorted:
             self.ctx.rebin(self.a, self.offs[0], self.b, self.offs[1], perm, mom, samp)
         else:
@@ -697,9 +702,10 @@ class Simulation:
         self.offs.reverse()
         self.a, self.b = self.b, self.a
         if mom is not None and not self.sorted:
-            self.ctx.moments(self.a, self.offsets, mom)
             if samp is not None:
-                self.ctx.sample(mom, samp)
+                self.ctx.moments_sample(self.a, self.offsets, mom, samp)
+            else:
+                self.ctx.moments(self.a, self.offsets, mom)
         self.sorted = True
 
     def step(self, s, sample=False):
@@ -802,9 +808,10 @@ class OpenSimulation:
         self.sorted = True
         self.a, self.b = self.b, self.a
         if not fused:
-            self.ctx.moments(self.a, self.offsets, self.mom)
             if sample:
-                self.ctx.sample(self.mom, self.samp)
+                self.ctx.moments_sample(self.a, self.offsets, self.mom, self.samp)
+            else:
+                self.ctx.moments(self.a, self.offsets, self.mom)
         if closure is None:
             self.ctx.closure_solve(self.mom, self.rec, self.status)
         else:

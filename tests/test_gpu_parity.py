@@ -168,6 +168,45 @@ def test_moments_parity(prec):
     assert np.all(np.abs(g - o) <= 1e-10 * scale)
 
 
+@pytest.mark.parametrize("prec,counts", [("f32", MIX_COUNTS), ("f64", MIX_COUNTS),
+                                         ("f32", "leaves"), ("f64", "leaves")])
+def test_moments_sample_is_moments_then_sample(prec, counts):
+    """fp_moments_sample: the records of fp_moments and the sums of fp_sample on each of the
+    two sets, bit for bit, also without the second set; the mixed counts take 32-lane
+    groups, cells of about 24 particles (the quadtree's leaves) 8-lane groups."""
+    F = fp()
+    if counts == "leaves":
+        counts = list(np.random.default_rng(5).poisson(24, 3000))
+    nc = len(counts)
+    w = I.cavity(ncell=4, precision=prec)
+    w["nx"], w["ny"] = nc, 1
+    s, off = _sorted_state(w, counts, seed=8)
+    ctx = F.Context(w, max(int(off[-1]), 1))
+    p = F.Particles.from_numpy(w, s)
+    offd = dev(off, torch.int32)
+    rng = np.random.default_rng(6)
+    s0 = dev(rng.uniform(0.0, 1e3, (nc, 16)), torch.float64)
+    s1 = dev(rng.uniform(0.0, 1e3, (nc, 16)), torch.float64)
+    ref_mom = torch.zeros((nc, 32), dtype=torch.float64, device="cuda")
+    ctx.moments(p, offd, ref_mom)
+    r0, r1 = s0.clone(), s1.clone()
+    ctx.sample(ref_mom, r0)
+    ctx.sample(ref_mom, r1)
+    mom = torch.full((nc, 32), -7.0, dtype=torch.float64, device="cuda")
+    ctx.moments_sample(p, offd, mom, s0, s1)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(cpu(mom), cpu(ref_mom))
+    np.testing.assert_array_equal(cpu(s0), cpu(r0))
+    np.testing.assert_array_equal(cpu(s1), cpu(r1))
+    ctx.moments_sample(p, offd, mom, s0)   # one set only
+    ctx.sample(ref_mom, r0)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(cpu(s0), cpu(r0))
+    np.testing.assert_array_equal(cpu(s1), cpu(r1))
+    with pytest.raises(Exception):
+        ctx.moments_sample(p, offd, mom, s0, s0)
+
+
 def _mixture_moments(counts, seed):
     vx, vy, vz, off = I.mixture_cells(counts, seed=seed)
     return O.moments(off, vx, vy, vz), (vx, vy, vz, off)
