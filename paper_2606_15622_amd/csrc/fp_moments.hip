@@ -35,6 +35,16 @@ __global__ __launch_bounds__(MOM_BLOCK) void moments_kernel(
         b = offsets[cell];
         n = offsets[cell + 1] - b;
     }
+    // the sums to update, loaded now (their latency hides behind the velocities')
+    constexpr int SQ = (14 + G - 1) / G;
+    double sv0[SQ], sv1[SQ];
+#pragma unroll
+    for (int u = 0; u < SQ; ++u) {
+        const int e = lg + u * G;
+        const int64_t at = (int64_t)cell * SAMP + e;
+        sv0[u] = in && samp0 && e < 14 ? samp0[at] : 0.0;
+        sv1[u] = in && samp1 && e < 14 ? samp1[at] : 0.0;
+    }
     T cx[K], cy[K], cz[K];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
@@ -76,7 +86,6 @@ __global__ __launch_bounds__(MOM_BLOCK) void moments_kernel(
     if (in && (samp0 || samp1)) {
         // every term with a compile-time entry index (no indexed access to m), the lane's
         // own ones kept
-        constexpr int SQ = (14 + G - 1) / G;
         double m[M_T + 10];
 #pragma unroll
         for (int e = 0; e < M_T + 10; ++e) m[e] = mom_entry<MOM_BLOCK, G, NVX>(sm, grp, n, U0, U1, U2, e);
@@ -94,8 +103,8 @@ __global__ __launch_bounds__(MOM_BLOCK) void moments_kernel(
             const int e = lg + u * G;
             if (e >= 14) continue;
             const int64_t at = (int64_t)cell * SAMP + e;
-            if (samp0) samp0[at] = samp0[at] + t[u];
-            if (samp1) samp1[at] = samp1[at] + t[u];
+            if (samp0) samp0[at] = sv0[u] + t[u];
+            if (samp1) samp1[at] = sv1[u] + t[u];
         }
     }
 }
