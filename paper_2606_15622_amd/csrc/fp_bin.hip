@@ -347,10 +347,11 @@ static void gather_launch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
 template <typename T>
 static void gather_dispatch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
                             const int32_t* offsets, int32_t* perm, hipStream_t s) {
-    // about two particles per lane, at most 32: the per-cell work (ordering the
-    // contributions, expanding their masks) shortens with wider groups (on 7.6e5 cells of
-    // 24 particles 1.41 ms at 16 lanes against 2.17 ms at 4)
-    int g = lanes_per_cell(c, src->n, FILL_8, 2);
+    // about one particle per lane, at most 32: the per-cell work (ordering the
+    // contributions, expanding their masks) shortens with wider groups (the quadtree
+    // cylinder's loop on 7.6e5 leaves of 24 particles: 1.68 ms per step at 32 lanes, 1.70 at
+    // 16, 1.91 at 8)
+    int g = lanes_per_cell(c, src->n, FILL_8, 1);
     if (c->cfg.lanes <= 0 && g > 32) g = 32;
     switch (g) {
         case 4: gather_launch<T, 4>(c, src, dst, offsets, perm, s); break;
