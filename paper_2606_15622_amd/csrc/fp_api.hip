@@ -139,7 +139,8 @@ extern "C" int fp_init(const fp_config* cfg, fp_ctx** out) {
     const size_t nc = (size_t)c->ncell + 1;
     const size_t cap = (size_t)cfg->capacity;
     bool ok = dalloc(&c->cnt, nc) && dalloc(&c->ccnt, nc) && dalloc(&c->coff, nc + 1) &&
-              dalloc(&c->ccur, nc) && dalloc(&c->cwave, cap) && dalloc(&c->cmask, cap) &&
+              dalloc(&c->ccur, nc) && dalloc(&c->cpair, 2 * nc) && dalloc(&c->cwave, cap) &&
+              dalloc(&c->cmask, cap) &&
               dalloc(&c->gidx, cap) && dalloc(&c->blocksum, 2 * 8192) &&
               dalloc(&c->errcount, 2) && dalloc(&c->ncnt, 9 * (nc - 1) + 1) && dalloc(&c->farn, 1) &&
               dalloc(&c->bidx, cap) && dalloc(&c->pend, nc) && dalloc(&c->stepc, 1);
@@ -148,6 +149,7 @@ extern "C" int fp_init(const fp_config* cfg, fp_ctx** out) {
                  hipMemset(c->cnt, 0, sizeof(int32_t) * nc) == hipSuccess &&
                  hipMemset(c->ccnt, 0, sizeof(int32_t) * nc) == hipSuccess &&
                  hipMemset(c->ccur, 0, sizeof(int32_t) * nc) == hipSuccess &&
+                 hipMemset(c->cpair, 0, sizeof(int32_t) * 2 * nc) == hipSuccess &&
                  hipMemset(c->farn, 0, sizeof(int32_t)) == hipSuccess &&
                  hipMemset(c->stepc, 0, sizeof(uint32_t)) == hipSuccess;
     if (ok && cfg->geometry == FP_CYLINDER2D) {
@@ -198,6 +200,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     (void)hipFree(c->ccnt);
     (void)hipFree(c->coff);
     (void)hipFree(c->ccur);
+    (void)hipFree(c->cpair);
     (void)hipFree(c->cwave);
     (void)hipFree(c->cmask);
     (void)hipFree(c->gidx);

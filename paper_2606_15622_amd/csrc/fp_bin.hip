@@ -14,12 +14,14 @@ namespace fpg {
 
 constexpr int BIN_BLOCK = 256;
 
-// PLACE = false: count particles and contributions per key.
+// PLACE = false: count particles and contributions per key: cpair[k] holds both counts
+// (particles in its low word, contributions in its high word), so one 64-bit atomic adds
+// a contribution.
 // PLACE = true:  write the contribution records at their slots.
 template <bool PLACE>
 __global__ __launch_bounds__(BIN_BLOCK) void bin_wave_kernel(
     const int32_t* __restrict__ key, int64_t n, const int64_t* __restrict__ n_dev, int32_t ncell,
-    int32_t* __restrict__ cnt, int32_t* __restrict__ ccnt, int32_t* __restrict__ ccur,
+    unsigned long long* __restrict__ cpair, int32_t* __restrict__ ccur,
     const int32_t* __restrict__ coff, int32_t* __restrict__ cwave, uint64_t* __restrict__ cmask,
     unsigned long long* __restrict__ errcount) {
     if (n_dev) n = *n_dev;   // the count kept on the device (the grid covers the slots)
@@ -51,8 +53,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void bin_wave_kernel(
             cwave[slot] = wave;
             cmask[slot] = mine;
         } else {
-            atomicAdd(&cnt[k], __popcll(mine));
-            atomicAdd(&ccnt[k], 1);
+            atomicAdd(&cpair[k], (1ull << 32) | (unsigned long long)__popcll(mine));
         }
     }
 }
@@ -88,8 +89,9 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* sh, int32
     return r;
 }
 
+// a[j st], b[j st]: two arrays, or (st = 2) the two words of interleaved pairs
 __global__ __launch_bounds__(SCAN_BLOCK) void scan_reduce_kernel(
-    const int32_t* __restrict__ a, const int32_t* __restrict__ b, int32_t len,
+    const int32_t* __restrict__ a, const int32_t* __restrict__ b, int32_t st, int32_t len,
     int32_t* __restrict__ bsum) {
     __shared__ int32_t sh[SCAN_BLOCK];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
@@ -97,8 +99,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_reduce_kernel(
     for (int i = 0; i < SCAN_ITEMS; ++i) {
         const int64_t j = base + (int64_t)i * SCAN_BLOCK + threadIdx.x;
         if (j < len) {
-            sa += a[j];
-            sb += b[j];
+            sa += a[j * st];
+            sb += b[j * st];
         }
     }
     int32_t ta, tb;
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_blocks_kernel(int32_t* __rest
 
 // item-contiguous per thread: thread t owns SCAN_ITEMS consecutive elements of the tile
 __global__ __launch_bounds__(SCAN_BLOCK) void scan_final_kernel(
-    const int32_t* __restrict__ a, const int32_t* __restrict__ b, int32_t len,
+    const int32_t* __restrict__ a, const int32_t* __restrict__ b, int32_t st, int32_t len,
     const int32_t* __restrict__ bsum, int32_t nblocks, int32_t* __restrict__ outa,
     int32_t* __restrict__ outb) {
     __shared__ int32_t sh[SCAN_BLOCK];
@@ -141,8 +143,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_final_kernel(
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) {
         const int64_t j = base + i;
-        va[i] = j < len ? a[j] : 0;
-        vb[i] = j < len ? b[j] : 0;
+        va[i] = j < len ? a[j * st] : 0;
+        vb[i] = j < len ? b[j * st] : 0;
         sa += va[i];
         sb += vb[i];
     }
@@ -202,8 +204,7 @@ template <typename T, int G>
 __global__ __launch_bounds__(GatherShape<G>::BLK) void bin_gather_kernel(
     int32_t ncell, const int32_t* __restrict__ offsets, const int32_t* __restrict__ coff,
     const int32_t* __restrict__ cwave, const uint64_t* __restrict__ cmask,
-    int32_t* __restrict__ cnt, int32_t* __restrict__ ccnt, int32_t* __restrict__ ccur,
-    int32_t* __restrict__ gidx, const T* __restrict__ sx, const T* __restrict__ sy,
+    unsigned long long* __restrict__ cpair, int32_t* __restrict__ ccur, int32_t* __restrict__ gidx, const T* __restrict__ sx, const T* __restrict__ sy,
     const T* __restrict__ svx, const T* __restrict__ svy, const T* __restrict__ svz,
     const uint32_t* __restrict__ spid, T* __restrict__ dx, T* __restrict__ dy,
     T* __restrict__ dvx, T* __restrict__ dvy, T* __restrict__ dvz, uint32_t* __restrict__ dpid,
@@ -217,8 +218,7 @@ __global__ __launch_bounds__(GatherShape<G>::BLK) void bin_gather_kernel(
     // counters of the count and place passes are spent: leave them zero for the next call
     for (int64_t i = (int64_t)blockIdx.x * S::BLK + threadIdx.x; i <= ncell;
          i += (int64_t)gridDim.x * S::BLK) {
-        cnt[i] = 0;
-        ccnt[i] = 0;
+        cpair[i] = 0ull;
         ccur[i] = 0;
     }
     const int grp = threadIdx.x / G;
@@ -336,7 +336,7 @@ static void gather_launch(fp_ctx* c, const fp_particles* src, fp_particles* dst,
     const int grid = (c->ncell + groups - 1) / groups;
     const bool two_d = c->cfg.geometry != FP_COUETTE1D;
     hipLaunchKernelGGL((bin_gather_kernel<T, G>), dim3(grid), dim3(GatherShape<G>::BLK), 0, s, c->ncell,
-                       offsets, c->coff, c->cwave, c->cmask, c->cnt, c->ccnt, c->ccur, c->gidx,
+                       offsets, c->coff, c->cwave, c->cmask, (unsigned long long*)c->cpair, c->ccur, c->gidx,
                        (const T*)src->x,
                        two_d ? (const T*)src->y : (const T*)nullptr, (const T*)src->vx,
                        (const T*)src->vy, (const T*)src->vz, src->pid, (T*)dst->x,
@@ -1234,9 +1234,9 @@ static void rebin_typed(fp_ctx* c, const fp_particles* src, const int32_t* src_o
     } else {
         const int32_t nblocks = (nc + SCAN_TILE - 1) / SCAN_TILE;
         hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt,
-                           nc, c->blocksum);
+                           1, nc, c->blocksum);
         hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(SCAN_BLOCK), 0, s, c->blocksum, nblocks);
-        hipLaunchKernelGGL(scan_final_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt, nc,
+        hipLaunchKernelGGL(scan_final_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt, 1, nc,
                            c->blocksum, nblocks, offsets, c->coff);
         hipLaunchKernelGGL(rebin_far_place_kernel, dim3(FAR_BLOCKS), dim3(BIN_BLOCK), 0, s,
                            (int64_t)c->cfg.capacity, (const int32_t*)c->farn, (const uint64_t*)c->cmask,
@@ -1264,25 +1264,25 @@ int launch_rebin(fp_ctx* c, const fp_particles* src, const int32_t* src_off, fp_
 
 int launch_bin(fp_ctx* c, const fp_particles* src, fp_particles* dst, int32_t* offsets,
                int32_t* perm, hipStream_t s) {
-    // cnt, ccnt and ccur are zero on entry (fp_init, and every fp_bin/fp_rebin leaves them so)
+    // cpair and ccur are zero on entry (fp_init, and every fp_bin leaves them so)
     const int32_t nc = c->ncell;
     const int64_t n = src->n, slots = slots_of(src);
     const int64_t pgrid = (slots + BIN_BLOCK - 1) / BIN_BLOCK;
     if (slots > 0)
         hipLaunchKernelGGL(bin_wave_kernel<false>, dim3((unsigned)pgrid), dim3(BIN_BLOCK), 0, s,
-                           src->key, n, (const int64_t*)src->n_dev, nc, c->cnt, c->ccnt, c->ccur,
-                           (const int32_t*)c->coff, c->cwave, c->cmask, c->errcount);
+                           src->key, n, (const int64_t*)src->n_dev, nc, (unsigned long long*)c->cpair,
+                           c->ccur, (const int32_t*)c->coff, c->cwave, c->cmask, c->errcount);
     const int32_t nblocks = (nc + SCAN_TILE - 1) / SCAN_TILE;
     if (nblocks > 8191) return set_err(c, FP_EINVAL, "fp_bin: too many cells for the scan");
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt,
-                       c->ccnt, nc, c->blocksum);
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cpair,
+                       c->cpair + 1, 2, nc, c->blocksum);
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(SCAN_BLOCK), 0, s, c->blocksum, nblocks);
-    hipLaunchKernelGGL(scan_final_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cnt, c->ccnt,
-                       nc, c->blocksum, nblocks, offsets, c->coff);
+    hipLaunchKernelGGL(scan_final_kernel, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, c->cpair,
+                       c->cpair + 1, 2, nc, c->blocksum, nblocks, offsets, c->coff);
     if (slots > 0)
         hipLaunchKernelGGL(bin_wave_kernel<true>, dim3((unsigned)pgrid), dim3(BIN_BLOCK), 0, s,
-                           src->key, n, (const int64_t*)src->n_dev, nc, c->cnt, c->ccnt, c->ccur,
-                           (const int32_t*)c->coff, c->cwave, c->cmask, c->errcount);
+                           src->key, n, (const int64_t*)src->n_dev, nc, (unsigned long long*)c->cpair,
+                           c->ccur, (const int32_t*)c->coff, c->cwave, c->cmask, c->errcount);
     if (c->cfg.precision == FP_F32)
         gather_dispatch<float>(c, src, dst, offsets, perm, s);
     else

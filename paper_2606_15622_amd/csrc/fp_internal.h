@@ -28,6 +28,8 @@ struct fp_ctx {
     int32_t* ccnt = nullptr;     // [ncell+1] contribution records per destination cell
     int32_t* coff = nullptr;     // [ncell+1] contribution offsets
     int32_t* ccur = nullptr;     // [ncell+1] contribution cursors
+    int32_t* cpair = nullptr;    // [2 (ncell+1)] full sort: per cell the particle count and the
+                                 // contribution count, adjacent (one 64-bit atomic adds both)
     int32_t* cwave = nullptr;    // [capacity] contribution: source wave index
     uint64_t* cmask = nullptr;   // [capacity] contribution: lane mask
     int32_t* gidx = nullptr;     // [capacity] slot list for cells too large for LDS
