@@ -492,12 +492,16 @@ class AMRSimulation:
     def adapt(self, steps):
         self.ctx.amr_adapt(self.prm, self.acc, self.samp, self.a, steps)
 
-    def step(self, s, sample=False, closure=None):
+    def _adapt_due(self, s):
+        """The adaptation that falls on step s (every adapt_every steps from the first)."""
         if self.since is None:
             self.since = s
         elif self.adapt_every > 0 and s - self.since >= self.adapt_every:
             self.adapt(s - self.since)
             self.since = s
+
+    def _body(self, sample, closure):
+        """One step at the device step number, which it advances (no adaptation)."""
         self.ctx.bin(self.a, self.b, self.offs[1])
         self.offs.reverse()
         self.a, self.b = self.b, self.a
@@ -507,10 +511,14 @@ class AMRSimulation:
             self.ctx.closure_solve(self.mom, self.rec, self.status)
         else:
             closure(self.mom, self.rec, self.status)
-        self.step_ctr.fill_(s)
         self.ctx.step_dev(self.a, self.offs[0], self.mom, self.rec, self.step_ctr,
                           STEP_COLLIDE | STEP_MOVE)
-        self.ctx.inject_dev(self.a, self.pid_next, self.step_ctr)
+        self.ctx.inject_dev(self.a, self.pid_next, self.step_ctr, STEP_ADVANCE)
+
+    def step(self, s, sample=False, closure=None):
+        self._adapt_due(s)
+        self.step_ctr.fill_(s)
+        self._body(sample, closure)
 
     def run(self, step0, nsteps, n_skip=None):
         n_skip = self.w.get("n_skip", 0) if n_skip is None else n_skip
@@ -539,6 +547,67 @@ class AMRSimulation:
         out = self.a.numpy()
         keep = out["key"] < self.ncell
         return {k: v[keep] for k, v in out.items()}
+
+
+class GraphAMRSimulation(AMRSimulation):
+    """AMRSimulation whose steps between adaptations are HIP-graph replays (for callers that
+    capture their loop): two steps per graph (the particle buffers, their count words and the
+    offsets return to their places), the step number and the particle count advanced on the
+    device.  An adaptation changes the leaf count and with it the launch shapes, so it drops
+    the graphs; the next replay captures them again (once per adaptation interval).  Not
+    faster than eager steps here: 1.67 against 1.65 ms per step at 7.6e5 leaves."""
+
+    def __init__(self, *args, **kw):
+        super().__init__(*args, **kw)
+        self.graphs = {}
+
+    def adapt(self, steps):
+        super().adapt(steps)
+        self.graphs = {}
+
+    def _graph(self, sample):
+        if sample not in self.graphs:
+            g = torch.cuda.CUDAGraph()
+            torch.cuda.synchronize()
+            live = (self.step_ctr, self.samp, self.acc, self.pid_next, self.a.n_dev, self.b.n_dev)
+            saved = tuple(t.clone() for t in live)
+            with torch.cuda.graph(g):
+                for _ in range(2):
+                    self._body(sample, None)
+            torch.cuda.synchronize()
+            # capture executes nothing; restore anyway
+            for t, v in zip(live, saved):
+                t.copy_(v)
+            self.graphs[sample] = g
+        return self.graphs[sample]
+
+    def run_pairs(self, npairs, sample=False):
+        """Advance 2 * npairs steps by graph replays (from the device step number); no
+        adaptation falls inside them."""
+        g = self._graph(sample)
+        for _ in range(npairs):
+            g.replay()
+
+    def run(self, step0, nsteps, n_skip=None):
+        """The steps of AMRSimulation.run, the same adaptations at the same steps, by graph
+        replays between them (an odd step before an adaptation, or before sampling starts,
+        runs eagerly)."""
+        n_skip = self.w.get("n_skip", 0) if n_skip is None else n_skip
+        s, end = step0, step0 + nsteps
+        while s < end:
+            self._adapt_due(s)
+            nxt = end if self.adapt_every <= 0 else min(self.since + self.adapt_every, end)
+            if s < n_skip:
+                nxt = min(nxt, n_skip)
+            sample = s >= n_skip
+            npairs = (nxt - s) // 2
+            if npairs:
+                self.step_ctr.fill_(s)
+                self.run_pairs(npairs, sample)
+                s += 2 * npairs
+            if s < nxt:
+                self.step(s, sample=sample)
+                s += 1
 
 
 class Network:

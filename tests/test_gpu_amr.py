@@ -196,6 +196,33 @@ def test_open_run_with_tree_matches_oracle(L, every):
     np.testing.assert_allclose(sim.samp[:nl].cpu().numpy(), osamp, rtol=1e-9, atol=1e-9 * np.abs(osamp).max())
 
 
+def test_graph_replay_matches_eager_bitwise():
+    """GraphAMRSimulation: HIP-graph replays between adaptations (graphs dropped and
+    captured again after each) give the eager loop's particles, both sets of sums, tree and
+    ids bit for bit; odd steps before an adaptation and before sampling starts run eagerly."""
+    F = fp()
+    w = small("f32", mach=10.0)
+    s = I.freestream_state(w, seed=5)
+    prm = dict(tau_grad=0.10, tau_coarse=0.05, shock_factor=1.2, p_inf=p_inf(w), n_max=1e9,
+               n_grad=40.0, eps=1e-300, age_min=4)
+    eager = F.AMRSimulation(w, s, 2, prm, 4)
+    graph = F.GraphAMRSimulation(w, s, 2, prm, 4)
+    eager.run(0, 13, n_skip=3)
+    graph.run(0, 13, n_skip=3)
+    torch.cuda.synchronize()
+    assert graph.ncell == eager.ncell
+    assert eager.ncell > (w["nx"] >> 2) * (w["ny"] >> 2)    # the tree was refined
+    ga, ea = graph.live(), eager.live()
+    for k in ea:
+        np.testing.assert_array_equal(ga[k], ea[k], err_msg=k)
+    assert torch.equal(graph.samp, eager.samp)
+    assert torch.equal(graph.acc, eager.acc)
+    assert torch.equal(graph.pid_next, eager.pid_next)
+    assert int(graph.step_ctr.cpu()[0]) == int(eager.step_ctr.cpu()[0]) == 13
+    for gt, et in zip(graph.tree(), eager.tree()):
+        np.testing.assert_array_equal(gt, et)
+
+
 def test_rebin_is_refused_with_a_tree_before_a_sort_by_its_leaves():
     F = fp()
     w = small("f32")
