@@ -168,15 +168,16 @@ def test_moments_parity(prec):
     assert np.all(np.abs(g - o) <= 1e-10 * scale)
 
 
-@pytest.mark.parametrize("prec,counts", [("f32", MIX_COUNTS), ("f64", MIX_COUNTS),
-                                         ("f32", "leaves"), ("f64", "leaves")])
+@pytest.mark.parametrize("prec,counts", [("f32", MIX_COUNTS), ("f64", MIX_COUNTS), ("f32", 10),
+                                         ("f32", 24), ("f64", 24), ("f32", 60), ("f32", 100)])
 def test_moments_sample_is_moments_then_sample(prec, counts):
     """fp_moments_sample: the records of fp_moments and the sums of fp_sample on each of the
-    two sets, bit for bit, also without the second set; the mixed counts take 32-lane
-    groups, cells of about 24 particles (the quadtree's leaves) 8-lane groups."""
+    two sets, bit for bit, also without the second set.  Every group width of the moments
+    kernel: the mixed counts (a few hundred particles per cell on average) take 64 lanes,
+    Poisson cells of mean 10, 24 (the quadtree's leaves), 60 and 100 take 4, 8, 16 and 32."""
     F = fp()
-    if counts == "leaves":
-        counts = list(np.random.default_rng(5).poisson(24, 3000))
+    if not isinstance(counts, list):
+        counts = list(np.random.default_rng(5).poisson(counts, 3000))
     nc = len(counts)
     w = I.cavity(ncell=4, precision=prec)
     w["nx"], w["ny"] = nc, 1
