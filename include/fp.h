@@ -160,7 +160,11 @@ int fp_bin(fp_ctx* ctx, const fp_particles* src, fp_particles* dst, int32_t* off
  * particles after them (e.g. injected ones) are in no particular order.  A particle
  * whose new cell is one of the 3 x 3 cells around its previous one is placed from
  * per-cell direction counts, without global atomics; the others take a general path
- * that is slower per particle.  src_offsets and offsets must not alias (keep two
+ * that is slower per particle: a destination ranks its arrivals from outside its 3 x 3
+ * neighbourhood by comparing them with one another, a cost that grows with the square of
+ * their number, so the call is meant for steps after which almost every particle is still
+ * within one cell of its old one (the step length of the method ensures it; use fp_bin
+ * after a step that scatters the particles).  src_offsets and offsets must not alias (keep two
  * offsets arrays and alternate them); src_offsets must be non-decreasing with
  * src_offsets[0] >= 0 and src_offsets[ncell] <= src->n.  mom (optional, may be NULL)
  * receives the moment records of the sorted cells, as fp_moments of dst would compute
