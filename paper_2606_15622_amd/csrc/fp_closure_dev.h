@@ -87,14 +87,18 @@ __device__ __forceinline__ bool lu_solve(CellSystem& s, double tol, double y[9])
             piv = gt ? r : piv;
         }
         ok = ok && (best >= tol);
+        // the row swap is a predicated select on every candidate row; it is skipped when no
+        // lane of the wave pivots off the diagonal (the common case near equilibrium)
+        if (__any(piv != k)) {
 #pragma unroll
-        for (int r = k + 1; r < 9; ++r) {
-            const bool sw = (piv == r);
+            for (int r = k + 1; r < 9; ++r) {
+                const bool sw = (piv == r);
 #pragma unroll
-            for (int cidx = k; cidx < 10; ++cidx) {
-                const double t = a[k][cidx];
-                a[k][cidx] = sw ? a[r][cidx] : t;
-                a[r][cidx] = sw ? t : a[r][cidx];
+                for (int cidx = k; cidx < 10; ++cidx) {
+                    const double t = a[k][cidx];
+                    a[k][cidx] = sw ? a[r][cidx] : t;
+                    a[r][cidx] = sw ? t : a[r][cidx];
+                }
             }
         }
         const double inv = 1.0 / a[k][k];
